@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Benchmark of the plane-wave H|psi> / Davidson path on one MI355X.
+
+Workload (default): the 64-atom diamond-structure cell (a = 20.52 bohr, 30 Ry,
+72^3 grid, 16 k-points of a shifted 4x4x1 mesh, 160 bands, 256 projectors),
+synthetic seeded inputs already resident in HBM.  One step = one qm_apply_h
+over every k-point and band (scatter, pruned inverse FFT, V(r), forward FFT,
+gather + kinetic, projector GEMMs).  The JSON line reports bands/s, the
+roofline of the dominant kernel (HIP events around each stage) and the FP64
+CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
+PREC_CODE = {"fp64": 0, "fp32": 1, "mixed": 2}
+PREC_DTYPE = {"fp64": "f64", "fp32": "f32", "mixed": "f32+bf16"}
+
+
+def _nsticks(miller, grid):
+    i = np.mod(miller[:, :2], np.asarray(grid[:2]))
+    return len(np.unique(i[:, 0] * grid[1] + i[:, 1]))
+
+
+def build_inputs(w):
+    import torch
+    miller = np.concatenate(w.miller).astype(np.int32)
+    beta = torch.empty(int(w.nproj * w.npw.sum()), dtype=torch.complex128, device="cuda")
+    off = 0
+    for ik in range(w.nk):
+        b = torch.from_numpy(w.beta(ik).reshape(-1))
+        beta[off:off + b.numel()].copy_(b)
+        off += b.numel()
+    vloc = torch.from_numpy(w.vloc_r()).cuda()
+    psi = torch.empty(int(w.nbnd * w.npw.sum()), dtype=torch.complex128, device="cuda")
+    off = 0
+    for ik in range(w.nk):
+        p = torch.from_numpy(w.psi(ik).reshape(-1))
+        psi[off:off + p.numel()].copy_(p)
+        off += p.numel()
+    return miller, beta, vloc, psi
+
+
+def algorithmic_model(w, prec):
+    """Per-band minimal HBM bytes of each local stage and flops of the projector GEMMs."""
+    csz = 16 if prec == "fp64" else 8
+    out = {}
+    nst = [_nsticks(m, w.grid) for m in w.miller]
+    n3 = w.grid[2]
+    tot_bands = w.nk * w.nbnd
+    sb = sum(w.nbnd * s * n3 * csz for s in nst)          # stick buffer, all bands
+    psi_b = sum(w.nbnd * int(n) * 16 for n in w.npw)      # c128 band block
+    out["zinv"] = ("hbm", psi_b + sb)
+    out["xy"] = ("hbm", 2 * sb)
+    out["zfwd"] = ("hbm", sb + 2 * psi_b)
+    fl = sum(8.0 * w.nproj * w.nbnd * int(n) for n in w.npw)
+    out["proj_gemm"] = ("mfma", fl)
+    out["expand_gemm"] = ("mfma", fl)
+    return out, tot_bands, nst
+
+
+def cpu_baseline(w, nb_sample):
+    """The FP64 oracle on one k-point and nb_sample bands, single thread."""
+    from threadpoolctl import threadpool_limits
+    from oracle import hamiltonian as ham
+    ik = 0
+    m = w.miller[ik]
+    beta = w.beta(ik)
+    v = w.vloc_r()
+    d = w.dmat()
+    psi = w.psi(ik)[:nb_sample]
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        ham.apply_h_ref(w.cell, w.grid, w.k_cryst[ik], m, v, beta, d, psi)
+        dt = time.perf_counter() - t0
+    return {"value": nb_sample / dt, "unit": "bands/s", "cores": 1, "kind": "oracle",
+            "sample": f"apply_h_ref (numpy FFT + BLAS, float64) on k-point 0 of the {w.name} "
+                      f"workload, {nb_sample} bands, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c3")
+    ap.add_argument("--prec", default="fp64", choices=list(PREC_CODE))
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--cpu-sample-bands", type=int, default=160)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(k-point and G-sphere sharding are described in the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workload
+    import paper_2308_07277_amd as qm
+
+    w = workload.make_workload(args.workload)
+    miller, beta, vloc, psi = build_inputs(w)
+    plan = qm.qm_hpsi_plan_create(w.cell, w.grid, w.k_cart, w.npw, miller, w.nbnd, w.nproj,
+                                  vloc, beta, w.dmat(), PREC_CODE[args.prec])
+    del beta, vloc
+    hpsi = torch.empty_like(psi)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        qm.qm_apply_h(plan, -1, psi, hpsi, w.nbnd)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        qm.qm_apply_h(plan, -1, psi, hpsi, w.nbnd)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms = 1000.0 * dt / args.steps
+    bands = w.nk * w.nbnd
+    value = bands / (ms / 1000.0)
+
+    # per-stage durations (HIP events on the launch stream), averaged
+    stages = {}
+    nrep = 5
+    for _ in range(nrep):
+        t = qm.qm_apply_h_timed(plan, -1, psi, hpsi, w.nbnd)
+        for k, v in t.items():
+            stages[k] = stages.get(k, 0.0) + v / nrep
+    model, _, nst = algorithmic_model(w, args.prec)
+    dom = max(stages, key=lambda k: stages[k])
+    bound, amount = model.get(dom, ("hbm", 0.0))
+    sec = stages[dom] / 1000.0
+    if bound == "hbm":
+        achieved = amount / sec / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom}
+    else:
+        dt_ = {"fp64": "f64", "fp32": "f32", "mixed": "bf16"}[args.prec]
+        achieved = amount / sec / 1e12
+        roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[dt_], "unit": "TFLOP/s",
+                "frac": achieved / PEAK_TFLOPS[dt_], "traffic": None, "kernel": dom}
+    stage_rates = {}
+    for k, (b, a) in model.items():
+        if stages.get(k, 0) > 0:
+            s_ = stages[k] / 1000.0
+            stage_rates[k] = ({"GB/s": a / s_ / 1e9} if b == "hbm" else {"TFLOP/s": a / s_ / 1e12})
+    out = {
+        "metric": "Hpsi bands/s (FP64 vs mixed) + Davidson time to 1e-8 Ha residual, 64-atom",
+        "value": value, "unit": "bands/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": PREC_DTYPE[args.prec], "data": "synthetic",
+        "config": {"workload": f"{w.name}: {len(w.atoms)}-atom diamond-structure cell, "
+                               f"{w.ecut_ry:g} Ry, {w.grid[0]}^3 grid, {w.nk} k-points, "
+                               f"{w.nbnd} bands, {w.nproj} projectors, all k and bands per step",
+                   "npw": [int(x) for x in w.npw], "nstick": nst, "prec": args.prec},
+        "stages_ms": stages, "stage_rates": stage_rates, "roofline": roof,
+    }
+    if args.cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_bands)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * qm_hpsi.h - C ABI of the MI355X (gfx950) plane-wave Kohn-Sham H|psi> and
+ * block-Davidson library.
+ *
+ * Physics (Hartree atomic units; bohr, Ha).  At a k-point the Hamiltonian acts
+ * on plane-wave coefficients c(G) of the G-sphere S_k as
+ *
+ *   (H c)(G) = 1/2 |k+G|^2 c(G)                                  kinetic, Sec. 4.3
+ *            + sum_{G'} V(G-G') c(G')                             local, eq. KSHamMat
+ *            + sum_ij beta_i(k+G) D_ij sum_{G'} conj(beta_j(k+G')) c(G')
+ *                                                                 Kleinman-Bylander, Sec. 2.3
+ *
+ * with V(dG) = (1/N_r) sum_r V(r) e^{-i dG.r} the grid Fourier coefficient of
+ * the local potential sampled on the FFT grid (dG modulo the grid).  The
+ * library evaluates the local term as the paper's Sec. 4.3 describes (inverse
+ * FFT of the sphere, multiply by V(r), forward FFT, keep the sphere), with
+ * the stick-pruned 3-D transform of Sec. 4.3 ("Optimizing FFT operations for
+ * G-Space"), and the non-local term as two complex GEMMs.  The eigensolver is
+ * a block Davidson on H(k) (Sec. 5, 'dft' module: Davidson with H as a
+ * Hermitian black box applied to trial blocks).
+ *
+ * Conventions shared by every entry point
+ *  - Status codes only: no exception or abort crosses this ABI.  After a
+ *    failure qm_last_error() returns a message; outputs are unspecified but
+ *    the plan stays usable.
+ *  - "device" pointers are HIP device memory of the current device; "host"
+ *    pointers are ordinary memory.  The caller owns every buffer it passes.
+ *  - stream is a hipStream_t passed as void*; NULL means the null stream.
+ *    qm_apply_h is asynchronous on it; the Davidson calls synchronise it once
+ *    per iteration to read the convergence numbers.
+ *  - Complex numbers are interleaved (re, im) float64 pairs ("c128").
+ *  - Band blocks are [nk][nbnd][npw_k], k-blocks concatenated in k order,
+ *    G in the caller's order given by the Miller list.
+ *  - A plan is not thread-safe; use one plan per stream.
+ */
+#ifndef QM_HPSI_H
+#define QM_HPSI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  QM_OK = 0,
+  QM_E_ARG = 1,            /* invalid argument (shape, range, duplicate G, non-Hermitian D ...) */
+  QM_E_SHAPE = 2,          /* grid or size not supported by the kernels */
+  QM_E_HIP = 3,            /* a HIP runtime call failed */
+  QM_E_NOMEM = 4,          /* device allocation failed */
+  QM_E_NOT_SPD = 5,        /* Cholesky of a Gram matrix failed (linearly dependent block) */
+  QM_E_NOT_CONVERGED = 6,  /* Davidson reached max_iter; eig/resnorm/stats are still filled */
+  QM_E_NAN = 7,            /* NaN or Inf met in a residual norm or Rayleigh quotient */
+  QM_E_STATE = 8           /* call not valid in the plan's current state */
+} qm_status;
+
+typedef enum {
+  QM_PREC_FP64 = 0,   /* FFT, pointwise and projector GEMMs in float64 */
+  QM_PREC_FP32 = 1,   /* FFT and pointwise in float32, projector GEMMs float32 (MFMA) */
+  QM_PREC_MIXED = 2   /* FFT float32, projector GEMMs bfloat16 inputs with float32 accumulation */
+} qm_prec;
+
+typedef enum {
+  QM_PRECOND_TETER = 0,  /* Teter-Payne-Allan K(x), x = (1/2|k+G|^2)/<X_n|T|X_n> */
+  QM_PRECOND_MLP = 1     /* learned per-(G, band) gain network, Teter as fallback */
+} qm_precond;
+
+typedef struct qm_hpsi_plan qm_hpsi_plan;
+
+/* k-point set and G-spheres (host memory, read during plan creation only).
+ *  k_cart [nk][3]     k in cartesian bohr^-1.
+ *  npw    [nk]        sphere size per k (>= 1).
+ *  miller [sum npw][3] integer triples m, G = m1 b1 + m2 b2 + m3 b3, k blocks
+ *                     concatenated; any order, no duplicates, 2|m_i| < N_i. */
+typedef struct {
+  int32_t nk;
+  const double *k_cart;
+  const int32_t *npw;
+  const int32_t *miller;
+} qm_kset;
+
+/* Davidson options (host).  Zero-initialise and set what you need; zero
+ * fields take the defaults in brackets. */
+typedef struct {
+  double tol;             /* convergence: max_n ||H x_n - theta_n x_n||_2 <= tol, Ha [1e-8] */
+  int32_t max_iter;       /* iteration limit [200] */
+  int32_t max_basis;      /* basis columns per k before a restart [4*nbnd] */
+  int32_t precond;        /* qm_precond [QM_PRECOND_TETER] */
+  int32_t restart;        /* qm_davidson_step: 1 = discard state and start from psi [0] */
+  double switch_resid;    /* precision ladder: while max residual > switch_resid the
+                             corrections are applied with the plan's reduced-precision
+                             H; below it (and for every reported residual) float64.
+                             0 = float64 throughout [0] */
+  const void *mlp_weights;/* device float32 weights of the learned preconditioner
+                             (layout in qm_mlp_*), required for QM_PRECOND_MLP */
+} qm_dav_opts;
+
+/* Davidson statistics (host), filled by qm_davidson_solve. */
+typedef struct {
+  int32_t iterations;     /* Davidson iterations of the slowest k */
+  int32_t converged;      /* 1 if every requested k converged */
+  int64_t n_hpsi_bands;   /* band-applications of H (all precisions) */
+  int64_t n_hpsi_bands_lowp; /* of which in reduced precision */
+  double max_resnorm;     /* final max residual, Ha */
+  double t_hpsi_ms;       /* device time in H application */
+  double t_subspace_ms;   /* subspace GEMMs, orthonormalisation and Ritz update */
+  double t_eig_ms;        /* projected eigenproblem */
+  double t_total_ms;      /* wall time of the call */
+} qm_dav_stats;
+
+/* ------------------------------------------------------------------ plan */
+
+/* Create an H(k) plan (Sec. 2.2 basis, Sec. 2.3 projectors, Sec. 4.3 grid).
+ *  cell     host [9]  rows a_1, a_2, a_3 (bohr).
+ *  grid     host [3]  FFT grid N1, N2, N3.  Supported: N1 == N2, and N1, N3 in
+ *                     {12,16,18,20,24,27,28,30,32,36,40,45,48,54,56,60,64,72,80,
+ *                      81,90,96,100,108,120,128,144}; else QM_E_SHAPE.
+ *  ks       k-points and spheres (see qm_kset).
+ *  nbnd_max largest band count any later call will pass (sizes the workspace).
+ *  nproj    number of projectors (>= 0).
+ *  vloc_r   device float64 [N1][N2][N3], C order; grid point j at sum_i (j_i/N_i) a_i; Ha.
+ *  beta     device c128 [nk][nproj][npw_k], <k+G|beta_i> in the caller's G order.
+ *  dmat     host float64 [nproj][nproj], real symmetric, Ha (D_ij of Sec. 2.3).
+ *  prec     qm_prec used by qm_apply_h.
+ *  stream   hipStream_t for the set-up copies.
+ *  out      receives the plan.
+ * The plan copies V, beta and D (in its working precisions) and owns its
+ * workspace, so inputs may be freed after the call returns. */
+qm_status qm_hpsi_plan_create(const double cell[9], const int32_t grid[3], const qm_kset *ks,
+                              int32_t nbnd_max, int32_t nproj, const double *vloc_r,
+                              const void *beta, const double *dmat, qm_prec prec, void *stream,
+                              qm_hpsi_plan **out);
+
+void qm_hpsi_plan_destroy(qm_hpsi_plan *plan);
+
+/* Message of the last failure on this plan (or of the last failed create
+ * when plan is NULL); "" if none.  Valid until the next call on the plan. */
+const char *qm_last_error(const qm_hpsi_plan *plan);
+
+/* Change the precision qm_apply_h uses (reconverts beta; synchronous). */
+qm_status qm_hpsi_plan_set_precision(qm_hpsi_plan *plan, qm_prec prec, void *stream);
+
+/* ------------------------------------------------------------------ H|psi> */
+
+/* hpsi = H(k) psi for a block of bands (eq. KSHamMat + KB term).
+ *  k      k index, or -1 for every k of the plan in one batched launch sequence.
+ *  psi    device c128, [nbnd][npw_k] for one k, [nk][nbnd][npw_k] for k = -1.
+ *  hpsi   device c128, same layout; must not alias psi.
+ *  nbnd   1 <= nbnd <= nbnd_max.
+ * Precision per qm_hpsi_plan_create/set_precision; psi and hpsi are c128
+ * whatever the precision. */
+qm_status qm_apply_h(qm_hpsi_plan *plan, int32_t k, const void *psi, void *hpsi, int32_t nbnd,
+                     void *stream);
+
+/* qm_apply_h with HIP events recorded on stream between its kernels; synchronises
+ * the stream and writes the duration of each stage in milliseconds to times_ms
+ * (host float64 [QM_NSTAGES]): 0 scatter + z inverse, 1 xy planes (y/x transforms
+ * and V), 2 z forward + gather + kinetic, 3 projection GEMM, 4 split-K reduction,
+ * 5 D application, 6 expansion GEMM.  Stages that do not run report 0. */
+#define QM_NSTAGES 7
+qm_status qm_apply_h_timed(qm_hpsi_plan *plan, int32_t k, const void *psi, void *hpsi,
+                           int32_t nbnd, double *times_ms, void *stream);
+
+/* ------------------------------------------------------------------ Davidson */
+
+/* One Davidson iteration on k (or all k with k = -1), state kept in the plan.
+ * First call (or opts->restart = 1): orthonormalise psi, apply H, Rayleigh-Ritz.
+ * Later calls: corrections for unconverged bands, restart if the basis is full,
+ * orthonormalise, apply H, Rayleigh-Ritz.  Every call writes the current Ritz
+ * vectors to psi (device c128, layout as qm_apply_h), Ritz values to eig and
+ * residual norms to resnorm (host float64 [nk_sel][nbnd], ascending per k),
+ * and the number of unconverged (k, band) pairs to *n_unconverged (host). */
+qm_status qm_davidson_step(qm_hpsi_plan *plan, int32_t k, void *psi, double *eig,
+                           double *resnorm, int32_t nbnd, const qm_dav_opts *opts,
+                           int32_t *n_unconverged, void *stream);
+
+/* Iterate qm_davidson_step from the start block psi until every residual norm
+ * is <= opts->tol or max_iter is reached (then QM_E_NOT_CONVERGED with all
+ * outputs filled).  psi receives the Ritz vectors; stats may be NULL. */
+qm_status qm_davidson_solve(qm_hpsi_plan *plan, int32_t k, void *psi, double *eig,
+                            double *resnorm, int32_t nbnd, const qm_dav_opts *opts,
+                            qm_dav_stats *stats, void *stream);
+
+/* ------------------------------------------------------------------ learned preconditioner */
+
+/* Per-(G, band) network t(G) = g(G) r(G), g complex, from five features
+ * f = [x, log x, theta_n - T_n, |r(G)|/||r_n|| * sqrt(npw), 1/2|k+G|^2]
+ * with x = (1/2|k+G|^2)/T_n and T_n the band kinetic energy; layer 1: 5 -> 128
+ * with SiLU, layer 2: 128 -> 2 (re, im of g).  Weights are float32 in one
+ * device buffer: W1[128][5], b1[128], W2[2][128], b2[2]  (QM_MLP_NPARAM floats). */
+#define QM_MLP_NIN 5
+#define QM_MLP_NHID 128
+#define QM_MLP_NPARAM (128 * 5 + 128 + 2 * 128 + 2)
+
+/* Forward pass over n rows of features (device float32 [n][5]) -> gains (device float32 [n][2]). */
+qm_status qm_mlp_forward(const float *weights, const float *feat, float *gain, int64_t n,
+                         void *stream);
+
+/* Loss and gradient of a weighted least-squares fit of the gain to targets:
+ * L = sum_r w_r |g_r - y_r|^2 / sum_r w_r over n rows (feat [n][5], target [n][2],
+ * weight [n]); writes grad (device float32 [QM_MLP_NPARAM]) and *loss (host). */
+qm_status qm_mlp_loss_grad(const float *weights, const float *feat, const float *target,
+                           const float *weight, int64_t n, float *grad, double *loss,
+                           void *stream);
+
+/* One Adam step (lr, beta1, beta2, eps; t = 1-based step) on weights with
+ * moment buffers m, v (device float32 [QM_MLP_NPARAM]). */
+qm_status qm_mlp_adam(float *weights, const float *grad, float *m, float *v, int32_t t,
+                      float lr, float beta1, float beta2, float eps, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QM_HPSI_H */

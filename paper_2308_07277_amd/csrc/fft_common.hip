@@ -1,0 +1,75 @@
+// Plan-side helpers of the local part: supported lengths, V(r) re-layout.
+#include "cplx.h"
+#include "qm_internal.h"
+
+namespace qm {
+
+void launch_local_f64(qm_hpsi_plan*, int, int, int, const void*, void*, hipStream_t, StageEvents*);
+void launch_local_f32(qm_hpsi_plan*, int, int, int, const void*, void*, hipStream_t, StageEvents*);
+
+bool fft_len_supported(int n) {
+  switch (n) {
+#define QM_CASE(x) case x:
+    QM_FOR_EACH_FFT_LEN(QM_CASE)
+#undef QM_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+int fft_split_r1(int n) {
+  switch (n) {
+#define QM_CASE(x) case x: return Split<x>::R1;
+    QM_FOR_EACH_FFT_LEN(QM_CASE)
+#undef QM_CASE
+    default:
+      return 0;
+  }
+}
+int fft_split_r2(int n) {
+  switch (n) {
+#define QM_CASE(x) case x: return Split<x>::R2;
+    QM_FOR_EACH_FFT_LEN(QM_CASE)
+#undef QM_CASE
+    default:
+      return 0;
+  }
+}
+
+void launch_hpsi_local(qm_hpsi_plan* p, int k0, int k1, int nbnd, const void* psi, void* hpsi,
+                       hipStream_t s, bool fp32, StageEvents* ev) {
+  if (fp32)
+    launch_local_f32(p, k0, k1, nbnd, psi, hpsi, s, ev);
+  else
+    launch_local_f64(p, k0, k1, nbnd, psi, hpsi, s, ev);
+}
+
+// V(r) [i1][i2][i3] (float64, C order) -> plan layout [slot][i1][i2] scaled by 1/N_r, where
+// slot p = k1 + R1 k2 holds plane i3 = k2 + R2 k1 (order left by the inverse z-transform).
+__global__ void k_vplan(const double* __restrict__ v, double* __restrict__ v64, float* __restrict__ v32,
+                        int N1, int N2, int N3, int R1, int R2, double scale) {
+  const int64_t n = int64_t(N1) * N2 * N3;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int i2 = int(t % N2);
+    const int64_t r = t / N2;
+    const int i1 = int(r % N1);
+    const int p = int(r / N1);
+    const int k1 = p % R1, k2 = p / R1;
+    const int i3 = k2 + R2 * k1;
+    const double val = v[(int64_t(i1) * N2 + i2) * N3 + i3] * scale;
+    v64[t] = val;
+    v32[t] = float(val);
+  }
+}
+
+void launch_vplan(qm_hpsi_plan* p, const double* vloc_r, hipStream_t s) {
+  const int64_t n = int64_t(p->N1) * p->N2 * p->N3;
+  const int blocks = int(std::min<int64_t>((n + 255) / 256, 65536));
+  hipLaunchKernelGGL(k_vplan, dim3(blocks), dim3(256), 0, s, vloc_r,
+                     reinterpret_cast<double*>(p->vplan64), reinterpret_cast<float*>(p->vplan32),
+                     p->N1, p->N2, p->N3, fft_split_r1(p->N3), fft_split_r2(p->N3), 1.0 / double(n));
+  QM_HIP(hipGetLastError());
+}
+
+}  // namespace qm

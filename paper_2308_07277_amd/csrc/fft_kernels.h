@@ -1,0 +1,334 @@
+// Stick-pruned batched 3-D FFT with the local potential fused in (gfx950).
+//
+// Local part of H|psi> for every (k, band) of a launch (Sec. 4.3: inverse
+// FFT of the sphere, multiply by V(r), forward FFT, keep the sphere; with the
+// stick pruning of "Optimizing FFT operations for G-Space"):
+//
+//   k_zinv  scatter the sphere coefficients of a tile of z-sticks into LDS
+//           (only sticks holding a G exist), inverse z-transform, write the
+//           tile to the stick buffer, plane-slot major ([slot][stick]).
+//   k_xy    one (k, band, z-plane) per workgroup, the plane staged in LDS
+//           restricted to the active x-columns: inverse y-transform on the
+//           active columns, then per y-row the inverse x-transform, the
+//           multiplication by V(r)/N_r and the forward x-transform chained in
+//           registers (only active columns written back), forward
+//           y-transform, write the plane back in place.
+//   k_zfwd  forward z-transform of a stick tile, then gather the sphere and
+//           add the kinetic term 1/2|k+G|^2 c(G) (computed in float64).
+//
+// Each 1-D transform of length N = R1*R2 is done in two in-place passes
+// (R2-point then R1-point register DFTs, twiddles between) by a group of
+// threads.  The inverse leaves its output in R1 x R2 transposed order and the
+// forward transform uses the swapped factorisation, which consumes exactly
+// that order and produces natural order, so no transposition pass exists
+// anywhere; V(r) is stored in the plan in the same permuted plane order.
+#pragma once
+#include "cplx.h"
+#include "qm_internal.h"
+
+namespace qm {
+
+struct LocalArgs {
+  const KInfo* kinfo;
+  int32_t k0, k1, nbnd, N3;
+  const double2* psi;       // c128, block of k0
+  double2* hpsi;            // c128
+  void* sbuf;               // cplx<R>
+  const int32_t* ent_g;
+  const int32_t* ent_sz;
+  const int32_t* tile_ptr;
+  const int32_t* stick_pos;
+  const int32_t* col_of_i1;
+  const double* kin;
+  const void* vplan;        // R [slot][i1][i2]
+  const double2* tw_z;      // exp(+2 pi i m / N3), m < N3
+  const double2* tw_x;      // exp(+2 pi i m / N1)
+  int64_t g_off0;           // g_off of k0
+  int32_t ts;               // sticks per tile
+  int32_t nax_stride;       // row stride of the xy-plane buffer (elements)
+};
+
+__device__ __forceinline__ int locate_tile_block(const KInfo* ki, int k0, int k1, int nbnd, int& bid) {
+  int k = k0;
+  for (; k < k1 - 1; ++k) {
+    int nb = nbnd * ki[k].ntile;
+    if (bid < nb) break;
+    bid -= nb;
+  }
+  return k;
+}
+
+// ------------------------------------------------------------------ z inverse + scatter
+template <typename R, int N3, int TS>
+__global__ void __launch_bounds__(TS * Split<N3>::R2) k_zinv(LocalArgs a) {
+  constexpr int R1 = Split<N3>::R1, R2 = Split<N3>::R2, NT = TS * R2;
+  __shared__ cplx<R> tile[N3 * TS];
+  __shared__ cplx<R> tw[N3];
+  const int tid = threadIdx.x;
+  int bid = blockIdx.x;
+  const int k = locate_tile_block(a.kinfo, a.k0, a.k1, a.nbnd, bid);
+  const KInfo ki = a.kinfo[k];
+  const int band = bid / ki.ntile, t = bid - band * ki.ntile;
+  const int s0 = t * TS;
+  const int cnt = min(TS, ki.nstick - s0);
+  for (int i = tid; i < N3; i += NT) {
+    double2 w = a.tw_z[i];
+    tw[i] = {R(w.x), R(w.y)};
+  }
+  for (int i = tid; i < N3 * TS; i += NT) tile[i] = {R(0), R(0)};
+  __syncthreads();
+  const int32_t* tp = a.tile_ptr + ki.tile_off;
+  const int e0 = tp[t], e1 = tp[t + 1];
+  const double2* psi_b = a.psi + int64_t(a.nbnd) * (ki.g_off - a.g_off0) + int64_t(band) * ki.npw;
+  const int32_t* eg = a.ent_g + ki.g_off;
+  const int32_t* esz = a.ent_sz + ki.g_off;
+  for (int e = e0 + tid; e < e1; e += NT) {
+    const int sz = esz[e];
+    const int s = sz / N3, z = sz - s * N3;
+    const double2 v = psi_b[eg[e]];
+    tile[z * TS + (s - s0)] = {R(v.x), R(v.y)};
+  }
+  __syncthreads();
+  const int sl = tid % TS, j = tid / TS;
+  if (j < R1) {
+    cplx<R> x[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) x[n2] = tile[(j + R1 * n2) * TS + sl];
+    Dft<R2, +1, R>::run(x);
+#pragma unroll
+    for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tw[(j * k2) % N3]);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) tile[(j + R1 * k2) * TS + sl] = x[k2];
+  }
+  __syncthreads();
+  if (sl < cnt) {
+    cplx<R> y[R1];
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) y[n1] = tile[(n1 + R1 * j) * TS + sl];
+    Dft<R1, +1, R>::run(y);
+    cplx<R>* out = reinterpret_cast<cplx<R>*>(a.sbuf) + ki.sbuf_off +
+                   int64_t(band) * N3 * ki.nstick + s0 + sl;
+#pragma unroll
+    for (int k1 = 0; k1 < R1; ++k1) out[int64_t(k1 + R1 * j) * ki.nstick] = y[k1];
+  }
+}
+
+// ------------------------------------------------------------------ xy plane
+template <typename R, int NX>
+__global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
+  constexpr int R1 = Split<NX>::R1, R2 = Split<NX>::R2;
+  constexpr int RG = 256 / R2;  // rows per x-pass group
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int ns = a.nax_stride;
+  cplx<R>* L = reinterpret_cast<cplx<R>*>(smem_raw);  // [NX positions][ns]
+  cplx<R>* X = L + NX * ns;                              // [NX positions][RG]
+  cplx<R>* tw = X + NX * RG;                             // [NX]
+  int* col = reinterpret_cast<int*>(tw + NX);            // [NX]
+  const int tid = threadIdx.x;
+  const int N3 = a.N3;
+  // (k, band) pair and z-slot; each XCD keeps a fixed eighth of the slots when N3 % 8 == 0
+  int bid = blockIdx.x, kb, p;
+  if ((N3 & 7) == 0) {
+    const int xcd = bid & 7, jj = bid >> 3, per = N3 >> 3;
+    kb = jj / per;
+    p = xcd * per + (jj - kb * per);
+  } else {
+    kb = bid / N3;
+    p = bid - kb * N3;
+  }
+  const int k = a.k0 + kb / a.nbnd, band = kb - (kb / a.nbnd) * a.nbnd;
+  const KInfo ki = a.kinfo[k];
+  const int nax = ki.nax;
+  for (int i = tid; i < NX; i += 256) {
+    double2 w = a.tw_x[i];
+    tw[i] = {R(w.x), R(w.y)};
+    col[i] = a.col_of_i1[int64_t(k) * NX + i];
+  }
+  for (int i = tid; i < NX * ns; i += 256) L[i] = {R(0), R(0)};
+  __syncthreads();
+  cplx<R>* plane = reinterpret_cast<cplx<R>*>(a.sbuf) + ki.sbuf_off +
+                   (int64_t(band) * N3 + p) * ki.nstick;
+  const int32_t* spos = a.stick_pos + ki.stick_off;
+  for (int s = tid; s < ki.nstick; s += 256) {
+    const int ps = spos[s];
+    L[(ps & 0xffff) * ns + (ps >> 16)] = plane[s];
+  }
+  __syncthreads();
+  // ---- inverse y on active columns: pass 1 (R2-point, stride R1)
+  for (int w = tid; w < nax * R1; w += 256) {
+    const int ia = w % nax, n1 = w / nax;
+    cplx<R> x[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) x[n2] = L[(n1 + R1 * n2) * ns + ia];
+    Dft<R2, +1, R>::run(x);
+#pragma unroll
+    for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tw[(n1 * k2) % NX]);
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2) L[(n1 + R1 * k2) * ns + ia] = x[k2];
+  }
+  __syncthreads();
+  // pass 2 (R1-point on contiguous runs); output X[k2 + R2 k1] at position k1 + R1 k2
+  for (int w = tid; w < nax * R2; w += 256) {
+    const int ia = w % nax, k2 = w / nax;
+    cplx<R> y[R1];
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) y[n1] = L[(n1 + R1 * k2) * ns + ia];
+    Dft<R1, +1, R>::run(y);
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) L[(n1 + R1 * k2) * ns + ia] = y[n1];
+  }
+  __syncthreads();
+  // ---- x rows: inverse x, * V / N_r, forward x; active columns only written back
+  const R* V = reinterpret_cast<const R*>(a.vplan) + int64_t(p) * NX * NX;  // [i1][i2]
+  const int r = tid % RG, q = tid / RG;
+  for (int r0 = 0; r0 < NX; r0 += RG) {
+    const int i2 = r0 + r;
+    const bool act = (q < R2) && (i2 < NX);
+    const int lrow = act ? (i2 / R2) + R1 * (i2 % R2) : 0;
+    if (act && q < R1) {
+      cplx<R> x[R2];
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) {
+        const int c = col[q + R1 * n2];
+        x[n2] = c >= 0 ? L[lrow * ns + c] : cplx<R>{R(0), R(0)};
+      }
+      Dft<R2, +1, R>::run(x);
+#pragma unroll
+      for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tw[(q * k2) % NX]);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) X[(q + R1 * k2) * RG + r] = x[k2];
+    }
+    __syncthreads();
+    cplx<R> y[R1];
+    if (act) {
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) y[n1] = X[(n1 + R1 * q) * RG + r];
+      Dft<R1, +1, R>::run(y);  // y[k1] is the row value at i1 = q + R2 k1
+#pragma unroll
+      for (int k1 = 0; k1 < R1; ++k1) {
+        const R v = V[(q + R2 * k1) * NX + i2];
+        y[k1] = cscale(y[k1], v);
+      }
+      Dft<R1, -1, R>::run(y);  // forward, factorisation (R2, R1): first pass over n2' = k1
+#pragma unroll
+      for (int k2 = 1; k2 < R1; ++k2) {
+        const cplx<R> w = tw[(q * k2) % NX];
+        y[k2] = cmul(y[k2], cplx<R>{w.re, -w.im});
+      }
+    }
+    __syncthreads();
+    if (act) {
+#pragma unroll
+      for (int k2 = 0; k2 < R1; ++k2) X[(q + R2 * k2) * RG + r] = y[k2];
+    }
+    __syncthreads();
+    if (act && q < R1) {
+      cplx<R> z[R2];
+#pragma unroll
+      for (int n1 = 0; n1 < R2; ++n1) z[n1] = X[(n1 + R2 * q) * RG + r];
+      Dft<R2, -1, R>::run(z);  // natural output at i1 = q + R1 k1
+#pragma unroll
+      for (int k1 = 0; k1 < R2; ++k1) {
+        const int c = col[q + R1 * k1];
+        if (c >= 0) L[lrow * ns + c] = z[k1];
+      }
+    }
+    __syncthreads();
+  }
+  // ---- forward y on active columns, input in the transposed order left above
+  for (int w = tid; w < nax * R2; w += 256) {
+    const int ia = w % nax, n1 = w / nax;  // n1 in [0, R2)
+    cplx<R> x[R1];
+#pragma unroll
+    for (int n2 = 0; n2 < R1; ++n2) x[n2] = L[(n2 + R1 * n1) * ns + ia];
+    Dft<R1, -1, R>::run(x);
+#pragma unroll
+    for (int k2 = 1; k2 < R1; ++k2) {
+      const cplx<R> t = tw[(n1 * k2) % NX];
+      x[k2] = cmul(x[k2], cplx<R>{t.re, -t.im});
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < R1; ++k2) L[(k2 + R1 * n1) * ns + ia] = x[k2];
+  }
+  __syncthreads();
+  for (int w = tid; w < nax * R1; w += 256) {
+    const int ia = w % nax, k2 = w / nax;  // k2 in [0, R1)
+    cplx<R> z[R2];
+#pragma unroll
+    for (int n1 = 0; n1 < R2; ++n1) z[n1] = L[(k2 + R1 * n1) * ns + ia];
+    Dft<R2, -1, R>::run(z);
+#pragma unroll
+    for (int k1 = 0; k1 < R2; ++k1) L[(k2 + R1 * k1) * ns + ia] = z[k1];
+  }
+  __syncthreads();
+  for (int s = tid; s < ki.nstick; s += 256) {
+    const int ps = spos[s];
+    plane[s] = L[(ps & 0xffff) * ns + (ps >> 16)];
+  }
+}
+
+// ------------------------------------------------------------------ z forward + gather + kinetic
+template <typename R, int N3, int TS>
+__global__ void __launch_bounds__(TS * Split<N3>::R2) k_zfwd(LocalArgs a) {
+  constexpr int R1 = Split<N3>::R1, R2 = Split<N3>::R2, NT = TS * R2;
+  __shared__ cplx<R> tile[N3 * TS];
+  __shared__ cplx<R> tw[N3];
+  const int tid = threadIdx.x;
+  int bid = blockIdx.x;
+  const int k = locate_tile_block(a.kinfo, a.k0, a.k1, a.nbnd, bid);
+  const KInfo ki = a.kinfo[k];
+  const int band = bid / ki.ntile, t = bid - band * ki.ntile;
+  const int s0 = t * TS;
+  const int cnt = min(TS, ki.nstick - s0);
+  for (int i = tid; i < N3; i += NT) {
+    double2 w = a.tw_z[i];
+    tw[i] = {R(w.x), R(w.y)};
+  }
+  __syncthreads();
+  const int sl = tid % TS, j = tid / TS;  // j in [0, R2)
+  {
+    const cplx<R>* in = reinterpret_cast<const cplx<R>*>(a.sbuf) + ki.sbuf_off +
+                        int64_t(band) * N3 * ki.nstick + s0 + sl;
+    cplx<R> x[R1];
+#pragma unroll
+    for (int n2 = 0; n2 < R1; ++n2)
+      x[n2] = sl < cnt ? in[int64_t(n2 + R1 * j) * ki.nstick] : cplx<R>{R(0), R(0)};
+    Dft<R1, -1, R>::run(x);
+#pragma unroll
+    for (int k2 = 1; k2 < R1; ++k2) {
+      const cplx<R> w = tw[(j * k2) % N3];
+      x[k2] = cmul(x[k2], cplx<R>{w.re, -w.im});
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < R1; ++k2) tile[(k2 + R1 * j) * TS + sl] = x[k2];
+  }
+  __syncthreads();
+  if (j < R1) {
+    cplx<R> z[R2];
+#pragma unroll
+    for (int n1 = 0; n1 < R2; ++n1) z[n1] = tile[(j + R1 * n1) * TS + sl];
+    Dft<R2, -1, R>::run(z);
+#pragma unroll
+    for (int k1 = 0; k1 < R2; ++k1) tile[(j + R1 * k1) * TS + sl] = z[k1];
+  }
+  __syncthreads();
+  const int32_t* tp = a.tile_ptr + ki.tile_off;
+  const int e0 = tp[t], e1 = tp[t + 1];
+  const int64_t boff = int64_t(a.nbnd) * (ki.g_off - a.g_off0) + int64_t(band) * ki.npw;
+  const double2* psi_b = a.psi + boff;
+  double2* out_b = a.hpsi + boff;
+  const int32_t* eg = a.ent_g + ki.g_off;
+  const int32_t* esz = a.ent_sz + ki.g_off;
+  const double* kin = a.kin + ki.g_off;
+  for (int e = e0 + tid; e < e1; e += NT) {
+    const int sz = esz[e];
+    const int s = sz / N3, z = sz - s * N3;
+    const int g = eg[e];
+    const cplx<R> v = tile[z * TS + (s - s0)];
+    const double2 ps = psi_b[g];
+    const double kv = kin[g];
+    out_b[g] = make_double2(kv * ps.x + double(v.re), kv * ps.y + double(v.im));
+  }
+}
+
+}  // namespace qm

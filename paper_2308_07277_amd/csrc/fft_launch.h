@@ -1,0 +1,86 @@
+// Host dispatch of the local-part kernels over the supported FFT lengths.
+#pragma once
+#include "fft_kernels.h"
+
+namespace qm {
+
+constexpr int kZTile = 32;  // sticks per z-kernel tile (the plan's tile tables use it)
+
+template <typename R>
+void launch_local_t(qm_hpsi_plan* p, int k0, int k1, int nbnd, const void* psi, void* hpsi,
+                    hipStream_t s, StageEvents* ev) {
+  LocalArgs a{};
+  a.kinfo = p->g.kinfo;
+  a.k0 = k0;
+  a.k1 = k1;
+  a.nbnd = nbnd;
+  a.N3 = p->N3;
+  a.psi = reinterpret_cast<const double2*>(psi);
+  a.hpsi = reinterpret_cast<double2*>(hpsi);
+  a.sbuf = p->sbuf;
+  a.ent_g = p->g.ent_g;
+  a.ent_sz = p->g.ent_sz;
+  a.tile_ptr = p->g.tile_ptr;
+  a.stick_pos = p->g.stick_pos;
+  a.col_of_i1 = p->g.col_of_i1;
+  a.kin = p->g.kin;
+  a.vplan = sizeof(R) == 8 ? p->vplan64 : p->vplan32;
+  a.tw_z = p->tw_z;
+  a.tw_x = p->tw_x;
+  a.g_off0 = p->kinfo[k0].g_off;
+  a.ts = kZTile;
+  a.nax_stride = p->nax_max | 1;
+  int64_t nblk_z = 0;
+  for (int k = k0; k < k1; ++k) nblk_z += int64_t(nbnd) * p->kinfo[k].ntile;
+  const int64_t nblk_xy = int64_t(nbnd) * (k1 - k0) * p->N3;
+  QM_REQUIRE(nblk_z < (int64_t(1) << 31) && nblk_xy < (int64_t(1) << 31), QM_E_SHAPE,
+             "launch too large");
+  const int NX = p->N1;
+  const int r2x = fft_split_r2(NX);
+  const size_t smem_xy = sizeof(cplx<R>) * (size_t(NX) * a.nax_stride + size_t(NX) * (256 / r2x) + NX) +
+                         sizeof(int) * NX;
+  QM_REQUIRE(smem_xy <= 160 * 1024, QM_E_SHAPE, "xy-plane does not fit in LDS for this grid/precision");
+#define QM_ZINV(n)                                                                          \
+  case n:                                                                                   \
+    hipLaunchKernelGGL((k_zinv<R, n, kZTile>), dim3(unsigned(nblk_z)),                      \
+                       dim3(kZTile * Split<n>::R2), 0, s, a);                               \
+    break;
+#define QM_ZFWD(n)                                                                          \
+  case n:                                                                                   \
+    hipLaunchKernelGGL((k_zfwd<R, n, kZTile>), dim3(unsigned(nblk_z)),                      \
+                       dim3(kZTile * Split<n>::R2), 0, s, a);                               \
+    break;
+#define QM_XY(n)                                                                            \
+  case n: {                                                                                 \
+    static bool attr_set = false;                                                           \
+    if (!attr_set) {                                                                        \
+      QM_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_xy<R, n>),               \
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));   \
+      attr_set = true;                                                                      \
+    }                                                                                       \
+    hipLaunchKernelGGL((k_xy<R, n>), dim3(unsigned(nblk_xy)), dim3(256), smem_xy, s, a);    \
+  } break;
+  switch (p->N3) {
+    QM_FOR_EACH_FFT_LEN(QM_ZINV)
+    default: throw Error(QM_E_SHAPE, "unsupported N3");
+  }
+  QM_HIP(hipGetLastError());
+  if (ev) ev->mark(0);
+  switch (NX) {
+    QM_FOR_EACH_FFT_LEN(QM_XY)
+    default: throw Error(QM_E_SHAPE, "unsupported N1");
+  }
+  QM_HIP(hipGetLastError());
+  if (ev) ev->mark(1);
+  switch (p->N3) {
+    QM_FOR_EACH_FFT_LEN(QM_ZFWD)
+    default: throw Error(QM_E_SHAPE, "unsupported N3");
+  }
+  QM_HIP(hipGetLastError());
+  if (ev) ev->mark(2);
+#undef QM_ZINV
+#undef QM_ZFWD
+#undef QM_XY
+}
+
+}  // namespace qm

@@ -1,0 +1,344 @@
+// Complex GEMMs on the gfx950 matrix cores.
+//
+// Two shapes cover the whole path:
+//   CN:  C(i,j) = sum_g conj(A(i,g)) B(j,g)        projection P = beta^dagger psi
+//        (Sec. 2.3 <beta_j|psi>), Davidson overlaps <v_i|H v_j>, <v_i|t_n>
+//        (the ZGEMM-based vdot of Sec. 4.4).  K = g is contiguous for both operands;
+//        tall-skinny (K up to 1e5), so K is split across workgroups and the
+//        partial sums are reduced in a fixed order (deterministic).
+//   EX:  Y(j,g) = alpha sum_i W(i,j) A(i,g) + beta Y   expansion beta (D P)
+//        accumulated into H psi, Ritz updates X = V Y, Gram-Schmidt and CholQR
+//        updates.
+// Complex products are four real MFMAs (v_mfma_f64_16x16x4f64 in float64,
+// v_mfma_f32_16x16x4f32 in float32, v_mfma_f32_16x16x32_bf16 for bfloat16
+// operands with float32 accumulation).  Workgroup tile 64x64, four waves of
+// 32x32 (2x2 MFMA tiles), K staged through LDS 16 (32 for bf16) at a time.
+#include <hip/hip_bf16.h>
+
+#include "cplx.h"
+#include "qm_internal.h"
+
+namespace qm {
+
+typedef double d4v __attribute__((ext_vector_type(4)));
+typedef float f4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+
+template <typename T> struct Acc;
+template <> struct Acc<double> { typedef d4v type; };
+template <> struct Acc<float> { typedef f4v type; };
+
+__device__ __forceinline__ d4v mfma4(double a, double b, d4v c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4v mfma4(float a, float b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Output row of accumulator element r held by a lane (column = lane % 16), as measured on
+// gfx950: the float64 16x16x4 MFMA interleaves rows (lane/16 + 4r), the float32 ones block
+// them (4 (lane/16) + r).
+template <typename T> __device__ __forceinline__ int acc_row(int lane, int r);
+template <> __device__ __forceinline__ int acc_row<double>(int lane, int r) { return (lane >> 4) + 4 * r; }
+template <> __device__ __forceinline__ int acc_row<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
+
+// storage -> compute conversion of one complex element
+template <typename T> __device__ __forceinline__ cplx<T> ld(const double2* p) {
+  double2 v = *p;
+  return {T(v.x), T(v.y)};
+}
+template <typename T> __device__ __forceinline__ cplx<T> ld(const float2* p) {
+  float2 v = *p;
+  return {T(v.x), T(v.y)};
+}
+
+struct CNDev {
+  const void* A; const void* B;
+  int32_t M, N, K, tm, tn, blk0;
+  int64_t lda, ldb;
+  int64_t work_off;   // complex elements
+};
+struct EXDev {
+  const void* W; const void* A; void* Y;
+  int32_t M, N, K, tm, tn, blk0;
+  int64_t ldw, lda, ldy;
+};
+
+constexpr int MAXP = 24; // problems per launch (descriptors travel as kernel arguments)
+struct CNBatch { CNDev p[MAXP]; int32_t n; };
+struct EXBatch { EXDev p[MAXP]; int32_t n; };
+struct CNOut;
+
+constexpr int BT = 64;   // tile edge
+constexpr int KC = 16;   // K chunk (complex elements)
+
+template <typename B>
+__device__ __forceinline__ int find_prob(const B& b, int bid) {
+  int pi = 0;
+  while (pi < b.n - 1 && bid >= b.p[pi + 1].blk0) ++pi;
+  return pi;
+}
+
+// ------------------------------------------------------------------ CN, split-K partials
+template <typename T, typename SA, typename SB>
+__global__ void __launch_bounds__(256) k_cgemm_cn(const CNBatch batch, int nsplit,
+                                                  cplx<T>* __restrict__ work) {
+  typedef typename Acc<T>::type AV;
+  __shared__ cplx<T> As[BT][KC + 1];
+  __shared__ cplx<T> Bs[BT][KC + 1];
+  const int pi = find_prob(batch, blockIdx.x);
+  const CNDev& P = batch.p[pi];
+  int bid = blockIdx.x - P.blk0;
+  const int split = bid % nsplit;
+  const int tile = bid / nsplit;
+  const int i0 = (tile % P.tm) * BT, j0 = (tile / P.tm) * BT;
+  const int nch = (P.K + KC - 1) / KC;
+  const int per = (nch + nsplit - 1) / nsplit;
+  const int c0 = split * per, c1 = min(nch, c0 + per);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = (wave & 1) * 32, wj = (wave >> 1) * 32;
+  const int lrow = tid >> 2, lseg = (tid & 3) * 4;
+  const SA* A = reinterpret_cast<const SA*>(P.A);
+  const SB* B = reinterpret_cast<const SB*>(P.B);
+  AV cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = AV{0, 0, 0, 0};
+      ci[a][b] = AV{0, 0, 0, 0};
+    }
+  const bool arow = (i0 + lrow) < P.M, brow = (j0 + lrow) < P.N;
+  const SA* Ar = A + int64_t(i0 + lrow) * P.lda;
+  const SB* Br = B + int64_t(j0 + lrow) * P.ldb;
+  for (int c = c0; c < c1; ++c) {
+    const int kb = c * KC + lseg;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int g = kb + q;
+      As[lrow][lseg + q] = (arow && g < P.K) ? ld<T>(Ar + g) : cplx<T>{T(0), T(0)};
+      Bs[lrow][lseg + q] = (brow && g < P.K) ? ld<T>(Br + g) : cplx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC / 4; ++kk) {
+      const int kq = kk * 4 + (lane >> 4);
+      cplx<T> a[2], b[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[t] = As[wi + t * 16 + (lane & 15)][kq];
+        b[t] = Bs[wj + t * 16 + (lane & 15)][kq];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) {
+          // conj(a) * b = (ar br + ai bi) + i (ar bi - ai br)
+          cr[ti][tj] = mfma4(a[ti].re, b[tj].re, cr[ti][tj]);
+          cr[ti][tj] = mfma4(a[ti].im, b[tj].im, cr[ti][tj]);
+          ci[ti][tj] = mfma4(a[ti].re, b[tj].im, ci[ti][tj]);
+          ci[ti][tj] = mfma4(-a[ti].im, b[tj].re, ci[ti][tj]);
+        }
+    }
+    __syncthreads();
+  }
+  cplx<T>* W = work + P.work_off + int64_t(split) * P.M * P.N;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wi + ti * 16 + acc_row<T>(lane, r);
+        const int j = j0 + wj + tj * 16 + (lane & 15);
+        if (i < P.M && j < P.N) W[int64_t(i) * P.N + j] = cplx<T>{cr[ti][tj][r], ci[ti][tj][r]};
+      }
+}
+
+// C = alpha * sum_s part_s + beta * C  (c128 output, row-major ldc)
+struct CNOut { void* C; int32_t M, N; int64_t ldc, work_off, elem0; };
+struct CNOutBatch { CNOut p[MAXP]; int32_t n; };
+__global__ void k_cn_reduce(const CNOutBatch outs, int nsplit,
+                            const cplx<double>* __restrict__ work, double alpha, double beta,
+                            int64_t total) {
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    int pi = 0;
+    while (pi < outs.n - 1 && t >= outs.p[pi + 1].elem0) ++pi;
+    const CNOut& o = outs.p[pi];
+    const int64_t e = t - o.elem0;
+    const int i = int(e / o.N), j = int(e % o.N);
+    double sr = 0, si = 0;
+    const cplx<double>* w = work + o.work_off + e;
+    for (int s = 0; s < nsplit; ++s) {
+      sr += w[int64_t(s) * o.M * o.N].re;
+      si += w[int64_t(s) * o.M * o.N].im;
+    }
+    double2* c = reinterpret_cast<double2*>(o.C) + int64_t(i) * o.ldc + j;
+    double2 old = beta != 0.0 ? *c : make_double2(0.0, 0.0);
+    *c = make_double2(alpha * sr + beta * old.x, alpha * si + beta * old.y);
+  }
+}
+
+// ------------------------------------------------------------------ EX
+template <typename T, typename SW, typename SA>
+__global__ void __launch_bounds__(256) k_cgemm_ex(const EXBatch batch, double alpha, double beta) {
+  typedef typename Acc<T>::type AV;
+  __shared__ cplx<T> Ws[KC][BT + 1];
+  __shared__ cplx<T> As[KC][BT + 1];
+  const int pi = find_prob(batch, blockIdx.x);
+  const EXDev& P = batch.p[pi];
+  const int tile = blockIdx.x - P.blk0;
+  const int m0 = (tile % P.tm) * BT, n0 = (tile / P.tm) * BT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = (wave & 1) * 32, wj = (wave >> 1) * 32;
+  const int lr = tid >> 4, lc = (tid & 15) * 4;
+  const SW* Wp = reinterpret_cast<const SW*>(P.W);
+  const SA* Ap = reinterpret_cast<const SA*>(P.A);
+  AV cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = AV{0, 0, 0, 0};
+      ci[a][b] = AV{0, 0, 0, 0};
+    }
+  const int nch = (P.K + KC - 1) / KC;
+  for (int c = 0; c < nch; ++c) {
+    const int i = c * KC + lr;
+    const bool irow = i < P.K;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = m0 + lc + q, n = n0 + lc + q;
+      Ws[lr][lc + q] = (irow && m < P.M) ? ld<T>(Wp + int64_t(i) * P.ldw + m) : cplx<T>{T(0), T(0)};
+      As[lr][lc + q] = (irow && n < P.N) ? ld<T>(Ap + int64_t(i) * P.lda + n) : cplx<T>{T(0), T(0)};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC / 4; ++kk) {
+      const int kq = kk * 4 + (lane >> 4);
+      cplx<T> a[2], b[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[t] = Ws[kq][wi + t * 16 + (lane & 15)];
+        b[t] = As[kq][wj + t * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj) {
+          cr[ti][tj] = mfma4(a[ti].re, b[tj].re, cr[ti][tj]);
+          cr[ti][tj] = mfma4(-a[ti].im, b[tj].im, cr[ti][tj]);
+          ci[ti][tj] = mfma4(a[ti].re, b[tj].im, ci[ti][tj]);
+          ci[ti][tj] = mfma4(a[ti].im, b[tj].re, ci[ti][tj]);
+        }
+    }
+    __syncthreads();
+  }
+  double2* Y = reinterpret_cast<double2*>(P.Y);
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wi + ti * 16 + acc_row<T>(lane, r);
+        const int n = n0 + wj + tj * 16 + (lane & 15);
+        if (m < P.M && n < P.N) {
+          double2* y = Y + int64_t(m) * P.ldy + n;
+          const double vr = double(cr[ti][tj][r]), vi = double(ci[ti][tj][r]);
+          if (beta != 0.0) {
+            const double2 o = *y;
+            *y = make_double2(alpha * vr + beta * o.x, alpha * vi + beta * o.y);
+          } else {
+            *y = make_double2(alpha * vr, alpha * vi);
+          }
+        }
+      }
+}
+
+// ------------------------------------------------------------------ host side
+static int choose_splits(int64_t tiles, int64_t maxK) {
+  int s = 1;
+  while (tiles * s < 1024 && (maxK / (KC * (s * 2))) >= 8 && s < 64) s *= 2;
+  return s;
+}
+
+int64_t zgemm_cn_work_bytes(const std::vector<GemmCN>& probs) {
+  int64_t tiles = 0, maxK = 0, mn = 0;
+  for (const GemmCN& g : probs) {
+    tiles += int64_t((g.M + BT - 1) / BT) * ((g.N + BT - 1) / BT);
+    maxK = std::max<int64_t>(maxK, g.K);
+    mn += int64_t(g.M) * g.N;
+  }
+  return int64_t(choose_splits(tiles, maxK)) * mn * int64_t(sizeof(cplx<double>));
+}
+
+void zgemm_cn_batched(const std::vector<GemmCN>& probs, double alpha, double beta_c, void* work,
+                      int64_t work_bytes, hipStream_t s, StageEvents* ev, int stage0) {
+  for (size_t base = 0; base < probs.size(); base += MAXP) {
+    const size_t n = std::min<size_t>(MAXP, probs.size() - base);
+    std::vector<GemmCN> sub(probs.begin() + base, probs.begin() + base + n);
+    CNBatch d{};
+    CNOutBatch o{};
+    d.n = o.n = int32_t(n);
+    int64_t tiles = 0, maxK = 0;
+    for (const GemmCN& g : sub) {
+      tiles += int64_t((g.M + BT - 1) / BT) * ((g.N + BT - 1) / BT);
+      maxK = std::max<int64_t>(maxK, g.K);
+    }
+    const int nsplit = choose_splits(tiles, maxK);
+    int64_t blk = 0, woff = 0, e0 = 0;
+    for (size_t i = 0; i < n; ++i) {
+      const GemmCN& g = sub[i];
+      CNDev& x = d.p[i];
+      x.A = g.A; x.B = g.B;
+      x.M = g.M; x.N = g.N; x.K = g.K;
+      x.tm = (g.M + BT - 1) / BT; x.tn = (g.N + BT - 1) / BT;
+      x.blk0 = int32_t(blk);
+      x.lda = g.lda; x.ldb = g.ldb;
+      x.work_off = woff;
+      o.p[i] = CNOut{g.C, g.M, g.N, g.ldc, woff, e0};
+      blk += int64_t(x.tm) * x.tn * nsplit;
+      woff += int64_t(nsplit) * g.M * g.N;
+      e0 += int64_t(g.M) * g.N;
+    }
+    if (e0 == 0) continue;
+    QM_REQUIRE(woff * int64_t(sizeof(cplx<double>)) <= work_bytes, QM_E_STATE,
+               "GEMM split-K workspace too small");
+    hipLaunchKernelGGL((k_cgemm_cn<double, double2, double2>), dim3(unsigned(blk)), dim3(256), 0, s,
+                       d, nsplit, reinterpret_cast<cplx<double>*>(work));
+    QM_HIP(hipGetLastError());
+    if (ev) ev->mark(stage0);
+    const int rb = int(std::min<int64_t>((e0 + 255) / 256, 8192));
+    hipLaunchKernelGGL(k_cn_reduce, dim3(rb), dim3(256), 0, s, o, nsplit,
+                       reinterpret_cast<const cplx<double>*>(work), alpha, beta_c, e0);
+    QM_HIP(hipGetLastError());
+    if (ev) ev->mark(stage0 + 1);
+  }
+}
+
+void zgemm_ex_batched(const std::vector<GemmEX>& probs, double alpha, double beta_y, hipStream_t s) {
+  for (size_t base = 0; base < probs.size(); base += MAXP) {
+    const size_t n = std::min<size_t>(MAXP, probs.size() - base);
+    EXBatch d{};
+    d.n = int32_t(n);
+    int64_t blk = 0;
+    for (size_t i = 0; i < n; ++i) {
+      const GemmEX& g = probs[base + i];
+      EXDev& x = d.p[i];
+      x.W = g.W; x.A = g.A; x.Y = g.Y;
+      x.M = g.M; x.N = g.N; x.K = g.K;
+      x.tm = (g.M + BT - 1) / BT; x.tn = (g.N + BT - 1) / BT;
+      x.blk0 = int32_t(blk);
+      x.ldw = g.ldw; x.lda = g.lda; x.ldy = g.ldy;
+      blk += int64_t(x.tm) * x.tn;
+    }
+    if (blk == 0) continue;
+    hipLaunchKernelGGL((k_cgemm_ex<double, double2, double2>), dim3(unsigned(blk)), dim3(256), 0, s,
+                       d, alpha, beta_y);
+    QM_HIP(hipGetLastError());
+  }
+}
+
+}  // namespace qm

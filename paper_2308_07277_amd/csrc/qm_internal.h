@@ -1,0 +1,134 @@
+// Internal declarations of the gfx950 H|psi> / Davidson library.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/qm_hpsi.h"
+
+namespace qm {
+
+struct Error : std::runtime_error {
+  qm_status code;
+  Error(qm_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define QM_HIP(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw ::qm::Error(e_ == hipErrorOutOfMemory ? QM_E_NOMEM : QM_E_HIP,             \
+                        std::string(#call) + ": " + hipGetErrorString(e_));            \
+  } while (0)
+
+#define QM_REQUIRE(cond, code, msg) \
+  do {                              \
+    if (!(cond)) throw ::qm::Error(code, msg); \
+  } while (0)
+
+// Per-k description used by every kernel; lives in device memory.
+struct KInfo {
+  int32_t npw;      // sphere size
+  int32_t nstick;   // z-sticks holding at least one G
+  int32_t ntile;    // stick tiles of the z kernels
+  int32_t nax;      // active x-columns (distinct i1 over the sticks)
+  int64_t g_off;    // prefix sum of npw over earlier k
+  int64_t stick_off;// prefix sum of nstick
+  int64_t tile_off; // prefix sum of (ntile + 1)
+  int64_t sbuf_off; // element offset of this k's stick buffer (band 0)
+  int64_t beta_off; // element offset of beta_k (= nproj * g_off)
+};
+
+// Device-resident G-space tables of one plan.
+struct GTables {
+  KInfo* kinfo = nullptr;        // [nk]
+  int32_t* ent_g = nullptr;      // [sum npw] caller index of the G, entries sorted by (stick, i3)
+  int32_t* ent_sz = nullptr;     // [sum npw] stick_local_in_k * N3 + i3
+  int32_t* tile_ptr = nullptr;   // [sum (ntile+1)] entry offset (within k) of each tile
+  int32_t* stick_pos = nullptr;  // [sum nstick] i2 | (ia << 16)
+  int32_t* col_of_i1 = nullptr;  // [nk][N1] active-column index of i1, or -1
+  double* kin = nullptr;         // [sum npw] 1/2|k+G|^2 in caller order
+};
+
+struct DavState;  // Davidson workspace (davidson.cpp)
+
+// Optional per-stage event recorder: mark(i) records event i+1 after stage i.
+struct StageEvents {
+  hipEvent_t ev[QM_NSTAGES + 1];
+  bool used[QM_NSTAGES];
+  hipStream_t s;
+  void mark(int i) {
+    if (hipEventRecord(ev[i + 1], s) == hipSuccess) used[i] = true;
+  }
+};
+
+}  // namespace qm
+
+struct qm_hpsi_plan {
+  int32_t N1 = 0, N2 = 0, N3 = 0;
+  int32_t nk = 0, nbnd_max = 0, nproj = 0;
+  qm_prec prec = QM_PREC_FP64;
+  int32_t zts = 32;               // sticks per z-kernel tile
+  int32_t nax_max = 0;
+  int64_t npw_total = 0;
+  int32_t npw_max = 0;
+  double cell[9] = {0}, recip[9] = {0};
+  std::vector<qm::KInfo> kinfo;   // host copy
+  qm::GTables g;
+  void* vplan64 = nullptr;        // float64 [N3 slot][N1][N2], scaled by 1/N_r
+  void* vplan32 = nullptr;        // float32, same layout
+  void* beta64 = nullptr;         // c128 copy of beta
+  void* beta_lp = nullptr;        // c64 (FP32) or bf16 pairs (MIXED) copy, per prec
+  int32_t beta_lp_kind = -1;      // which representation beta_lp holds (qm_prec) or -1
+  double* dmat = nullptr;         // [nproj][nproj]
+  int32_t* drange = nullptr;      // [nproj][2] nonzero column range per row of D
+  double2* tw_z = nullptr;        // exp(+2 pi i m / N3), m < N3
+  double2* tw_x = nullptr;        // exp(+2 pi i m / N1), m < N1
+  void* sbuf = nullptr;           // stick buffer, sized for float64 (reused by float32)
+  int64_t sbuf_elems = 0;
+  void* proj_part = nullptr;      // split-K partial projections
+  int64_t proj_part_bytes = 0;
+  void* proj_q = nullptr;         // Q = D P, c128 [nk][nproj][nbnd_max] or float in lower precisions
+  int32_t proj_splits = 1;
+  std::string err;
+  qm::DavState* dav = nullptr;
+};
+
+namespace qm {
+// launchers (fft.hip / gemm.hip); k0..k1 is the k range, psi/hpsi point at k0's first band
+void launch_hpsi_local(qm_hpsi_plan* p, int k0, int k1, int nbnd, const void* psi, void* hpsi,
+                       hipStream_t s, bool fp32, StageEvents* ev = nullptr);
+void launch_vplan(qm_hpsi_plan* p, const double* vloc_r, hipStream_t s);
+void launch_nonlocal(qm_hpsi_plan* p, int k0, int k1, int nbnd, const void* psi, void* hpsi,
+                     hipStream_t s, qm_prec prec, StageEvents* ev = nullptr);
+void convert_beta(qm_hpsi_plan* p, qm_prec prec, hipStream_t s);
+bool fft_len_supported(int n);
+int fft_split_r1(int n);
+int fft_split_r2(int n);
+
+// complex GEMMs (c128 data, float64 arithmetic) used by the Davidson and the non-local term
+// C[b](i,j) = alpha * sum_g conj(A[b](i,g)) B[b](j,g) + beta_c * C   (row-major, K = g contiguous)
+struct GemmCN {
+  const void* A; const void* B; void* C;
+  int32_t M, N, K;
+  int64_t lda, ldb, ldc;
+};
+// Y[b](j,g) = alpha * sum_i W[b](i,j) A[b](i,g) + beta_y * Y
+struct GemmEX {
+  const void* W; const void* A; void* Y;
+  int32_t M, N, K;        // M = rows of Y (j), N = cols of Y (g), K = i
+  int64_t ldw, lda, ldy;
+};
+void zgemm_cn_batched(const std::vector<GemmCN>& probs, double alpha, double beta_c,
+                      void* work, int64_t work_bytes, hipStream_t s, StageEvents* ev = nullptr,
+                      int stage0 = 0);
+int64_t zgemm_cn_work_bytes(const std::vector<GemmCN>& probs);
+void zgemm_ex_batched(const std::vector<GemmEX>& probs, double alpha, double beta_y,
+                      hipStream_t s);
+
+void plan_upload_davidson(qm_hpsi_plan* p);
+void davidson_free(qm_hpsi_plan* p);
+}  // namespace qm
