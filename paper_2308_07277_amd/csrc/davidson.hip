@@ -1,32 +1,483 @@
-// Block Davidson driver (placeholder until the GPU eigensolver lands).
-#include "qm_internal.h"
+// Block Davidson for the lowest bands of H(k), all k-points of a call batched
+// (Sec. 5 'dft' module: a Davidson that only needs H applied to trial blocks).
+//
+// Per iteration and active k:  corrections t_n = K(x) r_n for the unconverged
+// bands (Teter-Payne-Allan, or the learned gain network), restart V = X when
+// the basis would overflow, two block Gram-Schmidt passes against V and two
+// CholQR passes, H t, extend the projected matrix by its new columns,
+// Hermitian eigenproblem on the GPU (tridiagonalisation + bisection + inverse
+// iteration), Ritz vectors X = V Y, HX = HV Y, residuals.  Convergence is the
+// plain residual norm max_n ||H x_n - theta_n x_n|| <= tol.  The host only
+// reads the per-band residual norms and Ritz values once per iteration.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "dense.h"
 
 namespace qm {
-struct DavState {};
+
+void mlp_precondition(qm_hpsi_plan* p, const DJobs& jobs, const void* weights, hipStream_t s);
+
+struct DavState {
+  int nb = 0, mb = 0, k0 = 0, k1 = 0, nk = 0;
+  bool ready = false;
+  bool lowp = false;
+  double2 *V = nullptr, *HV = nullptr, *X = nullptr, *HX = nullptr, *R = nullptr, *TS = nullptr;
+  double2 *Hs = nullptr, *Aw = nullptr, *Z = nullptr, *tau = nullptr, *Cw = nullptr, *G = nullptr,
+          *W = nullptr;
+  double *theta = nullptr, *d = nullptr, *e = nullptr, *resn = nullptr, *tkin = nullptr,
+         *yw = nullptr, *fw = nullptr;
+  int32_t *unconv = nullptr, *info = nullptr;
+  int64_t* goff = nullptr;
+  void* work = nullptr;
+  int64_t work_bytes = 0;
+  double *h_resn = nullptr, *h_theta = nullptr;
+  int32_t *h_unconv = nullptr, *h_info = nullptr;
+  std::vector<int> m, it, done;
+  int64_t n_hpsi = 0, n_hpsi_lowp = 0;
+  double t_hpsi = 0, t_sub = 0, t_eig = 0;
+  hipEvent_t ev[6] = {};
+};
+
+static void dav_release(DavState* d) {
+  void* dev[] = {d->V, d->HV, d->X, d->HX, d->R, d->TS, d->Hs, d->Aw, d->Z, d->tau, d->Cw, d->G,
+                 d->W, d->theta, d->d, d->e, d->resn, d->tkin, d->yw, d->fw, d->unconv, d->info,
+                 d->goff, d->work};
+  for (void* q : dev)
+    if (q) (void)hipFree(q);
+  void* host[] = {d->h_resn, d->h_theta, d->h_unconv, d->h_info};
+  for (void* q : host)
+    if (q) (void)hipHostFree(q);
+  for (hipEvent_t& e : d->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete d;
+}
+
 void davidson_free(qm_hpsi_plan* p) {
-  delete p->dav;
+  if (p->dav) dav_release(p->dav);
   p->dav = nullptr;
 }
+
+template <typename T>
+static T* dalloc(size_t n) {
+  T* q = nullptr;
+  QM_HIP(hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)));
+  return q;
+}
+
+static DavState* dav_create(qm_hpsi_plan* p, int k0, int k1, int nb, int mb) {
+  DavState* d = new DavState();
+  try {
+    d->nb = nb;
+    d->mb = mb;
+    d->k0 = k0;
+    d->k1 = k1;
+    d->nk = p->nk;
+    const size_t np = size_t(p->npw_total), nk = size_t(p->nk);
+    d->V = dalloc<double2>(size_t(mb) * np);
+    d->HV = dalloc<double2>(size_t(mb) * np);
+    d->X = dalloc<double2>(size_t(nb) * np);
+    d->HX = dalloc<double2>(size_t(nb) * np);
+    d->R = dalloc<double2>(size_t(nb) * np);
+    d->TS = dalloc<double2>(size_t(nb) * np);
+    d->Hs = dalloc<double2>(nk * mb * mb);
+    d->Aw = dalloc<double2>(nk * mb * mb);
+    d->Z = dalloc<double2>(nk * mb * nb);
+    d->tau = dalloc<double2>(nk * mb);
+    d->Cw = dalloc<double2>(nk * mb * nb);
+    d->G = dalloc<double2>(nk * nb * nb);
+    d->W = dalloc<double2>(nk * nb * nb);
+    d->theta = dalloc<double>(nk * mb);
+    d->d = dalloc<double>(nk * mb);
+    d->e = dalloc<double>(nk * mb);
+    d->resn = dalloc<double>(nk * nb);
+    d->tkin = dalloc<double>(nk * nb);
+    d->yw = dalloc<double>(nk * nb * mb);
+    d->fw = dalloc<double>(nk * nb * 5 * mb);
+    d->unconv = dalloc<int32_t>(nk * nb);
+    d->info = dalloc<int32_t>(nk);
+    d->goff = dalloc<int64_t>(nk);
+    std::vector<int64_t> go(nk);
+    for (size_t k = 0; k < nk; ++k) go[k] = p->kinfo[k].g_off;
+    QM_HIP(hipMemcpy(d->goff, go.data(), nk * sizeof(int64_t), hipMemcpyHostToDevice));
+    d->work_bytes = int64_t(16) * int64_t(nk) * mb * nb * int64_t(sizeof(double2));
+    d->work = dalloc<char>(size_t(d->work_bytes));
+    QM_HIP(hipHostMalloc(reinterpret_cast<void**>(&d->h_resn), nk * nb * 2 * sizeof(double)));
+    QM_HIP(hipHostMalloc(reinterpret_cast<void**>(&d->h_theta), nk * mb * sizeof(double)));
+    QM_HIP(hipHostMalloc(reinterpret_cast<void**>(&d->h_unconv), nk * nb * sizeof(int32_t)));
+    QM_HIP(hipHostMalloc(reinterpret_cast<void**>(&d->h_info), nk * sizeof(int32_t)));
+    for (hipEvent_t& e : d->ev) QM_HIP(hipEventCreate(&e));
+    d->m.assign(nk, 0);
+    d->it.assign(nk, 0);
+    d->done.assign(nk, 0);
+  } catch (...) {
+    dav_release(d);
+    throw;
+  }
+  return d;
+}
+
+static double2* vrow(DavState* d, double2* base, const DJob& j, int row) {
+  return base + j.voff + int64_t(row) * j.npw;
+}
+
+static void timed_apply(qm_hpsi_plan* p, DavState* d, const std::vector<KSlice>& sl, const void* in,
+                        void* out, hipStream_t s, bool lowp) {
+  QM_HIP(hipEventRecord(d->ev[0], s));
+  apply_h_slices(p, sl, in, out, s, lowp ? p->prec : QM_PREC_FP64);
+  QM_HIP(hipEventRecord(d->ev[1], s));
+  QM_HIP(hipEventSynchronize(d->ev[1]));
+  float ms = 0.f;
+  QM_HIP(hipEventElapsedTime(&ms, d->ev[0], d->ev[1]));
+  d->t_hpsi += ms;
+  int64_t nb = 0;
+  for (const KSlice& x : sl) nb += x.nb;
+  d->n_hpsi += nb;
+  if (lowp && p->prec != QM_PREC_FP64) d->n_hpsi_lowp += nb;
+}
+
+// T = rows [m - nu, m) of V; orthogonalise against rows [0, m - nu) (two CGS passes) and
+// orthonormalise (two CholQR passes).  Returns false if a Gram matrix was not positive definite.
+static bool orthonormalise(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipStream_t s) {
+  std::vector<GemmCN> cn;
+  std::vector<GemmEX> ex;
+  for (int pass = 0; pass < 2; ++pass) {
+    cn.clear();
+    ex.clear();
+    for (int i = 0; i < jobs.n; ++i) {
+      const DJob& j = jobs.j[i];
+      const int base = j.m - j.nu;
+      if (base == 0) continue;
+      double2* T = vrow(d, d->V, j, base);
+      double2* C = d->Cw + int64_t(j.k) * d->mb * d->nb;
+      cn.push_back(GemmCN{vrow(d, d->V, j, 0), T, C, base, j.nu, j.npw, j.npw, j.npw, d->nb});
+      ex.push_back(GemmEX{C, vrow(d, d->V, j, 0), T, j.nu, j.npw, base, d->nb, j.npw, j.npw});
+    }
+    zgemm_cn_batched(cn, 1.0, 0.0, d->work, d->work_bytes, s);
+    zgemm_ex_batched(ex, -1.0, 1.0, s);
+  }
+  for (int pass = 0; pass < 2; ++pass) {
+    cn.clear();
+    ex.clear();
+    for (int i = 0; i < jobs.n; ++i) {
+      const DJob& j = jobs.j[i];
+      double2* T = pass == 0 ? vrow(d, d->V, j, j.m - j.nu) : d->TS + j.xoff;
+      double2* O = pass == 0 ? d->TS + j.xoff : vrow(d, d->V, j, j.m - j.nu);
+      double2* Gk = d->G + int64_t(j.k) * d->nb * d->nb;
+      double2* Wk = d->W + int64_t(j.k) * d->nb * d->nb;
+      cn.push_back(GemmCN{T, T, Gk, j.nu, j.nu, j.npw, j.npw, j.npw, d->nb});
+      ex.push_back(GemmEX{Wk, T, O, j.nu, j.npw, j.nu, d->nb, j.npw, j.npw});
+    }
+    zgemm_cn_batched(cn, 1.0, 0.0, d->work, d->work_bytes, s);
+    hipLaunchKernelGGL(k_chol_inv, dim3(jobs.n), dim3(1024), 0, s, jobs, d->G, d->W, d->info);
+    QM_HIP(hipGetLastError());
+    zgemm_ex_batched(ex, 1.0, 0.0, s);
+  }
+  QM_HIP(hipMemcpyAsync(d->h_info, d->info, sizeof(int32_t) * d->nk, hipMemcpyDeviceToHost, s));
+  QM_HIP(hipStreamSynchronize(s));
+  for (int i = 0; i < jobs.n; ++i)
+    if (d->h_info[jobs.j[i].k] != 0) return false;
+  return true;
+}
+
+// Projected matrix columns [m_old, m), eigenproblem, Ritz vectors and residuals.
+static void rayleigh_ritz(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipStream_t s) {
+  std::vector<GemmCN> cn;
+  for (int i = 0; i < jobs.n; ++i) {
+    const DJob& j = jobs.j[i];
+    double2* Hk = d->Hs + int64_t(j.k) * d->mb * d->mb;
+    cn.push_back(GemmCN{vrow(d, d->V, j, 0), vrow(d, d->HV, j, j.m_old), Hk + j.m_old, j.m,
+                        j.m - j.m_old, j.npw, j.npw, j.npw, d->mb});
+  }
+  zgemm_cn_batched(cn, 1.0, 0.0, d->work, d->work_bytes, s);
+  hipLaunchKernelGGL(k_hs_fill, dim3(64, jobs.n), dim3(256), 0, s, jobs, d->Hs);
+  hipLaunchKernelGGL(k_hs_copy, dim3(64, jobs.n), dim3(256), 0, s, jobs, d->Hs, d->Aw);
+  QM_HIP(hipGetLastError());
+  QM_HIP(hipEventRecord(d->ev[2], s));
+  hipLaunchKernelGGL(k_tridiag, dim3(jobs.n), dim3(1024), size_t(2) * d->mb * sizeof(double2), s,
+                     jobs, d->Aw, d->d, d->e, d->tau);
+  QM_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_tridiag_eig, dim3(jobs.n), dim3(1024), size_t(d->mb) * sizeof(double2), s,
+                     jobs, d->Aw, d->d, d->e, d->tau, d->theta, d->Z, d->yw, d->fw);
+  QM_HIP(hipGetLastError());
+  QM_HIP(hipEventRecord(d->ev[3], s));
+  std::vector<GemmEX> ex;
+  for (int i = 0; i < jobs.n; ++i) {
+    const DJob& j = jobs.j[i];
+    double2* Zk = d->Z + int64_t(j.k) * d->mb * d->nb;
+    ex.push_back(GemmEX{Zk, vrow(d, d->V, j, 0), d->X + j.xoff, d->nb, j.npw, j.m, d->nb, j.npw, j.npw});
+    ex.push_back(GemmEX{Zk, vrow(d, d->HV, j, 0), d->HX + j.xoff, d->nb, j.npw, j.m, d->nb, j.npw, j.npw});
+  }
+  zgemm_ex_batched(ex, 1.0, 0.0, s);
+  hipLaunchKernelGGL(k_residual, dim3(d->nb, jobs.n), dim3(256), 0, s, jobs, d->X, d->HX, d->R,
+                     d->theta, p->g.kin, d->goff, d->resn, d->tkin);
+  QM_HIP(hipGetLastError());
+  QM_HIP(hipMemcpyAsync(d->h_resn, d->resn, sizeof(double) * d->nk * d->nb, hipMemcpyDeviceToHost, s));
+  QM_HIP(hipMemcpyAsync(d->h_theta, d->theta, sizeof(double) * d->nk * d->mb, hipMemcpyDeviceToHost, s));
+  QM_HIP(hipStreamSynchronize(s));
+  float ms = 0.f;
+  QM_HIP(hipEventElapsedTime(&ms, d->ev[2], d->ev[3]));
+  d->t_eig += ms;
+}
+
+static DJob make_job(qm_hpsi_plan* p, DavState* d, int k) {
+  DJob j{};
+  j.k = k;
+  j.npw = p->kinfo[k].npw;
+  j.voff = int64_t(d->mb) * p->kinfo[k].g_off;
+  j.xoff = int64_t(d->nb) * p->kinfo[k].g_off;
+  return j;
+}
+
+// copy X (and HX) of the job's k into basis rows [0, nb) after re-orthonormalising X by CholQR
+static bool restart_basis(qm_hpsi_plan* p, DavState* d, std::vector<DJob>& js, hipStream_t s) {
+  for (DJob& j : js) {
+    QM_HIP(hipMemcpyAsync(vrow(d, d->V, j, 0), d->X + j.xoff, sizeof(double2) * d->nb * j.npw,
+                          hipMemcpyDeviceToDevice, s));
+    QM_HIP(hipMemcpyAsync(vrow(d, d->HV, j, 0), d->HX + j.xoff, sizeof(double2) * d->nb * j.npw,
+                          hipMemcpyDeviceToDevice, s));
+  }
+  (void)p;
+  return true;
+}
+
+struct StepResult {
+  int n_unconv = 0;
+  double max_res = 0.0;
+  bool nan = false;
+};
+
+static void collect(qm_hpsi_plan* p, DavState* d, double tol, StepResult& r) {
+  (void)p;
+  for (int k = d->k0; k < d->k1; ++k) {
+    if (d->done[k]) continue;
+    int nu = 0;
+    for (int n = 0; n < d->nb; ++n) {
+      const double x = d->h_resn[int64_t(k) * d->nb + n];
+      if (!std::isfinite(x)) r.nan = true;
+      r.max_res = std::max(r.max_res, x);
+      if (!(x <= tol)) d->h_unconv[int64_t(k) * d->nb + nu++] = n;
+    }
+    r.n_unconv += nu;
+    if (nu == 0) d->done[k] = 1;
+  }
+}
+
+static void write_outputs(qm_hpsi_plan* p, DavState* d, void* psi, double* eig, double* resnorm,
+                          hipStream_t s) {
+  const int64_t g0 = p->kinfo[d->k0].g_off;
+  for (int k = d->k0; k < d->k1; ++k) {
+    const KInfo& ki = p->kinfo[k];
+    if (psi)
+      QM_HIP(hipMemcpyAsync(reinterpret_cast<double2*>(psi) + int64_t(d->nb) * (ki.g_off - g0),
+                            d->X + int64_t(d->nb) * ki.g_off, sizeof(double2) * d->nb * ki.npw,
+                            hipMemcpyDeviceToDevice, s));
+    for (int n = 0; n < d->nb; ++n) {
+      if (eig) eig[int64_t(k - d->k0) * d->nb + n] = d->h_theta[int64_t(k) * d->mb + n];
+      if (resnorm) resnorm[int64_t(k - d->k0) * d->nb + n] = d->h_resn[int64_t(k) * d->nb + n];
+    }
+  }
+  QM_HIP(hipStreamSynchronize(s));
+}
+
+static qm_status dav_step(qm_hpsi_plan* p, int k, void* psi, double* eig, double* resnorm, int nb,
+                          const qm_dav_opts* o, int32_t* n_unconv, hipStream_t s) {
+  QM_REQUIRE(nb >= 1 && nb <= p->nbnd_max, QM_E_ARG, "need 1 <= nbnd <= nbnd_max");
+  QM_REQUIRE(k >= -1 && k < p->nk, QM_E_ARG, "k out of range");
+  QM_REQUIRE(psi, QM_E_ARG, "psi must be non-NULL");
+  const double tol = (o && o->tol > 0) ? o->tol : 1e-8;
+  int mb = (o && o->max_basis > 0) ? o->max_basis : 4 * nb;
+  QM_REQUIRE(mb >= 2 * nb, QM_E_ARG, "max_basis must be at least 2 nbnd");
+  QM_REQUIRE(mb <= 4096, QM_E_ARG, "max_basis above 4096 is not supported");
+  const int precond = o ? o->precond : QM_PRECOND_TETER;
+  QM_REQUIRE(precond == QM_PRECOND_TETER || (precond == QM_PRECOND_MLP && o->mlp_weights),
+             QM_E_ARG, "QM_PRECOND_MLP needs mlp_weights");
+  const int k0 = k < 0 ? 0 : k, k1 = k < 0 ? p->nk : k + 1;
+  QM_REQUIRE(k1 - k0 <= kMaxSlices, QM_E_ARG, "at most 32 k-points per Davidson call");
+  DavState* d = p->dav;
+  const bool fresh = !d || !d->ready || (o && o->restart) || d->k0 != k0 || d->k1 != k1 ||
+                     d->nb != nb || d->mb != mb;
+  if (fresh) {
+    if (!d || d->k0 != k0 || d->k1 != k1 || d->nb != nb || d->mb != mb) {
+      davidson_free(p);
+      p->dav = d = dav_create(p, k0, k1, nb, mb);
+    }
+    d->ready = false;
+    std::fill(d->m.begin(), d->m.end(), 0);
+    std::fill(d->it.begin(), d->it.end(), 0);
+    std::fill(d->done.begin(), d->done.end(), 0);
+    d->n_hpsi = d->n_hpsi_lowp = 0;
+    d->t_hpsi = d->t_sub = d->t_eig = 0;
+    d->lowp = o && o->switch_resid > 0.0 && p->prec != QM_PREC_FP64;
+  }
+  DJobs jobs{};
+  jobs.nb = nb;
+  jobs.mb = mb;
+  std::vector<KSlice> sl;
+  if (!d->ready) {
+    const int64_t g0 = p->kinfo[k0].g_off;
+    for (int kk = k0; kk < k1; ++kk) {
+      DJob j = make_job(p, d, kk);
+      QM_HIP(hipMemcpyAsync(vrow(d, d->V, j, 0),
+                            reinterpret_cast<const double2*>(psi) + int64_t(nb) * (p->kinfo[kk].g_off - g0),
+                            sizeof(double2) * nb * j.npw, hipMemcpyDeviceToDevice, s));
+      j.m = nb;
+      j.m_old = 0;
+      j.nu = nb;
+      jobs.j[jobs.n++] = j;
+      sl.push_back(KSlice{kk, nb, j.voff, j.voff});
+    }
+    if (!orthonormalise(p, d, jobs, s)) throw Error(QM_E_NOT_SPD, "start block is linearly dependent");
+    timed_apply(p, d, sl, d->V, d->HV, s, d->lowp);
+    rayleigh_ritz(p, d, jobs, s);
+    for (int i = 0; i < jobs.n; ++i) d->m[jobs.j[i].k] = nb;
+    d->ready = true;
+  } else {
+    // precision ladder: leave the reduced-precision H once the residual is small enough,
+    // rebuilding the basis from the Ritz vectors with float64 H
+    double maxres = 0.0;
+    for (int kk = k0; kk < k1; ++kk)
+      for (int n = 0; n < nb; ++n) maxres = std::max(maxres, d->h_resn[int64_t(kk) * nb + n]);
+    const bool refresh = d->lowp && o && maxres <= o->switch_resid;
+    if (refresh) {
+      d->lowp = false;
+      for (int kk = k0; kk < k1; ++kk) {
+        if (d->done[kk]) continue;
+        DJob j = make_job(p, d, kk);
+        QM_HIP(hipMemcpyAsync(vrow(d, d->V, j, 0), d->X + j.xoff, sizeof(double2) * nb * j.npw,
+                              hipMemcpyDeviceToDevice, s));
+        j.m = nb;
+        j.m_old = 0;
+        j.nu = nb;
+        jobs.j[jobs.n++] = j;
+        sl.push_back(KSlice{kk, nb, j.voff, j.voff});
+      }
+      if (jobs.n) {
+        if (!orthonormalise(p, d, jobs, s)) throw Error(QM_E_NOT_SPD, "Ritz block lost rank");
+        timed_apply(p, d, sl, d->V, d->HV, s, false);
+        rayleigh_ritz(p, d, jobs, s);
+        for (int i = 0; i < jobs.n; ++i) {
+          d->m[jobs.j[i].k] = nb;
+          d->it[jobs.j[i].k] += 1;
+        }
+      }
+    } else {
+      std::vector<DJob> restart;
+      for (int kk = k0; kk < k1; ++kk) {
+        if (d->done[kk]) continue;
+        int nu = 0;
+        for (int n = 0; n < nb; ++n)
+          if (!(d->h_resn[int64_t(kk) * nb + n] <= tol)) ++nu;
+        DJob j = make_job(p, d, kk);
+        if (d->m[kk] + nu > mb) {
+          restart.push_back(j);
+          d->m[kk] = nb;
+          j.m_old = 0;
+        } else {
+          j.m_old = d->m[kk];
+        }
+        j.m = d->m[kk] + nu;
+        j.nu = nu;
+        jobs.j[jobs.n++] = j;
+        sl.push_back(KSlice{kk, nu, j.voff + int64_t(j.m - nu) * j.npw, j.voff + int64_t(j.m - nu) * j.npw});
+      }
+      if (jobs.n) {
+        if (!restart.empty()) restart_basis(p, d, restart, s);
+        QM_HIP(hipMemcpyAsync(d->unconv, d->h_unconv, sizeof(int32_t) * d->nk * nb,
+                              hipMemcpyHostToDevice, s));
+        if (precond == QM_PRECOND_MLP) {
+          mlp_precondition(p, jobs, o->mlp_weights, s);
+        } else {
+          hipLaunchKernelGGL(k_teter, dim3(nb, jobs.n), dim3(256), 0, s, jobs, d->R, d->V, d->unconv,
+                             d->tkin, p->g.kin, d->goff);
+          QM_HIP(hipGetLastError());
+        }
+        if (!orthonormalise(p, d, jobs, s)) throw Error(QM_E_NOT_SPD, "correction block lost rank");
+        timed_apply(p, d, sl, d->V, d->HV, s, d->lowp);
+        rayleigh_ritz(p, d, jobs, s);
+        for (int i = 0; i < jobs.n; ++i) {
+          d->m[jobs.j[i].k] = jobs.j[i].m;
+          d->it[jobs.j[i].k] += 1;
+        }
+      }
+    }
+  }
+  StepResult r;
+  collect(p, d, tol, r);
+  write_outputs(p, d, psi, eig, resnorm, s);
+  if (n_unconv) *n_unconv = r.n_unconv;
+  if (r.nan) throw Error(QM_E_NAN, "non-finite residual norm");
+  return QM_OK;
+}
+
+DavState* dav_of(qm_hpsi_plan* p) { return p->dav; }
+
 }  // namespace qm
 
+using namespace qm;
+
 extern "C" {
-qm_status qm_davidson_step(qm_hpsi_plan* plan, int32_t, void*, double*, double*, int32_t,
-                           const qm_dav_opts*, int32_t*, void*) {
-  if (plan) plan->err = "qm_davidson_step: not available in this build";
-  return QM_E_STATE;
+
+qm_status qm_davidson_step(qm_hpsi_plan* plan, int32_t k, void* psi, double* eig, double* resnorm,
+                           int32_t nbnd, const qm_dav_opts* opts, int32_t* n_unconverged,
+                           void* stream) {
+  if (!plan) return QM_E_ARG;
+  try {
+    return dav_step(plan, k, psi, eig, resnorm, nbnd, opts, n_unconverged,
+                    reinterpret_cast<hipStream_t>(stream));
+  } catch (const Error& e) {
+    plan->err = e.what();
+    if (plan->dav) plan->dav->ready = false;
+    return e.code;
+  } catch (const std::exception& e) {
+    plan->err = e.what();
+    if (plan->dav) plan->dav->ready = false;
+    return QM_E_STATE;
+  }
 }
-qm_status qm_davidson_solve(qm_hpsi_plan* plan, int32_t, void*, double*, double*, int32_t,
-                            const qm_dav_opts*, qm_dav_stats*, void*) {
-  if (plan) plan->err = "qm_davidson_solve: not available in this build";
-  return QM_E_STATE;
+
+qm_status qm_davidson_solve(qm_hpsi_plan* plan, int32_t k, void* psi, double* eig, double* resnorm,
+                            int32_t nbnd, const qm_dav_opts* opts, qm_dav_stats* stats,
+                            void* stream) {
+  if (!plan) return QM_E_ARG;
+  const auto t0 = std::chrono::steady_clock::now();
+  qm_dav_opts o{};
+  if (opts) o = *opts;
+  const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
+  int32_t nun = 0;
+  o.restart = 1;
+  qm_status st = qm_davidson_step(plan, k, psi, eig, resnorm, nbnd, &o, &nun, stream);
+  o.restart = 0;
+  int iter = 0;
+  while (st == QM_OK && nun > 0 && iter < max_iter) {
+    st = qm_davidson_step(plan, k, psi, eig, resnorm, nbnd, &o, &nun, stream);
+    ++iter;
+  }
+  if (stats && plan->dav) {
+    DavState* d = plan->dav;
+    std::memset(stats, 0, sizeof(*stats));
+    int itmax = 0;
+    for (int kk = d->k0; kk < d->k1; ++kk) itmax = std::max(itmax, d->it[kk]);
+    stats->iterations = itmax;
+    stats->converged = (st == QM_OK && nun == 0) ? 1 : 0;
+    stats->n_hpsi_bands = d->n_hpsi;
+    stats->n_hpsi_bands_lowp = d->n_hpsi_lowp;
+    double mr = 0.0;
+    for (int kk = d->k0; kk < d->k1; ++kk)
+      for (int n = 0; n < d->nb; ++n) mr = std::max(mr, d->h_resn[int64_t(kk) * d->nb + n]);
+    stats->max_resnorm = mr;
+    stats->t_hpsi_ms = d->t_hpsi;
+    stats->t_eig_ms = d->t_eig;
+    stats->t_total_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    stats->t_subspace_ms = stats->t_total_ms - d->t_hpsi - d->t_eig;
+  }
+  if (st == QM_OK && nun > 0) {
+    plan->err = "Davidson did not converge within max_iter";
+    return QM_E_NOT_CONVERGED;
+  }
+  return st;
 }
-qm_status qm_mlp_forward(const float*, const float*, float*, int64_t, void*) { return QM_E_STATE; }
-qm_status qm_mlp_loss_grad(const float*, const float*, const float*, const float*, int64_t, float*,
-                           double*, void*) {
-  return QM_E_STATE;
-}
-qm_status qm_mlp_adam(float*, const float*, float*, float*, int32_t, float, float, float, float,
-                      void*) {
-  return QM_E_STATE;
-}
-}
+
+}  // extern "C"

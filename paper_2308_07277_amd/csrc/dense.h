@@ -1,0 +1,37 @@
+// Davidson job descriptors shared by the subspace kernels.
+#pragma once
+#include "qm_internal.h"
+
+namespace qm {
+
+// One active k-point of a Davidson step.
+struct DJob {
+  int32_t k;      // k index (selects the per-k blocks of every buffer)
+  int32_t m;      // basis size after this step's expansion
+  int32_t m_old;  // basis columns whose projected matrix entries are already known
+  int32_t nu;     // new columns in this step (corrections)
+  int32_t npw;
+  int32_t pad;
+  int64_t voff;   // element offset of the k's basis block V/HV ([mb][npw])
+  int64_t xoff;   // element offset of the k's band blocks X/HX/R ([nb][npw])
+};
+struct DJobs {
+  DJob j[kMaxSlices];
+  int32_t n, nb, mb, pad;
+};
+
+}  // namespace qm
+
+namespace qm {
+__global__ void k_hs_fill(DJobs jobs, double2* Hs);
+__global__ void k_hs_copy(DJobs jobs, const double2* Hs, double2* Aw);
+__global__ void k_tridiag(DJobs jobs, double2* Aw, double* dd, double* ee, double2* tau);
+__global__ void k_tridiag_eig(DJobs jobs, const double2* Aw, const double* dd, const double* ee,
+                              const double2* tau, double* theta, double2* Zout, double* yw, double* fw);
+__global__ void k_chol_inv(DJobs jobs, double2* Gm, double2* Wm, int32_t* info);
+__global__ void k_residual(DJobs jobs, const double2* X, const double2* HX, double2* Rr,
+                           const double* theta, const double* kin_all, const int64_t* goff,
+                           double* resn, double* tkin);
+__global__ void k_teter(DJobs jobs, const double2* Rr, double2* V, const int32_t* unconv,
+                        const double* tkin, const double* kin_all, const int64_t* goff);
+}  // namespace qm

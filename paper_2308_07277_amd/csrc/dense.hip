@@ -1,0 +1,502 @@
+// Small dense float64 linear algebra for the Davidson subspace, one workgroup
+// per k-point (all active k-points in one launch):
+//   k_hs_fill     complete the Hermitian projected matrix from its new columns
+//   k_tridiag     Householder reduction of the complex Hermitian projected matrix
+//                 to a real symmetric tridiagonal one (H = I - tau v v^H, with the
+//                 reflector chosen so the off-diagonal comes out real)
+//   k_tridiag_eig lowest nb eigenvalues by Sturm-count bisection, eigenvectors by
+//                 inverse iteration (re-orthogonalised inside clusters of close
+//                 eigenvalues, so degenerate levels get orthonormal vectors), then
+//                 back-transformed through the reflectors
+//   k_chol_inv    Cholesky G = L L^H of a Gram matrix and W = conj(L^-1)^T for the
+//                 CholQR update T <- L^-1 T
+//   k_residual    r = HX - theta X, ||r||, band kinetic energy <x|T|x>
+//   k_teter       Teter-Payne-Allan correction t = K(T(G)/T_n) r, normalised
+// These take the place of the LAPACK / cuSOLVER calls of a library-based Davidson.
+#include "dense.h"
+
+namespace qm {
+
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cmul2(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cadd2(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub2(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+
+// block-wide sum (blockDim.x a multiple of 64, <= 1024); identical result on every thread
+__device__ double block_sum(double v, double* red) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  const int nw = blockDim.x >> 6;
+  for (int i = 0; i < nw; ++i) s += red[i];
+  __syncthreads();
+  return s;
+}
+
+// ---------------------------------------------------------------- Hermitian fill
+__global__ void k_hs_fill(DJobs jobs, double2* __restrict__ Hs) {
+  const DJob& J = jobs.j[blockIdx.y];
+  const int mb = jobs.mb;
+  double2* H = Hs + int64_t(J.k) * mb * mb;
+  const int nnew = J.m - J.m_old;
+  const int64_t total = int64_t(J.m) * nnew;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int i = int(t / nnew), j = J.m_old + int(t % nnew);
+    if (i < J.m_old) {
+      H[int64_t(j) * mb + i] = cconj(H[int64_t(i) * mb + j]);
+    } else if (i < j) {
+      const double2 a = H[int64_t(i) * mb + j], b = H[int64_t(j) * mb + i];
+      const double2 h = make_double2(0.5 * (a.x + b.x), 0.5 * (a.y - b.y));
+      H[int64_t(i) * mb + j] = h;
+      H[int64_t(j) * mb + i] = cconj(h);
+    } else if (i == j) {
+      H[int64_t(i) * mb + i] = make_double2(H[int64_t(i) * mb + i].x, 0.0);
+    }
+  }
+}
+
+// copy Hs[0:m][0:m] -> Aw (eigensolver workspace)
+__global__ void k_hs_copy(DJobs jobs, const double2* __restrict__ Hs, double2* __restrict__ Aw) {
+  const DJob& J = jobs.j[blockIdx.y];
+  const int mb = jobs.mb;
+  const int64_t total = int64_t(J.m) * J.m;
+  const int64_t base = int64_t(J.k) * mb * mb;
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const int i = int(t / J.m), j = int(t % J.m);
+    Aw[base + int64_t(i) * mb + j] = Hs[base + int64_t(i) * mb + j];
+  }
+}
+
+// ---------------------------------------------------------------- tridiagonalisation
+__global__ void __launch_bounds__(1024) k_tridiag(DJobs jobs, double2* __restrict__ Aw,
+                                                  double* __restrict__ dd, double* __restrict__ ee,
+                                                  double2* __restrict__ tau) {
+  extern __shared__ double2 sh[];
+  const DJob& J = jobs.j[blockIdx.x];
+  const int mb = jobs.mb, m = J.m;
+  double2* A = Aw + int64_t(J.k) * mb * mb;
+  double* d = dd + int64_t(J.k) * mb;
+  double* e = ee + int64_t(J.k) * mb;
+  double2* tk = tau + int64_t(J.k) * mb;
+  double2* v = sh;       // [mb]
+  double2* w = sh + mb;  // [mb]
+  __shared__ double red[16];
+  __shared__ double2 s_tau, s_scale;
+  __shared__ double s_beta;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  for (int j = 0; j < m - 1; ++j) {
+    const int n = m - j - 1;
+    double xs = 0.0;
+    for (int r = j + 2 + tid; r < m; r += blockDim.x) {
+      const double2 a = A[int64_t(r) * mb + j];
+      xs += a.x * a.x + a.y * a.y;
+    }
+    xs = block_sum(xs, red);
+    if (tid == 0) {
+      const double2 alpha = A[int64_t(j + 1) * mb + j];
+      if (xs == 0.0 && alpha.y == 0.0) {
+        s_tau = make_double2(0.0, 0.0);
+        s_beta = alpha.x;
+        s_scale = make_double2(0.0, 0.0);
+      } else {
+        double beta = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xs);
+        if (alpha.x >= 0.0) beta = -beta;
+        s_tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+        const double2 den = make_double2(alpha.x - beta, alpha.y);
+        const double dn = den.x * den.x + den.y * den.y;
+        s_scale = make_double2(den.x / dn, -den.y / dn);
+        s_beta = beta;
+      }
+      d[j] = A[int64_t(j) * mb + j].x;
+      e[j] = s_beta;
+      tk[j] = s_tau;
+    }
+    __syncthreads();
+    const double2 t = s_tau;
+    if (t.x == 0.0 && t.y == 0.0) continue;  // uniform branch
+    for (int r = j + 1 + tid; r < m; r += blockDim.x) {
+      const double2 x = r == j + 1 ? make_double2(1.0, 0.0) : cmul2(A[int64_t(r) * mb + j], s_scale);
+      v[r - j - 1] = x;
+      if (r > j + 1) A[int64_t(r) * mb + j] = x;
+    }
+    __syncthreads();
+    // p = tau A_sub v, one wave per row
+    for (int rr = wave; rr < n; rr += nw) {
+      const double2* row = A + int64_t(j + 1 + rr) * mb + (j + 1);
+      double sr = 0.0, si = 0.0;
+      for (int c = lane; c < n; c += 64) {
+        const double2 a = row[c], b = v[c];
+        sr += a.x * b.x - a.y * b.y;
+        si += a.x * b.y + a.y * b.x;
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        sr += __shfl_down(sr, o, 64);
+        si += __shfl_down(si, o, 64);
+      }
+      if (lane == 0) w[rr] = cmul2(t, make_double2(sr, si));
+    }
+    __syncthreads();
+    double pr = 0.0, pi = 0.0;   // p^H v
+    for (int c = tid; c < n; c += blockDim.x) {
+      const double2 pc = w[c], vc = v[c];
+      pr += pc.x * vc.x + pc.y * vc.y;
+      pi += pc.x * vc.y - pc.y * vc.x;
+    }
+    pr = block_sum(pr, red);
+    pi = block_sum(pi, red);
+    const double2 aw = cmul2(make_double2(-0.5 * t.x, -0.5 * t.y), make_double2(pr, pi));
+    for (int c = tid; c < n; c += blockDim.x) w[c] = cadd2(w[c], cmul2(aw, v[c]));
+    __syncthreads();
+    for (int rr = wave; rr < n; rr += nw) {
+      double2* row = A + int64_t(j + 1 + rr) * mb + (j + 1);
+      const double2 vr = v[rr], wr = w[rr];
+      for (int c = lane; c < n; c += 64) {
+        const double2 vc = v[c], wc = w[c];
+        double2 a = row[c];
+        a = csub2(a, cmul2(vr, cconj(wc)));
+        a = csub2(a, cmul2(wr, cconj(vc)));
+        row[c] = a;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    d[m - 1] = A[int64_t(m - 1) * mb + (m - 1)].x;
+    e[m - 1] = 0.0;
+    tk[m - 1] = make_double2(0.0, 0.0);
+  }
+}
+
+// ---------------------------------------------------------------- tridiagonal eigenpairs
+__device__ int sturm_count(const double* d, const double* e, int m, double x, double pivmin) {
+  int c = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  if (q < 0) ++c;
+  for (int i = 1; i < m; ++i) {
+    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0) ++c;
+  }
+  return c;
+}
+
+// LU with partial pivoting of the tridiagonal T - lam I (rows swapped pairwise).
+// U has diagonal D, superdiagonals U1, U2; L has multipliers M; P[i] = 1 if rows i, i+1 swapped.
+__device__ void trid_lu(const double* d, const double* e, int m, double lam, double tiny,
+                        double* D, double* U1, double* U2, double* M, double* P) {
+  for (int i = 0; i < m; ++i) {
+    D[i] = d[i] - lam;
+    U1[i] = i < m - 1 ? e[i] : 0.0;
+    M[i] = i < m - 1 ? e[i] : 0.0;   // subdiagonal before elimination
+    U2[i] = 0.0;
+    P[i] = 0.0;
+  }
+  for (int i = 0; i < m - 1; ++i) {
+    if (fabs(D[i]) >= fabs(M[i])) {
+      const double f = D[i] != 0.0 ? M[i] / D[i] : 0.0;
+      M[i] = f;
+      D[i + 1] -= f * U1[i];
+    } else {
+      const double f = D[i] / M[i];
+      D[i] = M[i];
+      M[i] = f;
+      const double t = U1[i];
+      U1[i] = D[i + 1];
+      D[i + 1] = t - f * D[i + 1];
+      if (i < m - 2) {
+        U2[i] = U1[i + 1];
+        U1[i + 1] = -f * U1[i + 1];
+      }
+      P[i] = 1.0;
+    }
+  }
+  for (int i = 0; i < m; ++i)
+    if (fabs(D[i]) < tiny) D[i] = D[i] < 0.0 ? -tiny : tiny;
+}
+
+__device__ void trid_solve(int m, const double* D, const double* U1, const double* U2,
+                           const double* M, const double* P, double* b) {
+  for (int i = 0; i < m - 1; ++i) {
+    if (P[i] == 0.0) {
+      b[i + 1] -= M[i] * b[i];
+    } else {
+      const double t = b[i];
+      b[i] = b[i + 1];
+      b[i + 1] = t - M[i] * b[i];
+    }
+  }
+  b[m - 1] /= D[m - 1];
+  if (m > 1) b[m - 2] = (b[m - 2] - U1[m - 2] * b[m - 1]) / D[m - 2];
+  for (int i = m - 3; i >= 0; --i) b[i] = (b[i] - U1[i] * b[i + 1] - U2[i] * b[i + 2]) / D[i];
+}
+
+// theta[k][0..nb) ascending; Z[k][i][n] (row i < m, column n < nb).
+// yw: [k][nb][mb] real eigenvectors of T; fw: [k][nb][5][mb] LU workspace.
+__global__ void __launch_bounds__(1024) k_tridiag_eig(DJobs jobs, const double2* __restrict__ Aw,
+                                                      const double* __restrict__ dd,
+                                                      const double* __restrict__ ee,
+                                                      const double2* __restrict__ tau,
+                                                      double* __restrict__ theta,
+                                                      double2* __restrict__ Zout,
+                                                      double* __restrict__ yw,
+                                                      double* __restrict__ fw) {
+  extern __shared__ double2 sh[];  // [mb] reflector staging
+  const DJob& J = jobs.j[blockIdx.x];
+  const int mb = jobs.mb, nb = jobs.nb, m = J.m;
+  const double2* A = Aw + int64_t(J.k) * mb * mb;
+  const double* d = dd + int64_t(J.k) * mb;
+  const double* e = ee + int64_t(J.k) * mb;
+  const double2* tk = tau + int64_t(J.k) * mb;
+  double* th = theta + int64_t(J.k) * mb;
+  double2* Z = Zout + int64_t(J.k) * mb * nb;
+  double* Y = yw + int64_t(J.k) * nb * mb;
+  double* F = fw + int64_t(J.k) * nb * 5 * mb;
+  __shared__ double s_lo, s_hi, s_norm;
+  __shared__ int s_cl[1025];
+  __shared__ int s_ncl;
+  const int tid = threadIdx.x;
+  const int nwant = min(nb, m);
+  if (tid == 0) {
+    double lo = 1e300, hi = -1e300, nrm = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < m - 1 ? fabs(e[i]) : 0.0);
+      lo = fmin(lo, d[i] - r);
+      hi = fmax(hi, d[i] + r);
+      nrm = fmax(nrm, fabs(d[i]) + r);
+    }
+    s_lo = lo;
+    s_hi = hi;
+    s_norm = fmax(nrm, 1e-300);
+  }
+  __syncthreads();
+  const double eps = 2.220446049250313e-16;
+  const double nrm = s_norm;
+  const double pivmin = fmax(1e-290, eps * eps * nrm * nrm * 1e-6);
+  for (int n = tid; n < nwant; n += blockDim.x) {
+    double lo = s_lo - 4 * eps * nrm, hi = s_hi + 4 * eps * nrm;
+    for (int it = 0; it < 256; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (mid <= lo || mid >= hi) break;
+      if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi))) break;
+      if (sturm_count(d, e, m, mid, pivmin) <= n) lo = mid;
+      else hi = mid;
+    }
+    th[n] = 0.5 * (lo + hi);
+  }
+  __syncthreads();
+  const double ortol = 1e-5 * nrm;  // inter-cluster orthogonality ~ eps / 1e-5
+  if (tid == 0) {
+    int nc = 0;
+    s_cl[nc++] = 0;
+    for (int n = 1; n < nwant; ++n)
+      if (th[n] - th[n - 1] > ortol && nc < 1024) s_cl[nc++] = n;
+    s_cl[nc] = nwant;
+    s_ncl = nc;
+  }
+  __syncthreads();
+  const double tiny = eps * nrm;
+  for (int c = tid; c < s_ncl; c += blockDim.x) {
+    const int n0 = s_cl[c], n1 = s_cl[c + 1];
+    double prev = -1e300;
+    for (int n = n0; n < n1; ++n) {
+      double lam = th[n];
+      if (n > n0 && lam - prev < 10.0 * tiny) lam = prev + 10.0 * tiny;
+      prev = lam;
+      double* y = Y + int64_t(n) * mb;
+      double* D = F + (int64_t(n) * 5 + 0) * mb;
+      double* U1 = D + mb;
+      double* U2 = U1 + mb;
+      double* M = U2 + mb;
+      double* P = M + mb;
+      trid_lu(d, e, m, lam, tiny, D, U1, U2, M, P);
+      // deterministic start vector with every component nonzero
+      for (int i = 0; i < m; ++i) y[i] = 1.0 + 0.5 * sin(0.7 * double(i + 1) + 1.3 * double(n + 1));
+      for (int it = 0; it < 3; ++it) {
+        trid_solve(m, D, U1, U2, M, P, y);
+        for (int q = n0; q < n; ++q) {
+          const double* yq = Y + int64_t(q) * mb;
+          double s = 0.0;
+          for (int i = 0; i < m; ++i) s += y[i] * yq[i];
+          for (int i = 0; i < m; ++i) y[i] -= s * yq[i];
+        }
+        double s = 0.0;
+        for (int i = 0; i < m; ++i) s += y[i] * y[i];
+        s = 1.0 / sqrt(s);
+        for (int i = 0; i < m; ++i) y[i] *= s;
+      }
+    }
+  }
+  __syncthreads();
+  // Z = Q y: start from y, apply H_{m-2} ... H_0
+  for (int64_t t = tid; t < int64_t(m) * nwant; t += blockDim.x) {
+    const int i = int(t / nwant), n = int(t % nwant);
+    Z[int64_t(i) * nb + n] = make_double2(Y[int64_t(n) * mb + i], 0.0);
+  }
+  __syncthreads();
+  double2* vj = sh;
+  for (int j = m - 2; j >= 0; --j) {
+    const double2 t = tk[j];
+    if (t.x == 0.0 && t.y == 0.0) continue;  // uniform
+    for (int r = j + 1 + tid; r < m; r += blockDim.x)
+      vj[r] = r == j + 1 ? make_double2(1.0, 0.0) : A[int64_t(r) * mb + j];
+    __syncthreads();
+    for (int n = tid; n < nwant; n += blockDim.x) {
+      double sr = 0.0, si = 0.0;
+      for (int r = j + 1; r < m; ++r) {
+        const double2 vv = vj[r], z = Z[int64_t(r) * nb + n];
+        sr += vv.x * z.x + vv.y * z.y;   // conj(v) z
+        si += vv.x * z.y - vv.y * z.x;
+      }
+      const double2 f = cmul2(t, make_double2(sr, si));
+      for (int r = j + 1; r < m; ++r) Z[int64_t(r) * nb + n] = csub2(Z[int64_t(r) * nb + n], cmul2(vj[r], f));
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- Cholesky + inverse
+// G [k][nb][nb] (leading nu x nu, Hermitian PD) -> W[k][i][n] = conj(Linv[n][i]);
+// info[k] = 0 on success, j+1 if pivot j failed.  Right-looking, one workgroup.
+__global__ void __launch_bounds__(1024) k_chol_inv(DJobs jobs, double2* __restrict__ Gm,
+                                                   double2* __restrict__ Wm, int32_t* __restrict__ info) {
+  const DJob& J = jobs.j[blockIdx.x];
+  const int nb = jobs.nb, n = J.nu;
+  double2* G = Gm + int64_t(J.k) * nb * nb;
+  double2* W = Wm + int64_t(J.k) * nb * nb;
+  __shared__ int s_fail;
+  __shared__ double s_dmax;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    s_fail = 0;
+    double mx = 0.0;
+    for (int i = 0; i < n; ++i) mx = fmax(mx, G[int64_t(i) * nb + i].x);
+    s_dmax = mx;
+  }
+  __syncthreads();
+  for (int j = 0; j < n; ++j) {
+    __shared__ double s_piv;
+    if (tid == 0) {
+      const double djj = G[int64_t(j) * nb + j].x;
+      if (!(djj > 1e-14 * s_dmax) || !(djj < 1e300)) s_fail = j + 1;
+      s_piv = s_fail ? 1.0 : sqrt(djj);
+      G[int64_t(j) * nb + j] = make_double2(s_piv, 0.0);
+    }
+    __syncthreads();
+    if (s_fail) break;
+    const double inv = 1.0 / s_piv;
+    for (int r = j + 1 + tid; r < n; r += blockDim.x) {
+      const double2 a = G[int64_t(r) * nb + j];
+      G[int64_t(r) * nb + j] = make_double2(a.x * inv, a.y * inv);
+    }
+    __syncthreads();
+    // trailing lower update: G[r][c] -= L[r][j] conj(L[c][j]) for c <= r
+    const int nn = n - j - 1;
+    for (int64_t t = tid; t < int64_t(nn) * nn; t += blockDim.x) {
+      const int r = j + 1 + int(t / nn), c = j + 1 + int(t % nn);
+      if (c > r) continue;
+      const double2 lr = G[int64_t(r) * nb + j], lc = G[int64_t(c) * nb + j];
+      G[int64_t(r) * nb + c] = csub2(G[int64_t(r) * nb + c], cmul2(lr, cconj(lc)));
+    }
+    __syncthreads();
+  }
+  if (tid == 0) info[J.k] = s_fail;
+  if (s_fail) return;
+  // Linv column c by forward substitution; W[i][c'] = conj(Linv[c'][i])  (i <= c')
+  for (int c = tid; c < n; c += blockDim.x) {
+    // x = Linv[:, c]: x[r] = 0 for r < c
+    W[int64_t(c) * nb + c] = make_double2(1.0 / G[int64_t(c) * nb + c].x, 0.0);  // conj of real
+    for (int r = c + 1; r < n; ++r) {
+      double sr = 0.0, si = 0.0;
+      for (int q = c; q < r; ++q) {
+        const double2 l = G[int64_t(r) * nb + q];
+        const double2 x = cconj(W[int64_t(c) * nb + q]);   // Linv[q][c] = conj(W[c][q])
+        sr += l.x * x.x - l.y * x.y;
+        si += l.x * x.y + l.y * x.x;
+      }
+      const double lrr = G[int64_t(r) * nb + r].x;
+      // Linv[r][c] = -s / L[r][r]; W[c][r] = conj(Linv[r][c])
+      W[int64_t(c) * nb + r] = make_double2(-sr / lrr, si / lrr);
+    }
+    for (int r = 0; r < c; ++r) W[int64_t(c) * nb + r] = make_double2(0.0, 0.0);
+  }
+}
+
+// ---------------------------------------------------------------- residuals
+// One workgroup per (job, band): r = HX - theta X into R, ||r||, <x|T|x>/<x|x>.
+__global__ void __launch_bounds__(256) k_residual(DJobs jobs, const double2* __restrict__ X,
+                                                  const double2* __restrict__ HX,
+                                                  double2* __restrict__ Rr,
+                                                  const double* __restrict__ theta,
+                                                  const double* __restrict__ kin_all,
+                                                  const int64_t* __restrict__ goff,
+                                                  double* __restrict__ resn,
+                                                  double* __restrict__ tkin) {
+  __shared__ double red[16];
+  const DJob& J = jobs.j[blockIdx.y];
+  const int nb = jobs.nb, n = blockIdx.x;
+  if (n >= nb) return;
+  const double th = theta[int64_t(J.k) * jobs.mb + n];
+  const int64_t off = J.xoff + int64_t(n) * J.npw;
+  const double* kin = kin_all + goff[J.k];
+  double rr = 0.0, xt = 0.0, xx = 0.0;
+  for (int g = threadIdx.x; g < J.npw; g += blockDim.x) {
+    const double2 x = X[off + g], h = HX[off + g];
+    const double2 r = make_double2(h.x - th * x.x, h.y - th * x.y);
+    Rr[off + g] = r;
+    rr += r.x * r.x + r.y * r.y;
+    const double p = x.x * x.x + x.y * x.y;
+    xx += p;
+    xt += p * kin[g];
+  }
+  rr = block_sum(rr, red);
+  xt = block_sum(xt, red);
+  xx = block_sum(xx, red);
+  if (threadIdx.x == 0) {
+    resn[int64_t(J.k) * nb + n] = sqrt(rr);
+    tkin[int64_t(J.k) * nb + n] = xt / xx;
+  }
+}
+
+// One workgroup per (job, j < nu): band n = unconv[k][j]; t = K(kin/T_n) r_n normalised,
+// written to row (m - nu + j) of the basis block V.
+__global__ void __launch_bounds__(256) k_teter(DJobs jobs, const double2* __restrict__ Rr,
+                                               double2* __restrict__ V,
+                                               const int32_t* __restrict__ unconv,
+                                               const double* __restrict__ tkin,
+                                               const double* __restrict__ kin_all,
+                                               const int64_t* __restrict__ goff) {
+  __shared__ double red[16];
+  const DJob& J = jobs.j[blockIdx.y];
+  const int nb = jobs.nb, j = blockIdx.x;
+  if (j >= J.nu) return;
+  const int n = unconv[int64_t(J.k) * nb + j];
+  const double tn = tkin[int64_t(J.k) * nb + n];
+  const double* kin = kin_all + goff[J.k];
+  const double2* r = Rr + J.xoff + int64_t(n) * J.npw;
+  double2* t = V + J.voff + int64_t(J.m - J.nu + j) * J.npw;
+  double ss = 0.0;
+  for (int g = threadIdx.x; g < J.npw; g += blockDim.x) {
+    const double x = kin[g] / tn;
+    const double num = 27.0 + x * (18.0 + x * (12.0 + 8.0 * x));
+    const double k = num / (num + 16.0 * x * x * x * x);
+    const double2 v = make_double2(k * r[g].x, k * r[g].y);
+    t[g] = v;
+    ss += v.x * v.x + v.y * v.y;
+  }
+  ss = block_sum(ss, red);
+  const double s = 1.0 / sqrt(ss);
+  for (int g = threadIdx.x; g < J.npw; g += blockDim.x) {
+    const double2 v = t[g];
+    t[g] = make_double2(v.x * s, v.y * s);
+  }
+}
+
+}  // namespace qm

@@ -4,8 +4,10 @@
 
 namespace qm {
 
-void launch_local_f64(qm_hpsi_plan*, int, int, int, const void*, void*, hipStream_t, StageEvents*);
-void launch_local_f32(qm_hpsi_plan*, int, int, int, const void*, void*, hipStream_t, StageEvents*);
+void launch_local_f64(qm_hpsi_plan*, const std::vector<KSlice>&, const void*, void*, hipStream_t,
+                      StageEvents*);
+void launch_local_f32(qm_hpsi_plan*, const std::vector<KSlice>&, const void*, void*, hipStream_t,
+                      StageEvents*);
 
 bool fft_len_supported(int n) {
   switch (n) {
@@ -36,12 +38,35 @@ int fft_split_r2(int n) {
   }
 }
 
-void launch_hpsi_local(qm_hpsi_plan* p, int k0, int k1, int nbnd, const void* psi, void* hpsi,
+void launch_hpsi_local(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
                        hipStream_t s, bool fp32, StageEvents* ev) {
   if (fp32)
-    launch_local_f32(p, k0, k1, nbnd, psi, hpsi, s, ev);
+    launch_local_f32(p, sl, psi, hpsi, s, ev);
   else
-    launch_local_f64(p, k0, k1, nbnd, psi, hpsi, s, ev);
+    launch_local_f64(p, sl, psi, hpsi, s, ev);
+}
+
+std::vector<KSlice> contiguous_slices(const qm_hpsi_plan* p, int k0, int k1, int nbnd) {
+  std::vector<KSlice> out;
+  const int64_t g0 = p->kinfo[k0].g_off;
+  for (int k = k0; k < k1; ++k) {
+    const int64_t off = int64_t(nbnd) * (p->kinfo[k].g_off - g0);
+    out.push_back(KSlice{k, nbnd, off, off});
+  }
+  return out;
+}
+
+void apply_h_slices(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
+                    hipStream_t s, qm_prec prec, StageEvents* ev) {
+  for (size_t b = 0; b < sl.size(); b += kMaxSlices) {
+    std::vector<KSlice> chunk(sl.begin() + b, sl.begin() + std::min(sl.size(), b + kMaxSlices));
+    std::vector<KSlice> nz;
+    for (const KSlice& x : chunk)
+      if (x.nb > 0) nz.push_back(x);
+    if (nz.empty()) continue;
+    launch_hpsi_local(p, nz, psi, hpsi, s, prec != QM_PREC_FP64, ev);
+    launch_nonlocal(p, nz, psi, hpsi, s, prec, ev);
+  }
 }
 
 // V(r) [i1][i2][i3] (float64, C order) -> plan layout [slot][i1][i2] scaled by 1/N_r, where

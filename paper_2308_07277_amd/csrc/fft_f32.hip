@@ -1,8 +1,8 @@
 // float32 instantiation of the local-part kernels.
 #include "fft_launch.h"
 namespace qm {
-void launch_local_f32(qm_hpsi_plan* p, int k0, int k1, int nbnd, const void* psi, void* hpsi,
-                      hipStream_t s, StageEvents* ev) {
-  launch_local_t<float>(p, k0, k1, nbnd, psi, hpsi, s, ev);
+void launch_local_f32(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi,
+                      void* hpsi, hipStream_t s, StageEvents* ev) {
+  launch_local_t<float>(p, sl, psi, hpsi, s, ev);
 }
 }  // namespace qm

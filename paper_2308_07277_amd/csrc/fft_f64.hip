@@ -1,8 +1,8 @@
 // float64 instantiation of the local-part kernels.
 #include "fft_launch.h"
 namespace qm {
-void launch_local_f64(qm_hpsi_plan* p, int k0, int k1, int nbnd, const void* psi, void* hpsi,
-                      hipStream_t s, StageEvents* ev) {
-  launch_local_t<double>(p, k0, k1, nbnd, psi, hpsi, s, ev);
+void launch_local_f64(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi,
+                      void* hpsi, hipStream_t s, StageEvents* ev) {
+  launch_local_t<double>(p, sl, psi, hpsi, s, ev);
 }
 }  // namespace qm

@@ -30,9 +30,12 @@ namespace qm {
 
 struct LocalArgs {
   const KInfo* kinfo;
-  int32_t k0, k1, nbnd, N3;
-  const double2* psi;       // c128, block of k0
-  double2* hpsi;            // c128
+  KSlice sl[kMaxSlices];    // k-point band blocks of this launch
+  int32_t blk_z[kMaxSlices + 1];  // prefix of nb * ntile over slices (z kernels)
+  int32_t pair0[kMaxSlices + 1];  // prefix of nb over slices (xy kernel)
+  int32_t nsl, N3;
+  const double2* psi;       // c128 base
+  double2* hpsi;            // c128 base
   void* sbuf;               // cplx<R>
   const int32_t* ent_g;
   const int32_t* ent_sz;
@@ -43,19 +46,16 @@ struct LocalArgs {
   const void* vplan;        // R [slot][i1][i2]
   const double2* tw_z;      // exp(+2 pi i m / N3), m < N3
   const double2* tw_x;      // exp(+2 pi i m / N1)
-  int64_t g_off0;           // g_off of k0
   int32_t ts;               // sticks per tile
   int32_t nax_stride;       // row stride of the xy-plane buffer (elements)
 };
 
-__device__ __forceinline__ int locate_tile_block(const KInfo* ki, int k0, int k1, int nbnd, int& bid) {
-  int k = k0;
-  for (; k < k1 - 1; ++k) {
-    int nb = nbnd * ki[k].ntile;
-    if (bid < nb) break;
-    bid -= nb;
-  }
-  return k;
+// slice holding z-kernel block bid; bid becomes the block index within the slice
+__device__ __forceinline__ int locate_tile_block(const LocalArgs& a, int& bid) {
+  int s = 0;
+  while (s < a.nsl - 1 && bid >= a.blk_z[s + 1]) ++s;
+  bid -= a.blk_z[s];
+  return s;
 }
 
 // ------------------------------------------------------------------ z inverse + scatter
@@ -66,8 +66,9 @@ __global__ void __launch_bounds__(TS * Split<N3>::R2) k_zinv(LocalArgs a) {
   __shared__ cplx<R> tw[N3];
   const int tid = threadIdx.x;
   int bid = blockIdx.x;
-  const int k = locate_tile_block(a.kinfo, a.k0, a.k1, a.nbnd, bid);
-  const KInfo ki = a.kinfo[k];
+  const int si = locate_tile_block(a, bid);
+  const KSlice& ks = a.sl[si];
+  const KInfo ki = a.kinfo[ks.k];
   const int band = bid / ki.ntile, t = bid - band * ki.ntile;
   const int s0 = t * TS;
   const int cnt = min(TS, ki.nstick - s0);
@@ -79,7 +80,7 @@ __global__ void __launch_bounds__(TS * Split<N3>::R2) k_zinv(LocalArgs a) {
   __syncthreads();
   const int32_t* tp = a.tile_ptr + ki.tile_off;
   const int e0 = tp[t], e1 = tp[t + 1];
-  const double2* psi_b = a.psi + int64_t(a.nbnd) * (ki.g_off - a.g_off0) + int64_t(band) * ki.npw;
+  const double2* psi_b = a.psi + ks.psi_off + int64_t(band) * ki.npw;
   const int32_t* eg = a.ent_g + ki.g_off;
   const int32_t* esz = a.ent_sz + ki.g_off;
   for (int e = e0 + tid; e < e1; e += NT) {
@@ -136,7 +137,9 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
     kb = bid / N3;
     p = bid - kb * N3;
   }
-  const int k = a.k0 + kb / a.nbnd, band = kb - (kb / a.nbnd) * a.nbnd;
+  int si = 0;
+  while (si < a.nsl - 1 && kb >= a.pair0[si + 1]) ++si;
+  const int k = a.sl[si].k, band = kb - a.pair0[si];
   const KInfo ki = a.kinfo[k];
   const int nax = ki.nax;
   for (int i = tid; i < NX; i += 256) {
@@ -275,8 +278,9 @@ __global__ void __launch_bounds__(TS * Split<N3>::R2) k_zfwd(LocalArgs a) {
   __shared__ cplx<R> tw[N3];
   const int tid = threadIdx.x;
   int bid = blockIdx.x;
-  const int k = locate_tile_block(a.kinfo, a.k0, a.k1, a.nbnd, bid);
-  const KInfo ki = a.kinfo[k];
+  const int si = locate_tile_block(a, bid);
+  const KSlice& ks = a.sl[si];
+  const KInfo ki = a.kinfo[ks.k];
   const int band = bid / ki.ntile, t = bid - band * ki.ntile;
   const int s0 = t * TS;
   const int cnt = min(TS, ki.nstick - s0);
@@ -314,9 +318,8 @@ __global__ void __launch_bounds__(TS * Split<N3>::R2) k_zfwd(LocalArgs a) {
   __syncthreads();
   const int32_t* tp = a.tile_ptr + ki.tile_off;
   const int e0 = tp[t], e1 = tp[t + 1];
-  const int64_t boff = int64_t(a.nbnd) * (ki.g_off - a.g_off0) + int64_t(band) * ki.npw;
-  const double2* psi_b = a.psi + boff;
-  double2* out_b = a.hpsi + boff;
+  const double2* psi_b = a.psi + ks.psi_off + int64_t(band) * ki.npw;
+  double2* out_b = a.hpsi + ks.hpsi_off + int64_t(band) * ki.npw;
   const int32_t* eg = a.ent_g + ki.g_off;
   const int32_t* esz = a.ent_sz + ki.g_off;
   const double* kin = a.kin + ki.g_off;

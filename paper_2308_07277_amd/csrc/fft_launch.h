@@ -7,14 +7,23 @@ namespace qm {
 constexpr int kZTile = 32;  // sticks per z-kernel tile (the plan's tile tables use it)
 
 template <typename R>
-void launch_local_t(qm_hpsi_plan* p, int k0, int k1, int nbnd, const void* psi, void* hpsi,
+void launch_local_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
                     hipStream_t s, StageEvents* ev) {
   LocalArgs a{};
+  QM_REQUIRE(!sl.empty() && sl.size() <= size_t(kMaxSlices), QM_E_STATE, "bad slice count");
   a.kinfo = p->g.kinfo;
-  a.k0 = k0;
-  a.k1 = k1;
-  a.nbnd = nbnd;
+  a.nsl = int32_t(sl.size());
   a.N3 = p->N3;
+  int64_t nblk_z = 0, npair = 0;
+  for (size_t i = 0; i < sl.size(); ++i) {
+    a.sl[i] = sl[i];
+    a.blk_z[i] = int32_t(nblk_z);
+    a.pair0[i] = int32_t(npair);
+    nblk_z += int64_t(sl[i].nb) * p->kinfo[sl[i].k].ntile;
+    npair += sl[i].nb;
+  }
+  a.blk_z[sl.size()] = int32_t(nblk_z);
+  a.pair0[sl.size()] = int32_t(npair);
   a.psi = reinterpret_cast<const double2*>(psi);
   a.hpsi = reinterpret_cast<double2*>(hpsi);
   a.sbuf = p->sbuf;
@@ -27,12 +36,9 @@ void launch_local_t(qm_hpsi_plan* p, int k0, int k1, int nbnd, const void* psi, 
   a.vplan = sizeof(R) == 8 ? p->vplan64 : p->vplan32;
   a.tw_z = p->tw_z;
   a.tw_x = p->tw_x;
-  a.g_off0 = p->kinfo[k0].g_off;
   a.ts = kZTile;
   a.nax_stride = p->nax_max | 1;
-  int64_t nblk_z = 0;
-  for (int k = k0; k < k1; ++k) nblk_z += int64_t(nbnd) * p->kinfo[k].ntile;
-  const int64_t nblk_xy = int64_t(nbnd) * (k1 - k0) * p->N3;
+  const int64_t nblk_xy = npair * p->N3;
   QM_REQUIRE(nblk_z < (int64_t(1) << 31) && nblk_xy < (int64_t(1) << 31), QM_E_SHAPE,
              "launch too large");
   const int NX = p->N1;

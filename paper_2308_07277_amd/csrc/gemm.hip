@@ -287,7 +287,10 @@ void zgemm_cn_batched(const std::vector<GemmCN>& probs, double alpha, double bet
       tiles += int64_t((g.M + BT - 1) / BT) * ((g.N + BT - 1) / BT);
       maxK = std::max<int64_t>(maxK, g.K);
     }
-    const int nsplit = choose_splits(tiles, maxK);
+    int64_t mn = 0;
+    for (const GemmCN& g : sub) mn += int64_t(g.M) * g.N;
+    int nsplit = choose_splits(tiles, maxK);
+    while (nsplit > 1 && int64_t(nsplit) * mn * int64_t(sizeof(cplx<double>)) > work_bytes) nsplit /= 2;
     int64_t blk = 0, woff = 0, e0 = 0;
     for (size_t i = 0; i < n; ++i) {
       const GemmCN& g = sub[i];

@@ -28,40 +28,44 @@ __global__ void k_apply_d(const double2* __restrict__ P, double2* __restrict__ Q
   }
 }
 
-void launch_nonlocal_fp64(qm_hpsi_plan* p, int k0, int k1, int nbnd, const void* psi, void* hpsi,
-                          hipStream_t s, StageEvents* ev) {
+void launch_nonlocal_fp64(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi,
+                          void* hpsi, hipStream_t s, StageEvents* ev) {
   if (p->nproj == 0) return;
   const int np = p->nproj;
   double2* P = reinterpret_cast<double2*>(p->proj_q);
   double2* Q = P + int64_t(p->nk) * np * p->nbnd_max;
   std::vector<GemmCN> cn;
   std::vector<GemmEX> ex;
-  const int64_t g0 = p->kinfo[k0].g_off;
-  for (int k = k0; k < k1; ++k) {
-    const KInfo& ki = p->kinfo[k];
+  int64_t off = 0;
+  for (const KSlice& x : sl) {
+    const KInfo& ki = p->kinfo[x.k];
     const double2* bk = reinterpret_cast<const double2*>(p->beta64) + ki.beta_off;
-    const double2* pk = reinterpret_cast<const double2*>(psi) + int64_t(nbnd) * (ki.g_off - g0);
-    double2* hk = reinterpret_cast<double2*>(hpsi) + int64_t(nbnd) * (ki.g_off - g0);
-    double2* Pk = P + int64_t(k - k0) * np * nbnd;
-    double2* Qk = Q + int64_t(k - k0) * np * nbnd;
-    cn.push_back(GemmCN{bk, pk, Pk, np, nbnd, ki.npw, ki.npw, ki.npw, nbnd});
-    ex.push_back(GemmEX{Qk, bk, hk, nbnd, ki.npw, np, nbnd, ki.npw, ki.npw});
+    const double2* pk = reinterpret_cast<const double2*>(psi) + x.psi_off;
+    double2* hk = reinterpret_cast<double2*>(hpsi) + x.hpsi_off;
+    cn.push_back(GemmCN{bk, pk, P + off, np, x.nb, ki.npw, ki.npw, ki.npw, x.nb});
+    ex.push_back(GemmEX{Q + off, bk, hk, x.nb, ki.npw, np, x.nb, ki.npw, ki.npw});
+    off += int64_t(np) * x.nb;
   }
   zgemm_cn_batched(cn, 1.0, 0.0, p->proj_part, p->proj_part_bytes, s, ev, 3);
-  const int64_t total = int64_t(k1 - k0) * np * nbnd;
-  const int blocks = int(std::min<int64_t>((total + 255) / 256, 16384));
-  hipLaunchKernelGGL(k_apply_d, dim3(blocks), dim3(256), 0, s, P, Q, p->dmat, p->drange, np, nbnd,
-                     total);
-  QM_HIP(hipGetLastError());
+  // D acts on each slice's [np][nb] block; blocks are packed back to back
+  int64_t base = 0;
+  for (const KSlice& x : sl) {
+    const int64_t total = int64_t(np) * x.nb;
+    const int blocks = int(std::min<int64_t>((total + 255) / 256, 16384));
+    hipLaunchKernelGGL(k_apply_d, dim3(blocks), dim3(256), 0, s, P + base, Q + base, p->dmat,
+                       p->drange, np, x.nb, total);
+    QM_HIP(hipGetLastError());
+    base += total;
+  }
   if (ev) ev->mark(5);
   zgemm_ex_batched(ex, 1.0, 1.0, s);
   if (ev) ev->mark(6);
 }
 
-void launch_nonlocal(qm_hpsi_plan* p, int k0, int k1, int nbnd, const void* psi, void* hpsi,
+void launch_nonlocal(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
                      hipStream_t s, qm_prec prec, StageEvents* ev) {
   (void)prec;
-  launch_nonlocal_fp64(p, k0, k1, nbnd, psi, hpsi, s, ev);
+  launch_nonlocal_fp64(p, sl, psi, hpsi, s, ev);
 }
 
 void convert_beta(qm_hpsi_plan*, qm_prec, hipStream_t) {}

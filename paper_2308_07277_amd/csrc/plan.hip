@@ -327,8 +327,7 @@ qm_status qm_apply_h(qm_hpsi_plan* plan, int32_t k, const void* psi, void* hpsi,
     QM_REQUIRE(k >= -1 && k < plan->nk, QM_E_ARG, "k out of range");
     const int k0 = k < 0 ? 0 : k, k1 = k < 0 ? plan->nk : k + 1;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    launch_hpsi_local(plan, k0, k1, nbnd, psi, hpsi, s, plan->prec != QM_PREC_FP64);
-    launch_nonlocal(plan, k0, k1, nbnd, psi, hpsi, s, plan->prec);
+    apply_h_slices(plan, contiguous_slices(plan, k0, k1, nbnd), psi, hpsi, s, plan->prec);
   })
 }
 
@@ -348,9 +347,9 @@ qm_status qm_apply_h_timed(qm_hpsi_plan* plan, int32_t k, const void* psi, void*
     created = true;
     for (int i = 0; i < QM_NSTAGES; ++i) ev.used[i] = false;
     const int k0 = k < 0 ? 0 : k, k1 = k < 0 ? plan->nk : k + 1;
+    QM_REQUIRE(k1 - k0 <= kMaxSlices, QM_E_ARG, "timed application handles at most 32 k-points");
     QM_HIP(hipEventRecord(ev.ev[0], s));
-    launch_hpsi_local(plan, k0, k1, nbnd, psi, hpsi, s, plan->prec != QM_PREC_FP64, &ev);
-    launch_nonlocal(plan, k0, k1, nbnd, psi, hpsi, s, plan->prec, &ev);
+    apply_h_slices(plan, contiguous_slices(plan, k0, k1, nbnd), psi, hpsi, s, plan->prec, &ev);
     QM_HIP(hipStreamSynchronize(s));
     int last = 0;
     for (int i = 0; i < QM_NSTAGES; ++i) {

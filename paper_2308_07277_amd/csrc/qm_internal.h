@@ -53,7 +53,16 @@ struct GTables {
   double* kin = nullptr;         // [sum npw] 1/2|k+G|^2 in caller order
 };
 
-struct DavState;  // Davidson workspace (davidson.cpp)
+struct DavState;  // Davidson workspace (davidson.hip)
+
+// One k-point's band block in a batched H application: nb rows of npw_k
+// coefficients starting at element offsets psi_off / hpsi_off of the call's
+// base pointers, consecutive rows npw_k apart.
+constexpr int kMaxSlices = 32;
+struct KSlice {
+  int32_t k, nb;
+  int64_t psi_off, hpsi_off;
+};
 
 // Optional per-stage event recorder: mark(i) records event i+1 after stage i.
 struct StageEvents {
@@ -99,11 +108,15 @@ struct qm_hpsi_plan {
 
 namespace qm {
 // launchers (fft.hip / gemm.hip); k0..k1 is the k range, psi/hpsi point at k0's first band
-void launch_hpsi_local(qm_hpsi_plan* p, int k0, int k1, int nbnd, const void* psi, void* hpsi,
+void launch_hpsi_local(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
                        hipStream_t s, bool fp32, StageEvents* ev = nullptr);
 void launch_vplan(qm_hpsi_plan* p, const double* vloc_r, hipStream_t s);
-void launch_nonlocal(qm_hpsi_plan* p, int k0, int k1, int nbnd, const void* psi, void* hpsi,
+void launch_nonlocal(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
                      hipStream_t s, qm_prec prec, StageEvents* ev = nullptr);
+// H applied to every slice (local + non-local), in chunks of kMaxSlices
+void apply_h_slices(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
+                    hipStream_t s, qm_prec prec, StageEvents* ev = nullptr);
+std::vector<KSlice> contiguous_slices(const qm_hpsi_plan* p, int k0, int k1, int nbnd);
 void convert_beta(qm_hpsi_plan* p, qm_prec prec, hipStream_t s);
 bool fft_len_supported(int n);
 int fft_split_r1(int n);
