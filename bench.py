@@ -23,6 +23,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 PEAK_TFLOPS = {"f64": 78.6, "f32": 157.3, "bf16": 2500.0}
+# vector ALU peak without packed-FP32 instructions (the kernels are built without them):
+# 256 CUs x 2.4 GHz x 128 flop/clk (64 FMA lanes x 2) = 78.6 TFLOP/s for float32 and float64
+ALU_PEAK_TFLOPS = 78.6
 PREC_CODE = {"fp64": 0, "fp32": 1, "mixed": 2}
 PREC_DTYPE = {"fp64": "f64", "fp32": "f32", "mixed": "f32+bf16"}
 
@@ -30,6 +33,14 @@ PREC_DTYPE = {"fp64": "f64", "fp32": "f32", "mixed": "f32+bf16"}
 def _nsticks(miller, grid):
     i = np.mod(miller[:, :2], np.asarray(grid[:2]))
     return len(np.unique(i[:, 0] * grid[1] + i[:, 1]))
+
+
+def _nax(miller, grid):
+    return len(np.unique(np.mod(miller[:, 0], grid[0])))
+
+
+def _fft_flops(n):
+    return 5.0 * n * np.log2(n)
 
 
 def build_inputs(w):
@@ -61,7 +72,12 @@ def algorithmic_model(w, prec):
     sb = sum(w.nbnd * s * n3 * csz for s in nst)          # stick buffer, all bands
     psi_b = sum(w.nbnd * int(n) * 16 for n in w.npw)      # c128 band block
     out["zinv"] = ("hbm", psi_b + sb)
-    out["xy"] = ("hbm", 2 * sb)
+    n1, n2 = w.grid[0], w.grid[1]
+    xy_fl = 0.0
+    for m in w.miller:
+        nax = _nax(m, w.grid)
+        xy_fl += w.nbnd * n3 * ((2 * nax + 2 * n2) * _fft_flops(n1) + 2.0 * n1 * n2)
+    out["xy"] = ("alu", xy_fl)
     out["zfwd"] = ("hbm", sb + 2 * psi_b)
     fl = sum(8.0 * w.nproj * w.nbnd * int(n) for n in w.npw)
     out["proj_gemm"] = ("mfma", fl)
@@ -88,13 +104,43 @@ def cpu_baseline(w, nb_sample):
                       f"workload, {nb_sample} bands, {dt:.1f} s"}
 
 
+def davidson_run(name, tol=1e-8, max_basis_factor=4):
+    """FP64 Teter-preconditioned block Davidson from a seeded random start to max residual
+    <= tol over every k-point and band; wall time of qm_davidson_solve."""
+    import torch
+    import workload
+    import paper_2308_07277_amd as qm
+    w = workload.make_workload(name)
+    miller, beta, vloc, _ = build_inputs(w)
+    plan = qm.qm_hpsi_plan_create(w.cell, w.grid, w.k_cart, w.npw, miller, w.nbnd, w.nproj,
+                                  vloc, beta, w.dmat(), 0)
+    del beta, vloc
+    psi = torch.cat([torch.from_numpy(w.psi(ik, purpose=2).reshape(-1)) for ik in range(w.nk)]).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eig, res, stats, st = qm.qm_davidson_solve(plan, -1, psi, w.nbnd, tol=tol, max_iter=400,
+                                               max_basis=max_basis_factor * w.nbnd)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    plan.close()
+    return {"workload": f"{name}: {len(w.atoms)}-atom cell, {w.nk} k-points (Gamma + 16), "
+                        f"{w.nbnd} bands, tol {tol:g} Ha, max_basis {max_basis_factor} nbnd",
+            "arm": "fp64+teter", "status": int(st), "time_s": wall, "iterations": stats["iterations"],
+            "n_hpsi_bands": stats["n_hpsi_bands"], "max_resnorm": stats["max_resnorm"],
+            "t_hpsi_ms": stats["t_hpsi_ms"], "t_eig_ms": stats["t_eig_ms"],
+            "t_subspace_ms": stats["t_subspace_ms"], "lowest_eig_gamma": float(eig[0][0])}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c3")
-    ap.add_argument("--prec", default="fp64", choices=list(PREC_CODE))
+    ap.add_argument("--prec", default="fp64", choices=list(PREC_CODE),
+                    help="precision of the reported value; the other two are measured alongside")
+    ap.add_argument("--davidson", type=int, default=1,
+                    help="also time the FP64 Teter Davidson to 1e-8 Ha on the Gamma + 16 k cell")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample-bands", type=int, default=160)
     args = ap.parse_args()
@@ -114,26 +160,36 @@ def main():
                                   vloc, beta, w.dmat(), PREC_CODE[args.prec])
     del beta, vloc
     hpsi = torch.empty_like(psi)
-    torch.cuda.synchronize()
-    for _ in range(args.warmup):
-        qm.qm_apply_h(plan, -1, psi, hpsi, w.nbnd)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        qm.qm_apply_h(plan, -1, psi, hpsi, w.nbnd)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms = 1000.0 * dt / args.steps
     bands = w.nk * w.nbnd
-    value = bands / (ms / 1000.0)
 
-    # per-stage durations (HIP events on the launch stream), averaged
-    stages = {}
-    nrep = 5
-    for _ in range(nrep):
-        t = qm.qm_apply_h_timed(plan, -1, psi, hpsi, w.nbnd)
-        for k, v in t.items():
-            stages[k] = stages.get(k, 0.0) + v / nrep
+    def measure(prec):
+        qm.qm_hpsi_plan_set_precision(plan, PREC_CODE[prec])
+        torch.cuda.synchronize()
+        for _ in range(args.warmup):
+            qm.qm_apply_h(plan, -1, psi, hpsi, w.nbnd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            qm.qm_apply_h(plan, -1, psi, hpsi, w.nbnd)
+        torch.cuda.synchronize()
+        ms_ = 1000.0 * (time.perf_counter() - t0) / args.steps
+        st = {}
+        nrep = 5
+        for _ in range(nrep):
+            t = qm.qm_apply_h_timed(plan, -1, psi, hpsi, w.nbnd)
+            for k, v in t.items():
+                st[k] = st.get(k, 0.0) + v / nrep
+        return ms_, st
+
+    others = {}
+    for prec in PREC_CODE:
+        if prec == args.prec:
+            continue
+        ms_o, st_o = measure(prec)
+        others[prec] = {"bands_per_s": bands / (ms_o / 1000.0), "ms_per_step": ms_o,
+                        "stages_ms": st_o}
+    ms, stages = measure(args.prec)
+    value = bands / (ms / 1000.0)
     model, _, nst = algorithmic_model(w, args.prec)
     dom = max(stages, key=lambda k: stages[k])
     bound, amount = model.get(dom, ("hbm", 0.0))
@@ -142,6 +198,10 @@ def main():
         achieved = amount / sec / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom}
+    elif bound == "alu":
+        achieved = amount / sec / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / ALU_PEAK_TFLOPS, "traffic": None, "kernel": dom}
     else:
         dt_ = {"fp64": "f64", "fp32": "f32", "mixed": "bf16"}[args.prec]
         achieved = amount / sec / 1e12
@@ -151,7 +211,8 @@ def main():
     for k, (b, a) in model.items():
         if stages.get(k, 0) > 0:
             s_ = stages[k] / 1000.0
-            stage_rates[k] = ({"GB/s": a / s_ / 1e9} if b == "hbm" else {"TFLOP/s": a / s_ / 1e12})
+            stage_rates[k] = ({"GB/s": a / s_ / 1e9} if b == "hbm" else {"TFLOP/s": a / s_ / 1e12,
+                                                                         "bound": b})
     out = {
         "metric": "Hpsi bands/s (FP64 vs mixed) + Davidson time to 1e-8 Ha residual, 64-atom",
         "value": value, "unit": "bands/s", "n_gpus": 1, "steps": args.steps,
@@ -162,7 +223,13 @@ def main():
                                f"{w.nbnd} bands, {w.nproj} projectors, all k and bands per step",
                    "npw": [int(x) for x in w.npw], "nstick": nst, "prec": args.prec},
         "stages_ms": stages, "stage_rates": stage_rates, "roofline": roof,
+        "other_precisions": others,
     }
+    plan.close()
+    del psi, hpsi
+    torch.cuda.empty_cache()
+    if args.davidson:
+        out["davidson"] = davidson_run("c4")
     if args.cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_bands)
     print(json.dumps(out), flush=True)

@@ -158,8 +158,9 @@ __global__ void __launch_bounds__(256) k_cgemm_cn(const CNBatch batch, int nspli
 // C = alpha * sum_s part_s + beta * C  (c128 output, row-major ldc)
 struct CNOut { void* C; int32_t M, N; int64_t ldc, work_off, elem0; };
 struct CNOutBatch { CNOut p[MAXP]; int32_t n; };
+template <typename T>
 __global__ void k_cn_reduce(const CNOutBatch outs, int nsplit,
-                            const cplx<double>* __restrict__ work, double alpha, double beta,
+                            const cplx<T>* __restrict__ work, double alpha, double beta,
                             int64_t total) {
   for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < total;
        t += int64_t(gridDim.x) * blockDim.x) {
@@ -169,10 +170,10 @@ __global__ void k_cn_reduce(const CNOutBatch outs, int nsplit,
     const int64_t e = t - o.elem0;
     const int i = int(e / o.N), j = int(e % o.N);
     double sr = 0, si = 0;
-    const cplx<double>* w = work + o.work_off + e;
+    const cplx<T>* w = work + o.work_off + e;
     for (int s = 0; s < nsplit; ++s) {
-      sr += w[int64_t(s) * o.M * o.N].re;
-      si += w[int64_t(s) * o.M * o.N].im;
+      sr += double(w[int64_t(s) * o.M * o.N].re);
+      si += double(w[int64_t(s) * o.M * o.N].im);
     }
     double2* c = reinterpret_cast<double2*>(o.C) + int64_t(i) * o.ldc + j;
     double2 old = beta != 0.0 ? *c : make_double2(0.0, 0.0);
@@ -257,6 +258,216 @@ __global__ void __launch_bounds__(256) k_cgemm_ex(const EXBatch batch, double al
       }
 }
 
+
+// ------------------------------------------------------------------ bfloat16 operands
+// v_mfma_f32_16x16x32_bf16: lane l supplies A[i = l%16][k = 8(l/16) .. +7] and
+// B[k = 8(l/16) .. +7][j = l%16]; the four float32 accumulators follow the float32
+// 16x16 layout.  Complex operands are staged in LDS as separate re/im planes with K
+// contiguous so each lane reads its eight K values with one 16-byte load.
+typedef unsigned short u16;
+struct bf2 { u16 re, im; };   // bfloat16 complex storage (round to nearest even)
+
+__device__ __forceinline__ u16 f2bf(float x) {
+  __bf16 b = (__bf16)x;
+  return *reinterpret_cast<u16*>(&b);
+}
+__device__ __forceinline__ bf8v ld8(const u16* p) {
+  typedef u16 u16x8 __attribute__((ext_vector_type(8)));
+  u16x8 v = *reinterpret_cast<const u16x8*>(p);
+  return *reinterpret_cast<bf8v*>(&v);
+}
+__device__ __forceinline__ bf8v neg8(bf8v a) {
+  typedef u16 u16x8 __attribute__((ext_vector_type(8)));
+  u16x8 v = *reinterpret_cast<u16x8*>(&a);
+  v ^= (u16)0x8000;
+  return *reinterpret_cast<bf8v*>(&v);
+}
+__device__ __forceinline__ f4v mfma32(bf8v a, bf8v b, f4v c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+constexpr int KB = 32;       // K chunk of the bf16 kernels (complex elements)
+constexpr int KBP = KB + 8;  // padded LDS row (bf16 elements), keeps 16-byte alignment
+
+// CN with A = bf16 complex (beta), B = c128 (psi, converted on load); float32 partials
+__global__ void __launch_bounds__(256) k_cgemm_cn_bf16(const CNBatch batch, int nsplit,
+                                                       cplx<float>* __restrict__ work) {
+  __shared__ __align__(16) u16 Ar[BT][KBP], Ai[BT][KBP], Br[BT][KBP], Bi[BT][KBP];
+  const int pi = find_prob(batch, blockIdx.x);
+  const CNDev& P = batch.p[pi];
+  int bid = blockIdx.x - P.blk0;
+  const int split = bid % nsplit;
+  const int tile = bid / nsplit;
+  const int i0 = (tile % P.tm) * BT, j0 = (tile / P.tm) * BT;
+  const int nch = (P.K + KB - 1) / KB;
+  const int per = (nch + nsplit - 1) / nsplit;
+  const int c0 = split * per, c1 = min(nch, c0 + per);
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = (wave & 1) * 32, wj = (wave >> 1) * 32;
+  const int lrow = tid >> 2, lseg = (tid & 3) * 8;   // 64 rows x 4 segments of 8
+  const bf2* A = reinterpret_cast<const bf2*>(P.A);
+  const double2* B = reinterpret_cast<const double2*>(P.B);
+  f4v cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = f4v{0, 0, 0, 0};
+      ci[a][b] = f4v{0, 0, 0, 0};
+    }
+  const bool arow = (i0 + lrow) < P.M, brow = (j0 + lrow) < P.N;
+  const bf2* Arow = A + int64_t(i0 + lrow) * P.lda;
+  const double2* Brow = B + int64_t(j0 + lrow) * P.ldb;
+  for (int c = c0; c < c1; ++c) {
+    const int kb = c * KB + lseg;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int g = kb + q;
+      bf2 av = {0, 0};
+      if (arow && g < P.K) av = Arow[g];
+      Ar[lrow][lseg + q] = av.re;
+      Ai[lrow][lseg + q] = av.im;
+      double2 bv = make_double2(0.0, 0.0);
+      if (brow && g < P.K) bv = Brow[g];
+      Br[lrow][lseg + q] = f2bf(float(bv.x));
+      Bi[lrow][lseg + q] = f2bf(float(bv.y));
+    }
+    __syncthreads();
+    const int ko = 8 * (lane >> 4);
+    bf8v ar[2], ai[2], nai[2], br[2], bi[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      ar[t] = ld8(&Ar[wi + t * 16 + (lane & 15)][ko]);
+      ai[t] = ld8(&Ai[wi + t * 16 + (lane & 15)][ko]);
+      nai[t] = neg8(ai[t]);
+      br[t] = ld8(&Br[wj + t * 16 + (lane & 15)][ko]);
+      bi[t] = ld8(&Bi[wj + t * 16 + (lane & 15)][ko]);
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        cr[ti][tj] = mfma32(ar[ti], br[tj], cr[ti][tj]);
+        cr[ti][tj] = mfma32(ai[ti], bi[tj], cr[ti][tj]);
+        ci[ti][tj] = mfma32(ar[ti], bi[tj], ci[ti][tj]);
+        ci[ti][tj] = mfma32(nai[ti], br[tj], ci[ti][tj]);
+      }
+    __syncthreads();
+  }
+  cplx<float>* W = work + P.work_off + int64_t(split) * P.M * P.N;
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = i0 + wi + ti * 16 + acc_row<float>(lane, r);
+        const int j = j0 + wj + tj * 16 + (lane & 15);
+        if (i < P.M && j < P.N) W[int64_t(i) * P.N + j] = cplx<float>{cr[ti][tj][r], ci[ti][tj][r]};
+      }
+}
+
+// EX with W = c128 (Q, converted on load), A = bf16 complex (beta); Y c128 accumulated
+__global__ void __launch_bounds__(256) k_cgemm_ex_bf16(const EXBatch batch, double alpha, double beta) {
+  __shared__ __align__(16) u16 Wr[BT][KBP], Wi[BT][KBP], Ar[BT][KBP], Ai[BT][KBP];
+  const int pi = find_prob(batch, blockIdx.x);
+  const EXDev& P = batch.p[pi];
+  const int tile = blockIdx.x - P.blk0;
+  const int m0 = (tile % P.tm) * BT, n0 = (tile / P.tm) * BT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = (wave & 1) * 32, wj = (wave >> 1) * 32;
+  const double2* Wp = reinterpret_cast<const double2*>(P.W);
+  const bf2* Ap = reinterpret_cast<const bf2*>(P.A);
+  f4v cr[2][2], ci[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      cr[a][b] = f4v{0, 0, 0, 0};
+      ci[a][b] = f4v{0, 0, 0, 0};
+    }
+  const int nch = (P.K + KB - 1) / KB;
+  // staging: 32 K-rows x 64 columns; thread t -> K-row t/8, columns 8*(t%8) .. +7
+  const int lr = tid >> 3, lc = (tid & 7) * 8;
+  for (int c = 0; c < nch; ++c) {
+    const int i = c * KB + lr;
+    const bool irow = i < P.K;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int m = m0 + lc + q, n = n0 + lc + q;
+      double2 wv = make_double2(0.0, 0.0);
+      if (irow && m < P.M) wv = Wp[int64_t(i) * P.ldw + m];
+      Wr[lc + q][lr] = f2bf(float(wv.x));
+      Wi[lc + q][lr] = f2bf(float(wv.y));
+      bf2 av = {0, 0};
+      if (irow && n < P.N) av = Ap[int64_t(i) * P.lda + n];
+      Ar[lc + q][lr] = av.re;
+      Ai[lc + q][lr] = av.im;
+    }
+    __syncthreads();
+    const int ko = 8 * (lane >> 4);
+    bf8v wr[2], wim[2], nwi[2], ar[2], ai[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      wr[t] = ld8(&Wr[wi + t * 16 + (lane & 15)][ko]);
+      wim[t] = ld8(&Wi[wi + t * 16 + (lane & 15)][ko]);
+      nwi[t] = neg8(wim[t]);
+      ar[t] = ld8(&Ar[wj + t * 16 + (lane & 15)][ko]);
+      ai[t] = ld8(&Ai[wj + t * 16 + (lane & 15)][ko]);
+    }
+#pragma unroll
+    for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj) {
+        cr[ti][tj] = mfma32(wr[ti], ar[tj], cr[ti][tj]);
+        cr[ti][tj] = mfma32(nwi[ti], ai[tj], cr[ti][tj]);
+        ci[ti][tj] = mfma32(wr[ti], ai[tj], ci[ti][tj]);
+        ci[ti][tj] = mfma32(wim[ti], ar[tj], ci[ti][tj]);
+      }
+    __syncthreads();
+  }
+  double2* Y = reinterpret_cast<double2*>(P.Y);
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wi + ti * 16 + acc_row<float>(lane, r);
+        const int n = n0 + wj + tj * 16 + (lane & 15);
+        if (m < P.M && n < P.N) {
+          double2* y = Y + int64_t(m) * P.ldy + n;
+          const double vr = double(cr[ti][tj][r]), vi = double(ci[ti][tj][r]);
+          if (beta != 0.0) {
+            const double2 o = *y;
+            *y = make_double2(alpha * vr + beta * o.x, alpha * vi + beta * o.y);
+          } else {
+            *y = make_double2(alpha * vr, alpha * vi);
+          }
+        }
+      }
+}
+
+// beta (c128) -> float32 or bfloat16 complex copy
+__global__ void k_beta_lp(const double2* __restrict__ in, void* __restrict__ out, int64_t n, int kind) {
+  for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
+       t += int64_t(gridDim.x) * blockDim.x) {
+    const double2 v = in[t];
+    if (kind == 1) {
+      reinterpret_cast<float2*>(out)[t] = make_float2(float(v.x), float(v.y));
+    } else {
+      reinterpret_cast<bf2*>(out)[t] = bf2{f2bf(float(v.x)), f2bf(float(v.y))};
+    }
+  }
+}
+
+void convert_beta_lp(const void* beta64, void* out, int64_t n, int kind, hipStream_t s) {
+  const int blocks = int(std::min<int64_t>((n + 255) / 256, 65536));
+  hipLaunchKernelGGL(k_beta_lp, dim3(blocks), dim3(256), 0, s, reinterpret_cast<const double2*>(beta64),
+                     out, n, kind);
+  QM_HIP(hipGetLastError());
+}
+
 // ------------------------------------------------------------------ host side
 static int choose_splits(int64_t tiles, int64_t maxK) {
   int s = 1;
@@ -275,7 +486,7 @@ int64_t zgemm_cn_work_bytes(const std::vector<GemmCN>& probs) {
 }
 
 void zgemm_cn_batched(const std::vector<GemmCN>& probs, double alpha, double beta_c, void* work,
-                      int64_t work_bytes, hipStream_t s, StageEvents* ev, int stage0) {
+                      int64_t work_bytes, hipStream_t s, StageEvents* ev, int stage0, int lp) {
   for (size_t base = 0; base < probs.size(); base += MAXP) {
     const size_t n = std::min<size_t>(MAXP, probs.size() - base);
     std::vector<GemmCN> sub(probs.begin() + base, probs.begin() + base + n);
@@ -309,19 +520,33 @@ void zgemm_cn_batched(const std::vector<GemmCN>& probs, double alpha, double bet
     if (e0 == 0) continue;
     QM_REQUIRE(woff * int64_t(sizeof(cplx<double>)) <= work_bytes, QM_E_STATE,
                "GEMM split-K workspace too small");
-    hipLaunchKernelGGL((k_cgemm_cn<double, double2, double2>), dim3(unsigned(blk)), dim3(256), 0, s,
-                       d, nsplit, reinterpret_cast<cplx<double>*>(work));
-    QM_HIP(hipGetLastError());
-    if (ev) ev->mark(stage0);
     const int rb = int(std::min<int64_t>((e0 + 255) / 256, 8192));
-    hipLaunchKernelGGL(k_cn_reduce, dim3(rb), dim3(256), 0, s, o, nsplit,
-                       reinterpret_cast<const cplx<double>*>(work), alpha, beta_c, e0);
+    if (lp == 0) {
+      hipLaunchKernelGGL((k_cgemm_cn<double, double2, double2>), dim3(unsigned(blk)), dim3(256), 0, s,
+                         d, nsplit, reinterpret_cast<cplx<double>*>(work));
+      QM_HIP(hipGetLastError());
+      if (ev) ev->mark(stage0);
+      hipLaunchKernelGGL(k_cn_reduce<double>, dim3(rb), dim3(256), 0, s, o, nsplit,
+                         reinterpret_cast<const cplx<double>*>(work), alpha, beta_c, e0);
+    } else {
+      if (lp == 1)
+        hipLaunchKernelGGL((k_cgemm_cn<float, float2, double2>), dim3(unsigned(blk)), dim3(256), 0, s,
+                           d, nsplit, reinterpret_cast<cplx<float>*>(work));
+      else
+        hipLaunchKernelGGL(k_cgemm_cn_bf16, dim3(unsigned(blk)), dim3(256), 0, s, d, nsplit,
+                           reinterpret_cast<cplx<float>*>(work));
+      QM_HIP(hipGetLastError());
+      if (ev) ev->mark(stage0);
+      hipLaunchKernelGGL(k_cn_reduce<float>, dim3(rb), dim3(256), 0, s, o, nsplit,
+                         reinterpret_cast<const cplx<float>*>(work), alpha, beta_c, e0);
+    }
     QM_HIP(hipGetLastError());
     if (ev) ev->mark(stage0 + 1);
   }
 }
 
-void zgemm_ex_batched(const std::vector<GemmEX>& probs, double alpha, double beta_y, hipStream_t s) {
+void zgemm_ex_batched(const std::vector<GemmEX>& probs, double alpha, double beta_y, hipStream_t s,
+                      int lp) {
   for (size_t base = 0; base < probs.size(); base += MAXP) {
     const size_t n = std::min<size_t>(MAXP, probs.size() - base);
     EXBatch d{};
@@ -338,8 +563,14 @@ void zgemm_ex_batched(const std::vector<GemmEX>& probs, double alpha, double bet
       blk += int64_t(x.tm) * x.tn;
     }
     if (blk == 0) continue;
-    hipLaunchKernelGGL((k_cgemm_ex<double, double2, double2>), dim3(unsigned(blk)), dim3(256), 0, s,
-                       d, alpha, beta_y);
+    if (lp == 0)
+      hipLaunchKernelGGL((k_cgemm_ex<double, double2, double2>), dim3(unsigned(blk)), dim3(256), 0, s,
+                         d, alpha, beta_y);
+    else if (lp == 1)
+      hipLaunchKernelGGL((k_cgemm_ex<float, double2, float2>), dim3(unsigned(blk)), dim3(256), 0, s,
+                         d, alpha, beta_y);
+    else
+      hipLaunchKernelGGL(k_cgemm_ex_bf16, dim3(unsigned(blk)), dim3(256), 0, s, d, alpha, beta_y);
     QM_HIP(hipGetLastError());
   }
 }

@@ -28,8 +28,8 @@ __global__ void k_apply_d(const double2* __restrict__ P, double2* __restrict__ Q
   }
 }
 
-void launch_nonlocal_fp64(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi,
-                          void* hpsi, hipStream_t s, StageEvents* ev) {
+void launch_nonlocal_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi,
+                       void* hpsi, hipStream_t s, StageEvents* ev, int lp) {
   if (p->nproj == 0) return;
   const int np = p->nproj;
   double2* P = reinterpret_cast<double2*>(p->proj_q);
@@ -39,14 +39,16 @@ void launch_nonlocal_fp64(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const 
   int64_t off = 0;
   for (const KSlice& x : sl) {
     const KInfo& ki = p->kinfo[x.k];
-    const double2* bk = reinterpret_cast<const double2*>(p->beta64) + ki.beta_off;
+    const char* bbase = reinterpret_cast<const char*>(lp == 0 ? p->beta64 : p->beta_lp);
+    const size_t esz = lp == 0 ? 16 : (lp == 1 ? 8 : 4);
+    const void* bk = bbase + size_t(ki.beta_off) * esz;
     const double2* pk = reinterpret_cast<const double2*>(psi) + x.psi_off;
     double2* hk = reinterpret_cast<double2*>(hpsi) + x.hpsi_off;
     cn.push_back(GemmCN{bk, pk, P + off, np, x.nb, ki.npw, ki.npw, ki.npw, x.nb});
     ex.push_back(GemmEX{Q + off, bk, hk, x.nb, ki.npw, np, x.nb, ki.npw, ki.npw});
     off += int64_t(np) * x.nb;
   }
-  zgemm_cn_batched(cn, 1.0, 0.0, p->proj_part, p->proj_part_bytes, s, ev, 3);
+  zgemm_cn_batched(cn, 1.0, 0.0, p->proj_part, p->proj_part_bytes, s, ev, 3, lp);
   // D acts on each slice's [np][nb] block; blocks are packed back to back
   int64_t base = 0;
   for (const KSlice& x : sl) {
@@ -58,16 +60,26 @@ void launch_nonlocal_fp64(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const 
     base += total;
   }
   if (ev) ev->mark(5);
-  zgemm_ex_batched(ex, 1.0, 1.0, s);
+  zgemm_ex_batched(ex, 1.0, 1.0, s, lp);
   if (ev) ev->mark(6);
 }
 
 void launch_nonlocal(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
                      hipStream_t s, qm_prec prec, StageEvents* ev) {
-  (void)prec;
-  launch_nonlocal_fp64(p, sl, psi, hpsi, s, ev);
+  const int lp = prec == QM_PREC_FP64 ? 0 : (prec == QM_PREC_FP32 ? 1 : 2);
+  if (lp != 0 && p->beta_lp_kind != lp) convert_beta(p, prec, s);
+  launch_nonlocal_t(p, sl, psi, hpsi, s, ev, lp);
 }
 
-void convert_beta(qm_hpsi_plan*, qm_prec, hipStream_t) {}
+// low-precision copy of beta for the FP32 (c64) or MIXED (bf16 pairs) projector GEMMs
+void convert_beta(qm_hpsi_plan* p, qm_prec prec, hipStream_t s) {
+  if (p->nproj == 0 || prec == QM_PREC_FP64) return;
+  const int lp = prec == QM_PREC_FP32 ? 1 : 2;
+  if (p->beta_lp_kind == lp) return;
+  const int64_t n = int64_t(p->nproj) * p->npw_total;
+  if (!p->beta_lp) QM_HIP(hipMalloc(&p->beta_lp, size_t(n) * 8));
+  convert_beta_lp(p->beta64, p->beta_lp, n, lp, s);
+  p->beta_lp_kind = lp;
+}
 
 }  // namespace qm

@@ -238,6 +238,7 @@ static void build_plan(qm_hpsi_plan* p, const double cell[9], const int32_t grid
     p->proj_part_bytes = std::max<int64_t>(zgemm_cn_work_bytes(cn), 16);
     QM_HIP(hipMalloc(&p->proj_part, p->proj_part_bytes));
   }
+  if (prec != QM_PREC_FP64) convert_beta(p, prec, s);
   p->sbuf_elems = int64_t(nbnd_max) * N3 * stick_off;
   QM_HIP(hipMalloc(&p->sbuf, size_t(p->sbuf_elems) * 16));
   QM_HIP(hipStreamSynchronize(s));

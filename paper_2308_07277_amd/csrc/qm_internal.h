@@ -137,10 +137,13 @@ struct GemmEX {
 };
 void zgemm_cn_batched(const std::vector<GemmCN>& probs, double alpha, double beta_c,
                       void* work, int64_t work_bytes, hipStream_t s, StageEvents* ev = nullptr,
-                      int stage0 = 0);
+                      int stage0 = 0, int lp = 0);
 int64_t zgemm_cn_work_bytes(const std::vector<GemmCN>& probs);
 void zgemm_ex_batched(const std::vector<GemmEX>& probs, double alpha, double beta_y,
-                      hipStream_t s);
+                      hipStream_t s, int lp = 0);
+// lp: 0 float64 operands, 1 float32 (A of CN / A of EX stored float32), 2 bfloat16 (same
+// operands stored bfloat16); B of CN and W of EX are always c128 and converted on load
+void convert_beta_lp(const void* beta64, void* out, int64_t n, int kind, hipStream_t s);
 
 void plan_upload_davidson(qm_hpsi_plan* p);
 void davidson_free(qm_hpsi_plan* p);

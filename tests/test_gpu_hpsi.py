@@ -137,3 +137,22 @@ def test_full_size_fp64_sampled(name):
         err = band_rel_err(out[ik][bands], ref)
         print(f"{name} fp64 k={ik} bands {bands} rel err {err}")
         assert err.max() <= 1e-12
+
+
+@pytest.mark.parametrize("prec,bound", [(1, 1e-5), (2, 3e-2)])
+def test_c2_reduced_precision(prec, bound):
+    """float32 FFT + float32 GEMM (prec 1) and float32 FFT + bfloat16 GEMM (prec 2) against
+    the float64 oracle.  float32: unit roundoff 6e-8 times ~2 log2(N_r) butterfly levels and
+    the sqrt(K)-growth of the projector sums stays below 1e-5.  bfloat16 operands (unit
+    roundoff 3.9e-3) bound the non-local part's relative error by a few 1e-3, scaled by the
+    non-local share of H psi; 3e-2 leaves margin."""
+    w = workload.make_workload("c2")
+    plan, a = make_plan(w, w.nbnd, prec=prec)
+    flat, per = psi_block(w, w.nbnd)
+    out = split_k(_run(plan, w, w.nbnd, psi_flat=flat), w, w.nbnd)
+    worst = 0.0
+    for ik in range(w.nk):
+        err = band_rel_err(out[ik], _oracle(w, a, ik, per[ik]))
+        worst = max(worst, err.max())
+    print(f"c2 prec={prec} max per-band rel err {worst:.3e}")
+    assert worst <= bound

@@ -1,0 +1,78 @@
+"""Pins for the learned-preconditioner oracle: finite differences, special cases, Adam."""
+import numpy as np
+
+from oracle import mlp
+
+
+def _data(seed=0, nb=3, npw=40):
+    rng = np.random.default_rng(seed)
+    kin = rng.uniform(0, 4, npw)
+    r = rng.standard_normal((nb, npw)) + 1j * rng.standard_normal((nb, npw))
+    delta = rng.standard_normal((nb, npw)) + 1j * rng.standard_normal((nb, npw))
+    theta = rng.uniform(-0.5, 0.5, nb)
+    tkin = rng.uniform(0.5, 1.5, nb)
+    f = mlp.features(kin, r, theta, tkin).reshape(-1, 5)
+    ptr = np.arange(nb + 1) * npw
+    return f, r.reshape(-1), delta.reshape(-1), ptr
+
+
+def test_gradient_matches_finite_differences():
+    f, r, d, ptr = _data()
+    w = mlp.init_weights(3)
+    w[-256 - 2:-2] = np.random.default_rng(1).standard_normal(256) * 0.3   # non-trivial W2
+    L, g = mlp.loss_grad(w, f, r, d, ptr)
+    assert abs(L - mlp.loss(w, f, r, d, ptr)) < 1e-14
+    rng = np.random.default_rng(2)
+    idx = rng.choice(mlp.NPARAM, 40, replace=False)
+    for i in idx:
+        h = 1e-6
+        wp, wm = w.copy(), w.copy()
+        wp[i] += h
+        wm[i] -= h
+        fd = (mlp.loss(wp, f, r, d, ptr) - mlp.loss(wm, f, r, d, ptr)) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (i, fd, g[i])
+
+
+def test_unit_gain_is_plain_residual():
+    """W2 = 0, b2 = (1, 0): g = 1, t = r, so the loss is 1 - cos^2(r, delta) per band."""
+    f, r, d, ptr = _data(4)
+    W1, b1, W2, b2 = mlp.unpack(mlp.init_weights(0))
+    w = mlp.pack(W1, b1, np.zeros_like(W2), np.array([1.0, 0.0]))
+    np.testing.assert_allclose(mlp.forward(w, f), np.tile([1.0, 0.0], (f.shape[0], 1)), atol=0)
+    exp = 0.0
+    for b in range(len(ptr) - 1):
+        s = slice(ptr[b], ptr[b + 1])
+        exp += 1 - abs(np.vdot(r[s], d[s])) ** 2 / (np.linalg.norm(r[s]) ** 2 * np.linalg.norm(d[s]) ** 2)
+    assert abs(mlp.loss(w, f, r, d, ptr) - exp / (len(ptr) - 1)) < 1e-14
+
+
+def test_loss_is_phase_and_scale_free():
+    f, r, d, ptr = _data(5)
+    w = mlp.init_weights(1)
+    L0 = mlp.loss(w, f, r, d, ptr)
+    assert abs(mlp.loss(w, f, r, d * (2.5 * np.exp(0.7j)), ptr) - L0) < 1e-13
+    # a gain proportional to delta/r gives zero loss
+    assert abs(mlp.loss(w, f, r, r * 3j, ptr) - mlp.loss(w, f, r, r, ptr)) < 1e-13
+
+
+def test_adam_first_step():
+    """After one step the bias-corrected update is lr * g / (|g| + eps)."""
+    w = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -4.0, 1e-3])
+    w1, m, v = mlp.adam_step(w, g, np.zeros(3), np.zeros(3), 1, lr=0.01)
+    np.testing.assert_allclose(w1, w - 0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def test_correction_target():
+    rng = np.random.default_rng(6)
+    q, _ = np.linalg.qr(rng.standard_normal((30, 6)) + 1j * rng.standard_normal((30, 6)))
+    xs = q.T                                  # 6 orthonormal rows
+    eig = np.array([0.0, 1.0, 1.0, 2.0, 3.0, 4.0])  # rows 1, 2 degenerate
+    assert np.abs(mlp.correction_target(xs[:3], xs, eig)).max() < 1e-14
+    # x_1 tilted into the degenerate partner only: still exact (no correction needed)
+    x = np.cos(0.3) * xs[1] + np.sin(0.3) * xs[2]
+    assert np.abs(mlp.correction_target(np.stack([xs[0], x]), xs, eig)[1]).max() < 1e-14
+    # tilted toward a non-degenerate level: target points back to the level
+    y = np.cos(0.2) * xs[3] + np.sin(0.2) * xs[4]
+    dlt = mlp.correction_target(np.stack([xs[0], xs[1], xs[2], y]), xs, eig)[3]
+    np.testing.assert_allclose(dlt, xs[3] - y, atol=1e-14)
