@@ -183,30 +183,47 @@ qm_status qm_davidson_solve(qm_hpsi_plan *plan, int32_t k, void *psi, double *ei
 
 /* ------------------------------------------------------------------ learned preconditioner */
 
-/* Per-(G, band) network t(G) = g(G) r(G), g complex, from five features
- * f = [x, log x, theta_n - T_n, |r(G)|/||r_n|| * sqrt(npw), 1/2|k+G|^2]
- * with x = (1/2|k+G|^2)/T_n and T_n the band kinetic energy; layer 1: 5 -> 128
- * with SiLU, layer 2: 128 -> 2 (re, im of g).  Weights are float32 in one
- * device buffer: W1[128][5], b1[128], W2[2][128], b2[2]  (QM_MLP_NPARAM floats). */
+/* Per-(G, band) network with shared weights (an extension of the paper's
+ * Davidson; not in the paper).  Inputs f = [x, log(1 + x), (theta_n - T_n)/T_n,
+ * |r_n(G)| sqrt(npw_k)/||r_n||, T(G)] with T(G) = 1/2|k+G|^2 (Ha), T_n the
+ * band kinetic energy <x_n|T|x_n> and x = T(G)/T_n; hidden layer 128 with SiLU;
+ * output the complex gain g = (g_re, g_im); correction t_n(G) = g r_n(G).
+ * Weights: one device float32 buffer of QM_MLP_NPARAM numbers laid out
+ * W1[128][5], b1[128], W2[2][128], b2[2]. */
 #define QM_MLP_NIN 5
 #define QM_MLP_NHID 128
 #define QM_MLP_NPARAM (128 * 5 + 128 + 2 * 128 + 2)
 
-/* Forward pass over n rows of features (device float32 [n][5]) -> gains (device float32 [n][2]). */
+/* Gains for n feature rows: feat device float32 [n][5] -> gain device float32 [n][2]. */
 qm_status qm_mlp_forward(const float *weights, const float *feat, float *gain, int64_t n,
                          void *stream);
 
-/* Loss and gradient of a weighted least-squares fit of the gain to targets:
- * L = sum_r w_r |g_r - y_r|^2 / sum_r w_r over n rows (feat [n][5], target [n][2],
- * weight [n]); writes grad (device float32 [QM_MLP_NPARAM]) and *loss (host). */
-qm_status qm_mlp_loss_grad(const float *weights, const float *feat, const float *target,
-                           const float *weight, int64_t n, float *grad, double *loss,
-                           void *stream);
+/* Loss and gradient of the per-band cosine loss
+ *   L = (1/nbands) sum_b [1 - |<t_b, d_b>|^2 / (||t_b||^2 ||d_b||^2)],  t = g r,
+ * rows of band b are [band_ptr[b], band_ptr[b+1]).  feat [n][5], resid [n][2] (r),
+ * target [n][2] (d), band_ptr int32 [nbands+1] and grad [QM_MLP_NPARAM] are device
+ * arrays; *loss is written on the host.  Synchronises the stream. */
+qm_status qm_mlp_loss_grad(const float *weights, const float *feat, const float *resid,
+                           const float *target, const int32_t *band_ptr, int32_t nbands,
+                           float *grad, double *loss, void *stream);
 
-/* One Adam step (lr, beta1, beta2, eps; t = 1-based step) on weights with
- * moment buffers m, v (device float32 [QM_MLP_NPARAM]). */
+/* One Adam step (Kingma and Ba) on the weights with moment buffers m, v (device
+ * float32 [QM_MLP_NPARAM]); t is the 1-based step count. */
 qm_status qm_mlp_adam(float *weights, const float *grad, float *m, float *v, int32_t t,
                       float lr, float beta1, float beta2, float eps, void *stream);
+
+/* Training rows from the current Davidson state of the plan (after a
+ * qm_davidson_step): for every unconverged (k, band) of that state, npw_k rows
+ * of features (as above), residual r_n(G) and target d_n(G) = P x_n/||P x_n|| - x_n,
+ * with P the projector onto the converged eigenvectors x_star (device c128,
+ * layout as psi) whose eigenvalues eig_star (host [nk_sel][nbnd]) lie within
+ * cluster_tol (Ha; 0 = 1e-6) of eig_star[n].  Outputs are device arrays with
+ * capacity cap_rows rows / cap_bands bands; *nrows and *nbands (host) receive
+ * the counts and band_ptr (device int32 [nbands+1]) the row offsets. */
+qm_status qm_dav_training_pairs(qm_hpsi_plan *plan, const void *x_star, const double *eig_star,
+                                double cluster_tol, float *feat, float *resid, float *target,
+                                int32_t *band_ptr, int64_t cap_rows, int32_t cap_bands,
+                                int64_t *nrows, int32_t *nbands, void *stream);
 
 #ifdef __cplusplus
 }

@@ -85,7 +85,8 @@ def _load():
         "qm_davidson_solve": [_P, i32, _P, _P, _P, i32, ctypes.POINTER(qm_dav_opts),
                               ctypes.POINTER(qm_dav_stats), _P],
         "qm_mlp_forward": [_P, _P, _P, i64, _P],
-        "qm_mlp_loss_grad": [_P, _P, _P, _P, i64, _P, _P, _P],
+        "qm_mlp_loss_grad": [_P, _P, _P, _P, _P, i32, _P, _P, _P],
+        "qm_dav_training_pairs": [_P, _P, _P, dbl, _P, _P, _P, _P, i64, i32, _P, _P, _P],
         "qm_mlp_adam": [_P, _P, _P, _P, i32, flt, flt, flt, flt, _P],
     }
     for name, args in sig.items():
@@ -266,16 +267,37 @@ def qm_mlp_forward(weights, feat, gain, n, stream=None):
                                   _dev(gain, torch.float32, "gain"), int(n), _stream(stream)))
 
 
-def qm_mlp_loss_grad(weights, feat, target, weight, n, grad, stream=None):
+def qm_mlp_loss_grad(weights, feat, resid, target, band_ptr, nbands, grad, stream=None):
+    """Per-band cosine loss and its gradient (device tensors); returns the loss."""
     import torch
     loss = ctypes.c_double(0.0)
     _check(_load().qm_mlp_loss_grad(_dev(weights, torch.float32, "weights"),
                                     _dev(feat, torch.float32, "feat"),
+                                    _dev(resid, torch.float32, "resid"),
                                     _dev(target, torch.float32, "target"),
-                                    _dev(weight, torch.float32, "weight"), int(n),
+                                    _dev(band_ptr, torch.int32, "band_ptr"), int(nbands),
                                     _dev(grad, torch.float32, "grad"), ctypes.byref(loss),
                                     _stream(stream)))
     return loss.value
+
+
+def qm_dav_training_pairs(plan, x_star, eig_star, feat, resid, target, band_ptr, cluster_tol=0.0,
+                          stream=None):
+    """Training rows from the plan's current Davidson state; returns (nrows, nbands)."""
+    import torch
+    es = np.ascontiguousarray(eig_star, np.float64)
+    nrows = ctypes.c_int64(0)
+    nb = ctypes.c_int32(0)
+    _check(_load().qm_dav_training_pairs(plan.handle, _dev(x_star, torch.complex128, "x_star"),
+                                         es.ctypes.data, float(cluster_tol),
+                                         _dev(feat, torch.float32, "feat"),
+                                         _dev(resid, torch.float32, "resid"),
+                                         _dev(target, torch.float32, "target"),
+                                         _dev(band_ptr, torch.int32, "band_ptr"),
+                                         int(feat.shape[0]), int(band_ptr.numel()) - 1,
+                                         ctypes.byref(nrows), ctypes.byref(nb), _stream(stream)),
+           plan.handle)
+    return int(nrows.value), int(nb.value)
 
 
 def qm_mlp_adam(weights, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

@@ -17,7 +17,9 @@
 
 namespace qm {
 
-void mlp_precondition(qm_hpsi_plan* p, const DJobs& jobs, const void* weights, hipStream_t s);
+void mlp_precondition(qm_hpsi_plan* p, const DJobs& jobs, const void* weights, hipStream_t s,
+                      const double2* R, double2* V, const int32_t* unconv, const double* tkin,
+                      const double* theta, const double* resn, const int64_t* goff);
 
 struct DavState {
   int nb = 0, mb = 0, k0 = 0, k1 = 0, nk = 0;
@@ -36,6 +38,8 @@ struct DavState {
   int32_t *h_unconv = nullptr, *h_info = nullptr;
   std::vector<int> m, it, done;
   int64_t n_hpsi = 0, n_hpsi_lowp = 0;
+  double tol = 1e-8;
+  double* estar = nullptr;   // converged eigenvalues for training-pair generation
   double t_hpsi = 0, t_sub = 0, t_eig = 0;
   hipEvent_t ev[6] = {};
 };
@@ -43,7 +47,7 @@ struct DavState {
 static void dav_release(DavState* d) {
   void* dev[] = {d->V, d->HV, d->X, d->HX, d->R, d->TS, d->Hs, d->Aw, d->Z, d->tau, d->Cw, d->G,
                  d->W, d->theta, d->d, d->e, d->resn, d->tkin, d->yw, d->fw, d->unconv, d->info,
-                 d->goff, d->work};
+                 d->goff, d->work, d->estar};
   for (void* q : dev)
     if (q) (void)hipFree(q);
   void* host[] = {d->h_resn, d->h_theta, d->h_unconv, d->h_info};
@@ -387,7 +391,8 @@ static qm_status dav_step(qm_hpsi_plan* p, int k, void* psi, double* eig, double
         QM_HIP(hipMemcpyAsync(d->unconv, d->h_unconv, sizeof(int32_t) * d->nk * nb,
                               hipMemcpyHostToDevice, s));
         if (precond == QM_PRECOND_MLP) {
-          mlp_precondition(p, jobs, o->mlp_weights, s);
+          mlp_precondition(p, jobs, o->mlp_weights, s, d->R, d->V, d->unconv, d->tkin, d->theta,
+                           d->resn, d->goff);
         } else {
           hipLaunchKernelGGL(k_teter, dim3(nb, jobs.n), dim3(256), 0, s, jobs, d->R, d->V, d->unconv,
                              d->tkin, p->g.kin, d->goff);
@@ -404,6 +409,7 @@ static qm_status dav_step(qm_hpsi_plan* p, int k, void* psi, double* eig, double
     }
   }
   StepResult r;
+  d->tol = tol;
   collect(p, d, tol, r);
   write_outputs(p, d, psi, eig, resnorm, s);
   if (n_unconv) *n_unconv = r.n_unconv;
@@ -412,6 +418,128 @@ static qm_status dav_step(qm_hpsi_plan* p, int k, void* psi, double* eig, double
 }
 
 DavState* dav_of(qm_hpsi_plan* p) { return p->dav; }
+
+// keep C[m][n] only where |e*_m - e*_n| <= ctol (the degenerate level of band n)
+__global__ void k_mask_cluster(DJobs jobs, double2* __restrict__ C, const double* __restrict__ estar,
+                               double ctol) {
+  const DJob& J = jobs.j[blockIdx.y];
+  const int nb = jobs.nb;
+  double2* Ck = C + int64_t(J.k) * nb * nb;
+  const double* e = estar + int64_t(J.k) * nb;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nb * nb; t += gridDim.x * blockDim.x) {
+    const int m = t / nb, n = t % nb;
+    if (fabs(e[m] - e[n]) > ctol) Ck[t] = make_double2(0.0, 0.0);
+  }
+}
+
+struct PairArgs { int64_t rowbase[kMaxSlices]; };
+
+// rows of (features, residual, target) for unconverged band j of each job
+__global__ void __launch_bounds__(256) k_pairs(DJobs jobs, PairArgs pa, const double2* __restrict__ X,
+                                               const double2* __restrict__ P, const double2* __restrict__ Rr,
+                                               const int32_t* __restrict__ unconv,
+                                               const double* __restrict__ tkin,
+                                               const double* __restrict__ theta,
+                                               const double* __restrict__ resn,
+                                               const double* __restrict__ kin_all,
+                                               const int64_t* __restrict__ goff, float* __restrict__ feat,
+                                               float* __restrict__ resid, float* __restrict__ target) {
+  __shared__ double red[16];
+  const DJob& J = jobs.j[blockIdx.y];
+  const int nb = jobs.nb, j = blockIdx.x;
+  if (j >= J.nu) return;
+  const int n = unconv[int64_t(J.k) * nb + j];
+  const double2* x = X + J.xoff + int64_t(n) * J.npw;
+  const double2* pn = P + J.xoff + int64_t(n) * J.npw;
+  const double2* r = Rr + J.xoff + int64_t(n) * J.npw;
+  const double* kin = kin_all + goff[J.k];
+  double pp = 0.0;
+  for (int g = threadIdx.x; g < J.npw; g += blockDim.x) pp += pn[g].x * pn[g].x + pn[g].y * pn[g].y;
+  // block reduction (same order on every thread)
+  for (int o = 32; o > 0; o >>= 1) pp += __shfl_down(pp, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = pp;
+  __syncthreads();
+  double s = 0.0;
+  for (int i = 0; i < int(blockDim.x >> 6); ++i) s += red[i];
+  const double ip = 1.0 / sqrt(s);
+  const double tn = tkin[int64_t(J.k) * nb + n];
+  const double th = theta[int64_t(J.k) * jobs.mb + n];
+  const double rs = sqrt(double(J.npw)) / resn[int64_t(J.k) * nb + n];
+  const int64_t row0 = pa.rowbase[blockIdx.y] + int64_t(j) * J.npw;
+  for (int g = threadIdx.x; g < J.npw; g += blockDim.x) {
+    const int64_t row = row0 + g;
+    const double kv = kin[g], x2 = kv / tn;
+    const double2 rv = r[g];
+    feat[row * 5 + 0] = float(x2);
+    feat[row * 5 + 1] = float(log1p(x2));
+    feat[row * 5 + 2] = float((th - tn) / tn);
+    feat[row * 5 + 3] = float(sqrt(rv.x * rv.x + rv.y * rv.y) * rs);
+    feat[row * 5 + 4] = float(kv);
+    resid[2 * row] = float(rv.x);
+    resid[2 * row + 1] = float(rv.y);
+    target[2 * row] = float(pn[g].x * ip - x[g].x);
+    target[2 * row + 1] = float(pn[g].y * ip - x[g].y);
+  }
+}
+
+static void training_pairs(qm_hpsi_plan* p, const void* xstar, const double* estar, double ctol,
+                           float* feat, float* resid, float* target, int32_t* band_ptr,
+                           int64_t cap_rows, int32_t cap_bands, int64_t* nrows, int32_t* nbands,
+                           hipStream_t s) {
+  DavState* d = p->dav;
+  QM_REQUIRE(d && d->ready, QM_E_STATE, "no Davidson state: call qm_davidson_step first");
+  QM_REQUIRE(xstar && estar && feat && resid && target && band_ptr && nrows && nbands, QM_E_ARG,
+             "NULL argument");
+  if (!d->estar) d->estar = dalloc<double>(size_t(d->nk) * d->nb);
+  std::vector<double> eh(size_t(d->nk) * d->nb, 0.0);
+  DJobs jobs{};
+  jobs.nb = d->nb;
+  jobs.mb = d->mb;
+  PairArgs pa{};
+  std::vector<int32_t> bp;
+  int64_t rows = 0;
+  std::vector<GemmCN> cn;
+  std::vector<GemmEX> ex;
+  const int64_t g0 = p->kinfo[d->k0].g_off;
+  for (int kk = d->k0; kk < d->k1; ++kk) {
+    for (int n = 0; n < d->nb; ++n) eh[size_t(kk) * d->nb + n] = estar[size_t(kk - d->k0) * d->nb + n];
+    if (d->done[kk]) continue;
+    int nu = 0;
+    for (int n = 0; n < d->nb; ++n)
+      if (!(d->h_resn[int64_t(kk) * d->nb + n] <= d->tol)) ++nu;
+    if (nu == 0) continue;
+    DJob j = make_job(p, d, kk);
+    j.nu = nu;
+    j.m = d->m[kk];
+    pa.rowbase[jobs.n] = rows;
+    for (int q = 0; q < nu; ++q) bp.push_back(int32_t(rows + int64_t(q) * j.npw));
+    rows += int64_t(nu) * j.npw;
+    jobs.j[jobs.n++] = j;
+    const double2* xs = reinterpret_cast<const double2*>(xstar) + int64_t(d->nb) * (p->kinfo[kk].g_off - g0);
+    double2* C = d->G + int64_t(kk) * d->nb * d->nb;
+    cn.push_back(GemmCN{xs, d->X + j.xoff, C, d->nb, d->nb, j.npw, j.npw, j.npw, d->nb});
+    ex.push_back(GemmEX{C, xs, d->TS + j.xoff, d->nb, j.npw, d->nb, d->nb, j.npw, j.npw});
+  }
+  bp.push_back(int32_t(rows));
+  QM_REQUIRE(rows <= cap_rows && int64_t(bp.size()) - 1 <= cap_bands, QM_E_ARG,
+             "training-pair buffers too small");
+  QM_REQUIRE(rows < (int64_t(1) << 31), QM_E_ARG, "too many rows");
+  *nrows = rows;
+  *nbands = int32_t(bp.size()) - 1;
+  QM_HIP(hipMemcpy(d->estar, eh.data(), sizeof(double) * eh.size(), hipMemcpyHostToDevice));
+  QM_HIP(hipMemcpy(band_ptr, bp.data(), sizeof(int32_t) * bp.size(), hipMemcpyHostToDevice));
+  if (jobs.n == 0) return;
+  zgemm_cn_batched(cn, 1.0, 0.0, d->work, d->work_bytes, s);
+  hipLaunchKernelGGL(k_mask_cluster, dim3(32, jobs.n), dim3(256), 0, s, jobs, d->G, d->estar, ctol);
+  QM_HIP(hipGetLastError());
+  zgemm_ex_batched(ex, 1.0, 0.0, s);
+  QM_HIP(hipMemcpyAsync(d->unconv, d->h_unconv, sizeof(int32_t) * d->nk * d->nb, hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_pairs, dim3(d->nb, jobs.n), dim3(256), 0, s, jobs, pa, d->X, d->TS, d->R, d->unconv,
+                     d->tkin, d->theta, d->resn, p->g.kin, d->goff, feat, resid, target);
+  QM_HIP(hipGetLastError());
+  QM_HIP(hipStreamSynchronize(s));
+}
 
 }  // namespace qm
 
@@ -478,6 +606,24 @@ qm_status qm_davidson_solve(qm_hpsi_plan* plan, int32_t k, void* psi, double* ei
     return QM_E_NOT_CONVERGED;
   }
   return st;
+}
+
+qm_status qm_dav_training_pairs(qm_hpsi_plan* plan, const void* x_star, const double* eig_star,
+                                double cluster_tol, float* feat, float* resid, float* target,
+                                int32_t* band_ptr, int64_t cap_rows, int32_t cap_bands, int64_t* nrows,
+                                int32_t* nbands, void* stream) {
+  if (!plan) return QM_E_ARG;
+  try {
+    training_pairs(plan, x_star, eig_star, cluster_tol > 0 ? cluster_tol : 1e-6, feat, resid, target,
+                   band_ptr, cap_rows, cap_bands, nrows, nbands, reinterpret_cast<hipStream_t>(stream));
+    return QM_OK;
+  } catch (const Error& e) {
+    plan->err = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    plan->err = e.what();
+    return QM_E_STATE;
+  }
 }
 
 }  // extern "C"
