@@ -1,0 +1,73 @@
+"""Learned preconditioner kernels on the GPU against the FP64 oracle (oracle/mlp.py).
+
+Bounds (float32 kernels vs float64 oracle): forward gains 1e-5 relative to the gain
+scale; loss within 1e-5; gradient within 1e-4 relative in norm (float32 accumulation over
+~1e3 rows per band); Adam update within 1e-6.  Training pairs: features, residuals and
+targets recomputed by the oracle from the returned Ritz vectors within 2e-5 relative."""
+import numpy as np
+import pytest
+
+from oracle import mlp as omlp
+
+pytestmark = pytest.mark.gpu
+
+
+def _data(seed=0, nb=6, npw=300):
+    rng = np.random.default_rng(seed)
+    kin = rng.uniform(0, 6, npw)
+    r = rng.standard_normal((nb, npw)) + 1j * rng.standard_normal((nb, npw))
+    delta = r * (1.0 / (1.0 + kin))[None, :] + 0.3 * (rng.standard_normal((nb, npw)) + 1j * rng.standard_normal((nb, npw)))
+    f = omlp.features(kin, r, rng.uniform(-0.5, 0.5, nb), rng.uniform(0.5, 1.5, nb)).reshape(-1, 5)
+    return f, r.reshape(-1), delta.reshape(-1), np.arange(nb + 1) * npw
+
+
+def _t(x, dt):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=dt)).cuda()
+
+
+def _c2(z):
+    return np.stack([z.real, z.imag], -1)
+
+
+def test_forward_and_grad_vs_oracle():
+    import torch
+    import paper_2308_07277_amd as qm
+    f, r, d, ptr = _data()
+    w = omlp.init_weights(2)
+    w[768:1024] = np.random.default_rng(3).standard_normal(256) * 0.2
+    w32 = w.astype(np.float32).astype(np.float64)   # compare on the float32-rounded weights
+    gain = torch.empty((f.shape[0], 2), dtype=torch.float32, device="cuda")
+    qm.qm_mlp_forward(_t(w32, np.float32), _t(f, np.float32), gain, f.shape[0])
+    ref = omlp.forward(w32, f.astype(np.float32).astype(np.float64))
+    got = gain.cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
+    grad = torch.empty(qm.QM_MLP_NPARAM, dtype=torch.float32, device="cuda")
+    L = qm.qm_mlp_loss_grad(_t(w32, np.float32), _t(f, np.float32), _t(_c2(r), np.float32),
+                            _t(_c2(d), np.float32), _t(ptr, np.int32), len(ptr) - 1, grad)
+    fr = f.astype(np.float32).astype(np.float64)
+    rr = _c2(r).astype(np.float32).astype(np.float64)
+    dd = _c2(d).astype(np.float32).astype(np.float64)
+    Lr, gr = omlp.loss_grad(w32, fr, rr[:, 0] + 1j * rr[:, 1], dd[:, 0] + 1j * dd[:, 1], ptr)
+    print("loss gpu", L, "oracle", Lr)
+    assert abs(L - Lr) <= 1e-5
+    gg = grad.cpu().numpy()
+    rel = np.linalg.norm(gg - gr) / np.linalg.norm(gr)
+    print("grad rel err", rel)
+    assert rel <= 1e-4
+
+
+def test_adam_vs_oracle():
+    import torch
+    import paper_2308_07277_amd as qm
+    rng = np.random.default_rng(5)
+    w = rng.standard_normal(qm.QM_MLP_NPARAM).astype(np.float32)
+    g = rng.standard_normal(qm.QM_MLP_NPARAM).astype(np.float32)
+    m = rng.standard_normal(qm.QM_MLP_NPARAM).astype(np.float32) * 0.1
+    v = np.abs(rng.standard_normal(qm.QM_MLP_NPARAM)).astype(np.float32) * 0.1
+    tw, tm, tv = _t(w, np.float32), _t(m, np.float32), _t(v, np.float32)
+    qm.qm_mlp_adam(tw, _t(g, np.float32), tm, tv, 3, lr=0.01)
+    wr, mr, vr = omlp.adam_step(w.astype(np.float64), g.astype(np.float64), m.astype(np.float64),
+                                v.astype(np.float64), 3, lr=0.01)
+    assert np.abs(tw.cpu().numpy() - wr).max() <= 1e-6
+    assert np.abs(tm.cpu().numpy() - mr).max() <= 1e-6
