@@ -140,6 +140,12 @@ const char *qm_last_error(const qm_hpsi_plan *plan);
 /* Change the precision qm_apply_h uses (reconverts beta; synchronous). */
 qm_status qm_hpsi_plan_set_precision(qm_hpsi_plan *plan, qm_prec prec, void *stream);
 
+/* Launch mode of qm_apply_h: enable = 1 (default) replays a hipGraph captured once per
+ * (k, nbnd, psi, hpsi, precision) - up to 8 are cached per plan, least recently used
+ * evicted - so repeated applications cost one graph launch; enable = 0 launches the
+ * kernels one by one.  Changing the mode drops the cached graphs. */
+qm_status qm_hpsi_plan_set_graphs(qm_hpsi_plan *plan, int32_t enable);
+
 /* ------------------------------------------------------------------ H|psi> */
 
 /* hpsi = H(k) psi for a block of bands (eq. KSHamMat + KB term).

@@ -69,17 +69,17 @@ void apply_h_slices(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* 
   }
 }
 
-// V(r) [i1][i2][i3] (float64, C order) -> plan layout [slot][i1][i2] scaled by 1/N_r, where
+// V(r) [i1][i2][i3] (float64, C order) -> plan layout [slot][i2][i1] scaled by 1/N_r, where
 // slot p = k1 + R1 k2 holds plane i3 = k2 + R2 k1 (order left by the inverse z-transform).
 __global__ void k_vplan(const double* __restrict__ v, double* __restrict__ v64, float* __restrict__ v32,
                         int N1, int N2, int N3, int R1, int R2, double scale) {
   const int64_t n = int64_t(N1) * N2 * N3;
   for (int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; t < n;
        t += int64_t(gridDim.x) * blockDim.x) {
-    const int i2 = int(t % N2);
-    const int64_t r = t / N2;
-    const int i1 = int(r % N1);
-    const int p = int(r / N1);
+    const int i1 = int(t % N1);
+    const int64_t r = t / N1;
+    const int i2 = int(r % N2);
+    const int p = int(r / N2);
     const int k1 = p % R1, k2 = p / R1;
     const int i3 = k2 + R2 * k1;
     const double val = v[(int64_t(i1) * N2 + i2) * N3 + i3] * scale;

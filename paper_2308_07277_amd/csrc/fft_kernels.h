@@ -122,8 +122,8 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int ns = a.nax_stride;
   cplx<R>* L = reinterpret_cast<cplx<R>*>(smem_raw);  // [NX positions][ns]
-  cplx<R>* X = L + NX * ns;                              // [NX positions][RG]
-  cplx<R>* tw = X + NX * RG;                             // [NX]
+  cplx<R>* X = L + NX * ns;                              // [RG rows][NX + 1]
+  cplx<R>* tw = X + (NX + 1) * RG;                       // [NX]
   int* col = reinterpret_cast<int*>(tw + NX);            // [NX]
   const int tid = threadIdx.x;
   const int N3 = a.N3;
@@ -181,13 +181,17 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
     for (int n1 = 0; n1 < R1; ++n1) L[(n1 + R1 * k2) * ns + ia] = y[n1];
   }
   __syncthreads();
-  // ---- x rows: inverse x, * V / N_r, forward x; active columns only written back
-  const R* V = reinterpret_cast<const R*>(a.vplan) + int64_t(p) * NX * NX;  // [i1][i2]
-  const int r = tid % RG, q = tid / RG;
+  // ---- x rows: inverse x, * V / N_r, forward x; active columns only written back.
+  // Lanes run over the intra-row index q first (consecutive LDS columns, consecutive V
+  // entries), then over the rows of the group; the row scratch X is row-major [r][NX + 1].
+  const R* V = reinterpret_cast<const R*>(a.vplan) + int64_t(p) * NX * NX;  // [i2][i1]
+  constexpr int NXP = NX + 1;
+  const int q = tid % R2, r = tid / R2;
   for (int r0 = 0; r0 < NX; r0 += RG) {
     const int i2 = r0 + r;
-    const bool act = (q < R2) && (i2 < NX);
+    const bool act = (r < RG) && (i2 < NX);
     const int lrow = act ? (i2 / R2) + R1 * (i2 % R2) : 0;
+    cplx<R>* Xr = X + r * NXP;
     if (act && q < R1) {
       cplx<R> x[R2];
 #pragma unroll
@@ -199,19 +203,17 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
 #pragma unroll
       for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tw[(q * k2) % NX]);
 #pragma unroll
-      for (int k2 = 0; k2 < R2; ++k2) X[(q + R1 * k2) * RG + r] = x[k2];
+      for (int k2 = 0; k2 < R2; ++k2) Xr[q + R1 * k2] = x[k2];
     }
     __syncthreads();
     cplx<R> y[R1];
     if (act) {
 #pragma unroll
-      for (int n1 = 0; n1 < R1; ++n1) y[n1] = X[(n1 + R1 * q) * RG + r];
+      for (int n1 = 0; n1 < R1; ++n1) y[n1] = Xr[n1 + R1 * q];
       Dft<R1, +1, R>::run(y);  // y[k1] is the row value at i1 = q + R2 k1
+      const R* Vrow = V + i2 * NX;
 #pragma unroll
-      for (int k1 = 0; k1 < R1; ++k1) {
-        const R v = V[(q + R2 * k1) * NX + i2];
-        y[k1] = cscale(y[k1], v);
-      }
+      for (int k1 = 0; k1 < R1; ++k1) y[k1] = cscale(y[k1], Vrow[q + R2 * k1]);
       Dft<R1, -1, R>::run(y);  // forward, factorisation (R2, R1): first pass over n2' = k1
 #pragma unroll
       for (int k2 = 1; k2 < R1; ++k2) {
@@ -222,13 +224,13 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
     __syncthreads();
     if (act) {
 #pragma unroll
-      for (int k2 = 0; k2 < R1; ++k2) X[(q + R2 * k2) * RG + r] = y[k2];
+      for (int k2 = 0; k2 < R1; ++k2) Xr[q + R2 * k2] = y[k2];
     }
     __syncthreads();
     if (act && q < R1) {
       cplx<R> z[R2];
 #pragma unroll
-      for (int n1 = 0; n1 < R2; ++n1) z[n1] = X[(n1 + R2 * q) * RG + r];
+      for (int n1 = 0; n1 < R2; ++n1) z[n1] = Xr[n1 + R2 * q];
       Dft<R2, -1, R>::run(z);  // natural output at i1 = q + R1 k1
 #pragma unroll
       for (int k1 = 0; k1 < R2; ++k1) {

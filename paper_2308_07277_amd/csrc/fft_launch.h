@@ -43,7 +43,7 @@ void launch_local_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* 
              "launch too large");
   const int NX = p->N1;
   const int r2x = fft_split_r2(NX);
-  const size_t smem_xy = sizeof(cplx<R>) * (size_t(NX) * a.nax_stride + size_t(NX) * (256 / r2x) + NX) +
+  const size_t smem_xy = sizeof(cplx<R>) * (size_t(NX) * a.nax_stride + size_t(NX + 1) * (256 / r2x) + NX) +
                          sizeof(int) * NX;
   QM_REQUIRE(smem_xy <= 160 * 1024, QM_E_SHAPE, "xy-plane does not fit in LDS for this grid/precision");
 #define QM_ZINV(n)                                                                          \

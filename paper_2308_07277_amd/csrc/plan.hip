@@ -34,6 +34,9 @@ static T* upload(const std::vector<T>& v, hipStream_t s) {
 static void plan_free(qm_hpsi_plan* p) {
   if (!p) return;
   davidson_free(p);
+  for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+  p->graphs.clear();
+  if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
   void* ptrs[] = {p->g.kinfo, p->g.ent_g, p->g.ent_sz, p->g.tile_ptr, p->g.stick_pos,
                   p->g.col_of_i1, p->g.kin, p->vplan64, p->vplan32, p->beta64, p->beta_lp,
                   p->dmat, p->drange, p->tw_z, p->tw_x, p->sbuf, p->proj_part, p->proj_q};
@@ -318,6 +321,45 @@ qm_status qm_hpsi_plan_set_precision(qm_hpsi_plan* plan, qm_prec prec, void* str
   })
 }
 
+// Replay a captured launch sequence for (k, nbnd, psi, hpsi, prec), capturing it on the
+// plan's own stream the first time (the caller's stream may be the null stream, which cannot
+// be captured).  Graphs hold kernel nodes only.
+static void apply_graph(qm_hpsi_plan* p, int k, const void* psi, void* hpsi, int nbnd, hipStream_t s) {
+  const int k0 = k < 0 ? 0 : k, k1 = k < 0 ? p->nk : k + 1;
+  for (auto& g : p->graphs)
+    if (g.k == k && g.nbnd == nbnd && g.prec == int(p->prec) && g.psi == psi && g.hpsi == hpsi) {
+      g.last_use = ++p->graph_clock;
+      QM_HIP(hipGraphLaunch(g.exec, s));
+      return;
+    }
+  if (!p->capture_stream) QM_HIP(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
+  convert_beta(p, p->prec, s);                     // any one-time conversion happens eagerly
+  QM_HIP(hipStreamSynchronize(s));
+  hipGraph_t graph = nullptr;
+  QM_HIP(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
+  try {
+    apply_h_slices(p, contiguous_slices(p, k0, k1, nbnd), psi, hpsi, p->capture_stream, p->prec);
+  } catch (...) {
+    (void)hipStreamEndCapture(p->capture_stream, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  QM_HIP(hipStreamEndCapture(p->capture_stream, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  QM_HIP(ie);
+  if (p->graphs.size() >= 8) {   // evict the least recently used entry
+    size_t lru = 0;
+    for (size_t i = 1; i < p->graphs.size(); ++i)
+      if (p->graphs[i].last_use < p->graphs[lru].last_use) lru = i;
+    (void)hipGraphExecDestroy(p->graphs[lru].exec);
+    p->graphs.erase(p->graphs.begin() + lru);
+  }
+  p->graphs.push_back({k, nbnd, int(p->prec), psi, hpsi, exec, ++p->graph_clock});
+  QM_HIP(hipGraphLaunch(exec, s));
+}
+
 qm_status qm_apply_h(qm_hpsi_plan* plan, int32_t k, const void* psi, void* hpsi, int32_t nbnd,
                      void* stream) {
   if (!plan) return QM_E_ARG;
@@ -328,8 +370,19 @@ qm_status qm_apply_h(qm_hpsi_plan* plan, int32_t k, const void* psi, void* hpsi,
     QM_REQUIRE(k >= -1 && k < plan->nk, QM_E_ARG, "k out of range");
     const int k0 = k < 0 ? 0 : k, k1 = k < 0 ? plan->nk : k + 1;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    apply_h_slices(plan, contiguous_slices(plan, k0, k1, nbnd), psi, hpsi, s, plan->prec);
+    if (plan->use_graphs && k1 - k0 <= kMaxSlices)
+      apply_graph(plan, k, psi, hpsi, nbnd, s);
+    else
+      apply_h_slices(plan, contiguous_slices(plan, k0, k1, nbnd), psi, hpsi, s, plan->prec);
   })
+}
+
+qm_status qm_hpsi_plan_set_graphs(qm_hpsi_plan* plan, int32_t enable) {
+  if (!plan) return QM_E_ARG;
+  plan->use_graphs = enable ? 1 : 0;
+  for (auto& g : plan->graphs) (void)hipGraphExecDestroy(g.exec);
+  plan->graphs.clear();
+  return QM_OK;
 }
 
 qm_status qm_apply_h_timed(qm_hpsi_plan* plan, int32_t k, const void* psi, void* hpsi,

@@ -87,7 +87,7 @@ struct qm_hpsi_plan {
   double cell[9] = {0}, recip[9] = {0};
   std::vector<qm::KInfo> kinfo;   // host copy
   qm::GTables g;
-  void* vplan64 = nullptr;        // float64 [N3 slot][N1][N2], scaled by 1/N_r
+  void* vplan64 = nullptr;        // float64 [N3 slot][N2][N1], scaled by 1/N_r
   void* vplan32 = nullptr;        // float32, same layout
   void* beta64 = nullptr;         // c128 copy of beta
   void* beta_lp = nullptr;        // c64 (FP32) or bf16 pairs (MIXED) copy, per prec
@@ -104,6 +104,18 @@ struct qm_hpsi_plan {
   int32_t proj_splits = 1;
   std::string err;
   qm::DavState* dav = nullptr;
+  // captured qm_apply_h launch sequences (kernel nodes only), replayed on the caller's stream
+  struct GraphEntry {
+    int32_t k, nbnd, prec;
+    const void* psi;
+    void* hpsi;
+    hipGraphExec_t exec;
+    uint64_t last_use;
+  };
+  std::vector<GraphEntry> graphs;
+  uint64_t graph_clock = 0;
+  hipStream_t capture_stream = nullptr;
+  int32_t use_graphs = 1;
 };
 
 namespace qm {

@@ -156,3 +156,28 @@ def test_c2_reduced_precision(prec, bound):
         worst = max(worst, err.max())
     print(f"c2 prec={prec} max per-band rel err {worst:.3e}")
     assert worst <= bound
+
+
+def test_graph_replays_match_eager():
+    """The captured launch sequence, replayed several times on new data in the same buffers
+    with eager work and synchronisations in between, matches the one-by-one launches."""
+    import torch
+    import paper_2308_07277_amd as qm
+    w = workload.make_workload("c2")
+    plan, a = make_plan(w, w.nbnd)
+    psi = torch.empty(int(w.nbnd * w.npw.sum()), dtype=torch.complex128, device="cuda")
+    hg = torch.empty_like(psi)
+    he = torch.empty_like(psi)
+    for rep in range(4):
+        flat, _ = psi_block(w, w.nbnd, purpose=10 + rep)
+        psi.copy_(torch.from_numpy(flat))
+        qm.qm_hpsi_plan_set_graphs(plan, 1) if rep == 0 else None
+        qm.qm_apply_h(plan, -1, psi, hg, w.nbnd)           # graph (captured on rep 0)
+        torch.cuda.synchronize()
+        _ = (psi.abs() ** 2).sum().item()                     # eager work in between
+        plan2 = plan
+        qm.qm_hpsi_plan_set_graphs(plan2, 0)
+        qm.qm_apply_h(plan2, -1, psi, he, w.nbnd)          # eager launches
+        torch.cuda.synchronize()
+        qm.qm_hpsi_plan_set_graphs(plan2, 1)
+        assert torch.equal(hg, he), rep
