@@ -159,25 +159,23 @@ def test_c2_reduced_precision(prec, bound):
 
 
 def test_graph_replays_match_eager():
-    """The captured launch sequence, replayed several times on new data in the same buffers
-    with eager work and synchronisations in between, matches the one-by-one launches."""
+    """One captured launch sequence, replayed on new data in the same buffers with eager work
+    and synchronisations in between, matches a second plan that launches kernel by kernel."""
     import torch
     import paper_2308_07277_amd as qm
     w = workload.make_workload("c2")
-    plan, a = make_plan(w, w.nbnd)
+    plan_g, a = make_plan(w, w.nbnd)
+    plan_e, _ = make_plan(w, w.nbnd, arrays=a)
+    qm.qm_hpsi_plan_set_graphs(plan_e, 0)
     psi = torch.empty(int(w.nbnd * w.npw.sum()), dtype=torch.complex128, device="cuda")
     hg = torch.empty_like(psi)
     he = torch.empty_like(psi)
     for rep in range(4):
         flat, _ = psi_block(w, w.nbnd, purpose=10 + rep)
         psi.copy_(torch.from_numpy(flat))
-        qm.qm_hpsi_plan_set_graphs(plan, 1) if rep == 0 else None
-        qm.qm_apply_h(plan, -1, psi, hg, w.nbnd)           # graph (captured on rep 0)
+        qm.qm_apply_h(plan_g, -1, psi, hg, w.nbnd)    # captured on rep 0, replayed after
         torch.cuda.synchronize()
-        _ = (psi.abs() ** 2).sum().item()                     # eager work in between
-        plan2 = plan
-        qm.qm_hpsi_plan_set_graphs(plan2, 0)
-        qm.qm_apply_h(plan2, -1, psi, he, w.nbnd)          # eager launches
+        _ = (psi.abs() ** 2).sum().item()              # eager work in between
+        qm.qm_apply_h(plan_e, -1, psi, he, w.nbnd)
         torch.cuda.synchronize()
-        qm.qm_hpsi_plan_set_graphs(plan2, 1)
         assert torch.equal(hg, he), rep
