@@ -210,6 +210,9 @@ def main():
     del beta, vloc
     hpsi = torch.empty_like(psi)
     bands = w.nk * w.nbnd
+    t_tune = time.perf_counter()
+    qm.qm_hpsi_plan_autotune(plan, w.nbnd)
+    t_tune = time.perf_counter() - t_tune
 
     def measure(prec):
         qm.qm_hpsi_plan_set_precision(plan, PREC_CODE[prec])
@@ -272,7 +275,7 @@ def main():
                                f"{w.nbnd} bands, {w.nproj} projectors, all k and bands per step",
                    "npw": [int(x) for x in w.npw], "nstick": nst, "prec": args.prec},
         "stages_ms": stages, "stage_rates": stage_rates, "roofline": roof,
-        "other_precisions": others,
+        "other_precisions": others, "autotune_s": t_tune,
     }
     plan.close()
     del psi, hpsi

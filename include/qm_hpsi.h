@@ -146,6 +146,12 @@ qm_status qm_hpsi_plan_set_precision(qm_hpsi_plan *plan, qm_prec prec, void *str
  * kernels one by one.  Changing the mode drops the cached graphs. */
 qm_status qm_hpsi_plan_set_graphs(qm_hpsi_plan *plan, int32_t enable);
 
+/* Autotune the launch parameters of the projector GEMM (split-K count) for nbnd bands in
+ * every precision, timing the candidates with HIP events on stream; the choice is kept in
+ * the plan.  If the environment variable QM_AUTOTUNE_CACHE names a file, choices are read
+ * from and written to it (one JSON object keyed by problem shape).  Synchronous. */
+qm_status qm_hpsi_plan_autotune(qm_hpsi_plan *plan, int32_t nbnd, void *stream);
+
 /* ------------------------------------------------------------------ H|psi> */
 
 /* hpsi = H(k) psi for a block of bands (eq. KSHamMat + KB term).

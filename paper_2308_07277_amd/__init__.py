@@ -80,6 +80,7 @@ def _load():
         "qm_hpsi_plan_destroy": [_P],
         "qm_hpsi_plan_set_precision": [_P, i32, _P],
         "qm_hpsi_plan_set_graphs": [_P, i32],
+        "qm_hpsi_plan_autotune": [_P, i32, _P],
         "qm_apply_h": [_P, i32, _P, _P, i32, _P],
         "qm_apply_h_timed": [_P, i32, _P, _P, i32, _P, _P],
         "qm_davidson_step": [_P, i32, _P, _P, _P, i32, ctypes.POINTER(qm_dav_opts), _P, _P],
@@ -193,6 +194,10 @@ def qm_hpsi_plan_create(cell, grid, k_cart, npw, miller, nbnd_max, nproj, vloc_r
 
 def qm_hpsi_plan_set_precision(plan, prec, stream=None):
     _check(_load().qm_hpsi_plan_set_precision(plan.handle, int(prec), _stream(stream)), plan.handle)
+
+
+def qm_hpsi_plan_autotune(plan, nbnd, stream=None):
+    _check(_load().qm_hpsi_plan_autotune(plan.handle, int(nbnd), _stream(stream)), plan.handle)
 
 
 def qm_hpsi_plan_set_graphs(plan, enable):

@@ -486,7 +486,8 @@ int64_t zgemm_cn_work_bytes(const std::vector<GemmCN>& probs) {
 }
 
 void zgemm_cn_batched(const std::vector<GemmCN>& probs, double alpha, double beta_c, void* work,
-                      int64_t work_bytes, hipStream_t s, StageEvents* ev, int stage0, int lp) {
+                      int64_t work_bytes, hipStream_t s, StageEvents* ev, int stage0, int lp,
+                      int force_split) {
   for (size_t base = 0; base < probs.size(); base += MAXP) {
     const size_t n = std::min<size_t>(MAXP, probs.size() - base);
     std::vector<GemmCN> sub(probs.begin() + base, probs.begin() + base + n);
@@ -500,7 +501,7 @@ void zgemm_cn_batched(const std::vector<GemmCN>& probs, double alpha, double bet
     }
     int64_t mn = 0;
     for (const GemmCN& g : sub) mn += int64_t(g.M) * g.N;
-    int nsplit = choose_splits(tiles, maxK);
+    int nsplit = force_split > 0 ? force_split : choose_splits(tiles, maxK);
     while (nsplit > 1 && int64_t(nsplit) * mn * int64_t(sizeof(cplx<double>)) > work_bytes) nsplit /= 2;
     int64_t blk = 0, woff = 0, e0 = 0;
     for (size_t i = 0; i < n; ++i) {

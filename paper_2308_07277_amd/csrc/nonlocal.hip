@@ -48,7 +48,7 @@ void launch_nonlocal_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const voi
     ex.push_back(GemmEX{Q + off, bk, hk, x.nb, ki.npw, np, x.nb, ki.npw, ki.npw});
     off += int64_t(np) * x.nb;
   }
-  zgemm_cn_batched(cn, 1.0, 0.0, p->proj_part, p->proj_part_bytes, s, ev, 3, lp);
+  zgemm_cn_batched(cn, 1.0, 0.0, p->proj_part, p->proj_part_bytes, s, ev, 3, lp, p->tuned_splits[lp]);
   // D acts on each slice's [np][nb] block; blocks are packed back to back
   int64_t base = 0;
   for (const KSlice& x : sl) {
@@ -83,3 +83,109 @@ void convert_beta(qm_hpsi_plan* p, qm_prec prec, hipStream_t s) {
 }
 
 }  // namespace qm
+
+// ---------------------------------------------------------------- autotuning
+#include <cstdio>
+#include <cstdlib>
+#include <fstream>
+#include <map>
+#include <sstream>
+
+namespace qm {
+
+static std::map<std::string, int> load_cache(const char* path) {
+  std::map<std::string, int> m;
+  if (!path) return m;
+  std::ifstream f(path);
+  std::string line;
+  while (std::getline(f, line)) {  // one "key": value per line
+    const size_t a = line.find('"'), b = line.find('"', a + 1), c = line.find(':', b);
+    if (a == std::string::npos || b == std::string::npos || c == std::string::npos) continue;
+    m[line.substr(a + 1, b - a - 1)] = std::atoi(line.c_str() + c + 1);
+  }
+  return m;
+}
+
+static void save_cache(const char* path, const std::map<std::string, int>& m) {
+  if (!path) return;
+  std::ofstream f(path);
+  f << "{\n";
+  size_t i = 0;
+  for (const auto& kv : m) f << "  \"" << kv.first << "\": " << kv.second << (++i < m.size() ? ",\n" : "\n");
+  f << "}\n";
+}
+
+// time the projector GEMM of every k at nbnd bands for each split-K candidate
+void autotune_projection(qm_hpsi_plan* p, int nbnd, hipStream_t s, int lp, double* best_ms) {
+  if (p->nproj == 0) return;
+  if (lp != 0) convert_beta(p, lp == 1 ? QM_PREC_FP32 : QM_PREC_MIXED, s);
+  std::ostringstream key;
+  key << "cn/" << lp << "/" << p->nproj << "x" << nbnd << "/" << p->nk << "/" << p->npw_total;
+  const char* path = std::getenv("QM_AUTOTUNE_CACHE");
+  std::map<std::string, int> cache = load_cache(path);
+  auto it = cache.find(key.str());
+  if (it != cache.end()) {
+    p->tuned_splits[lp] = it->second;
+    if (best_ms) *best_ms = -1.0;
+    return;
+  }
+  void* psi = nullptr;
+  QM_HIP(hipMalloc(&psi, size_t(nbnd) * size_t(p->npw_total) * 16));
+  QM_HIP(hipMemsetAsync(psi, 0, size_t(nbnd) * size_t(p->npw_total) * 16, s));
+  double2* P = reinterpret_cast<double2*>(p->proj_q);
+  std::vector<GemmCN> cn;
+  int64_t off = 0;
+  for (int k = 0; k < p->nk; ++k) {
+    const KInfo& ki = p->kinfo[k];
+    const char* bbase = reinterpret_cast<const char*>(lp == 0 ? p->beta64 : p->beta_lp);
+    const size_t esz = lp == 0 ? 16 : (lp == 1 ? 8 : 4);
+    cn.push_back(GemmCN{bbase + size_t(ki.beta_off) * esz,
+                        reinterpret_cast<const double2*>(psi) + int64_t(nbnd) * ki.g_off, P + off,
+                        p->nproj, nbnd, ki.npw, ki.npw, ki.npw, nbnd});
+    off += int64_t(p->nproj) * nbnd;
+  }
+  hipEvent_t e0, e1;
+  QM_HIP(hipEventCreate(&e0));
+  QM_HIP(hipEventCreate(&e1));
+  int best = 0;
+  double bms = 1e30;
+  for (int sp = 1; sp <= 64; sp *= 2) {
+    if (int64_t(sp) * off * 16 > p->proj_part_bytes) break;
+    zgemm_cn_batched(cn, 1.0, 0.0, p->proj_part, p->proj_part_bytes, s, nullptr, 0, lp, sp);  // warm
+    QM_HIP(hipEventRecord(e0, s));
+    for (int r = 0; r < 3; ++r)
+      zgemm_cn_batched(cn, 1.0, 0.0, p->proj_part, p->proj_part_bytes, s, nullptr, 0, lp, sp);
+    QM_HIP(hipEventRecord(e1, s));
+    QM_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    QM_HIP(hipEventElapsedTime(&ms, e0, e1));
+    if (ms / 3.0 < bms) {
+      bms = ms / 3.0;
+      best = sp;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  (void)hipFree(psi);
+  p->tuned_splits[lp] = best;
+  if (best_ms) *best_ms = bms;
+  cache[key.str()] = best;
+  save_cache(path, cache);
+}
+
+}  // namespace qm
+
+extern "C" qm_status qm_hpsi_plan_autotune(qm_hpsi_plan* plan, int32_t nbnd, void* stream) {
+  if (!plan) return QM_E_ARG;
+  try {
+    QM_REQUIRE(nbnd >= 1 && nbnd <= plan->nbnd_max, QM_E_ARG, "need 1 <= nbnd <= nbnd_max");
+    for (auto& g : plan->graphs) (void)hipGraphExecDestroy(g.exec);
+    plan->graphs.clear();
+    for (int lp = 0; lp < 3; ++lp)
+      qm::autotune_projection(plan, nbnd, reinterpret_cast<hipStream_t>(stream), lp, nullptr);
+    return QM_OK;
+  } catch (const qm::Error& e) {
+    plan->err = e.what();
+    return e.code;
+  }
+}

@@ -102,6 +102,7 @@ struct qm_hpsi_plan {
   int64_t proj_part_bytes = 0;
   void* proj_q = nullptr;         // Q = D P, c128 [nk][nproj][nbnd_max] or float in lower precisions
   int32_t proj_splits = 1;
+  int32_t tuned_splits[3] = {0, 0, 0};  // projector split-K chosen by the autotuner, per precision
   std::string err;
   qm::DavState* dav = nullptr;
   // captured qm_apply_h launch sequences (kernel nodes only), replayed on the caller's stream
@@ -149,7 +150,7 @@ struct GemmEX {
 };
 void zgemm_cn_batched(const std::vector<GemmCN>& probs, double alpha, double beta_c,
                       void* work, int64_t work_bytes, hipStream_t s, StageEvents* ev = nullptr,
-                      int stage0 = 0, int lp = 0);
+                      int stage0 = 0, int lp = 0, int force_split = 0);
 int64_t zgemm_cn_work_bytes(const std::vector<GemmCN>& probs);
 void zgemm_ex_batched(const std::vector<GemmEX>& probs, double alpha, double beta_y,
                       hipStream_t s, int lp = 0);

@@ -179,3 +179,24 @@ def test_graph_replays_match_eager():
         qm.qm_apply_h(plan_e, -1, psi, he, w.nbnd)
         torch.cuda.synchronize()
         assert torch.equal(hg, he), rep
+
+
+def test_autotune_keeps_results(tmp_path, monkeypatch):
+    """Autotuning changes only the split-K schedule: results stay within float64 rounding
+    and a second plan reads the choice back from the cache file."""
+    import json
+    import torch
+    import paper_2308_07277_amd as qm
+    monkeypatch.setenv("QM_AUTOTUNE_CACHE", str(tmp_path / "tune.json"))
+    w = workload.make_workload("c2")
+    plan, a = make_plan(w, w.nbnd)
+    flat, per = psi_block(w, w.nbnd)
+    before = _run(plan, w, w.nbnd, psi_flat=flat)
+    qm.qm_hpsi_plan_autotune(plan, w.nbnd)
+    after = _run(plan, w, w.nbnd, psi_flat=flat)
+    assert np.abs(after - before).max() <= 1e-13 * np.abs(before).max()
+    cache = json.load(open(tmp_path / "tune.json"))
+    assert any(k.startswith("cn/0/") for k in cache)
+    plan2, _ = make_plan(w, w.nbnd, arrays=a)
+    qm.qm_hpsi_plan_autotune(plan2, w.nbnd)          # served from the cache file
+    assert np.abs(_run(plan2, w, w.nbnd, psi_flat=flat) - after).max() == 0.0
