@@ -138,7 +138,7 @@ def train_preconditioner(steps=400):
                      "loss_final": l_final}
 
 
-def davidson_run(name, weights=None, tol=1e-8, max_basis_factor=4, switch_resid=1e-4):
+def davidson_run(name, weights=None, tol=1e-8, max_basis_factor=4, switch_resid=1e-3):
     """Block Davidson from a seeded random start to max residual <= tol over every k-point
     and band: arm A float64 H + Teter; arm B float32-FFT/bf16-GEMM H while the residual is
     above switch_resid (float64 H below) + the learned preconditioner."""
@@ -150,11 +150,13 @@ def davidson_run(name, weights=None, tol=1e-8, max_basis_factor=4, switch_resid=
     start = torch.cat([torch.from_numpy(w.psi(ik, purpose=2).reshape(-1)) for ik in range(w.nk)]).cuda()
     arms = {}
     eigs = {}
-    cfgs = [("fp64+teter", dict(precond=qm.QM_PRECOND_TETER, switch_resid=0.0))]
+    cfgs = [("fp64+teter", dict(precond=qm.QM_PRECOND_TETER, switch_resid=0.0)),
+            ("mixed+teter", dict(precond=qm.QM_PRECOND_TETER, switch_resid=switch_resid))]
     if weights is not None:
+        cfgs.append(("fp64+mlp", dict(precond=qm.QM_PRECOND_MLP, mlp_weights=weights,
+                                      switch_resid=0.0)))
         cfgs.append(("mixed+mlp", dict(precond=qm.QM_PRECOND_MLP, mlp_weights=weights,
                                        switch_resid=switch_resid)))
-        cfgs.append(("mixed+teter", dict(precond=qm.QM_PRECOND_TETER, switch_resid=switch_resid)))
     for arm, kw in cfgs:
         psi = start.clone()
         torch.cuda.synchronize()

@@ -39,6 +39,7 @@ struct DavState {
   std::vector<int> m, it, done;
   int64_t n_hpsi = 0, n_hpsi_lowp = 0;
   double tol = 1e-8;
+  std::vector<double> hist;  // max residual per step (precision-ladder stagnation test)
   double* estar = nullptr;   // converged eigenvalues for training-pair generation
   double t_hpsi = 0, t_sub = 0, t_eig = 0;
   hipEvent_t ev[6] = {};
@@ -112,6 +113,10 @@ static DavState* dav_create(qm_hpsi_plan* p, int k0, int k1, int nb, int mb) {
     QM_HIP(hipHostMalloc(reinterpret_cast<void**>(&d->h_unconv), nk * nb * sizeof(int32_t)));
     QM_HIP(hipHostMalloc(reinterpret_cast<void**>(&d->h_info), nk * sizeof(int32_t)));
     for (hipEvent_t& e : d->ev) QM_HIP(hipEventCreate(&e));
+    const void* big[] = {reinterpret_cast<const void*>(&k_tridiag), reinterpret_cast<const void*>(&k_tridiag_eig),
+                         reinterpret_cast<const void*>(&k_backtransform)};
+    for (const void* f : big)
+      QM_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
     d->m.assign(nk, 0);
     d->it.assign(nk, 0);
     d->done.assign(nk, 0);
@@ -202,8 +207,14 @@ static void rayleigh_ritz(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipSt
   hipLaunchKernelGGL(k_tridiag, dim3(jobs.n), dim3(1024), size_t(2) * d->mb * sizeof(double2), s,
                      jobs, d->Aw, d->d, d->e, d->tau);
   QM_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_tridiag_eig, dim3(jobs.n), dim3(1024), size_t(d->mb) * sizeof(double2), s,
-                     jobs, d->Aw, d->d, d->e, d->tau, d->theta, d->Z, d->yw, d->fw);
+  hipLaunchKernelGGL(k_tridiag_eig, dim3(jobs.n), dim3(1024), size_t(2) * d->mb * sizeof(double), s,
+                     jobs, d->d, d->e, d->theta, d->yw, d->fw);
+  QM_HIP(hipGetLastError());
+  // Z slice + one reflector must fit in the 160 KiB of LDS
+  const int cols = std::max(1, std::min(8, int((160 * 1024 - 1024) / (16 * int64_t(d->mb))) - 1));
+  hipLaunchKernelGGL(k_backtransform, dim3((d->nb + cols - 1) / cols, jobs.n), dim3(256),
+                     size_t(d->mb) * (cols + 1) * sizeof(double2), s, jobs, d->Aw, d->tau, d->yw, d->Z,
+                     cols);
   QM_HIP(hipGetLastError());
   QM_HIP(hipEventRecord(d->ev[3], s));
   std::vector<GemmEX> ex;
@@ -343,7 +354,12 @@ static qm_status dav_step(qm_hpsi_plan* p, int k, void* psi, double* eig, double
     double maxres = 0.0;
     for (int kk = k0; kk < k1; ++kk)
       for (int n = 0; n < nb; ++n) maxres = std::max(maxres, d->h_resn[int64_t(kk) * nb + n]);
-    const bool refresh = d->lowp && o && maxres <= o->switch_resid;
+    // switch when below switch_resid, or when the reduced-precision H stops making progress
+    // (max residual not down by 20% over the last four iterations)
+    bool stagnant = false;
+    const size_t nh = d->hist.size();
+    if (nh >= 5) stagnant = d->hist[nh - 1] > 0.8 * d->hist[nh - 5];
+    const bool refresh = d->lowp && o && (maxres <= o->switch_resid || stagnant);
     if (refresh) {
       d->lowp = false;
       for (int kk = k0; kk < k1; ++kk) {
@@ -411,6 +427,8 @@ static qm_status dav_step(qm_hpsi_plan* p, int k, void* psi, double* eig, double
   StepResult r;
   d->tol = tol;
   collect(p, d, tol, r);
+  if (fresh || r.max_res < 0) d->hist.clear();
+  d->hist.push_back(r.max_res);
   write_outputs(p, d, psi, eig, resnorm, s);
   if (n_unconv) *n_unconv = r.n_unconv;
   if (r.nan) throw Error(QM_E_NAN, "non-finite residual norm");

@@ -26,8 +26,10 @@ namespace qm {
 __global__ void k_hs_fill(DJobs jobs, double2* Hs);
 __global__ void k_hs_copy(DJobs jobs, const double2* Hs, double2* Aw);
 __global__ void k_tridiag(DJobs jobs, double2* Aw, double* dd, double* ee, double2* tau);
-__global__ void k_tridiag_eig(DJobs jobs, const double2* Aw, const double* dd, const double* ee,
-                              const double2* tau, double* theta, double2* Zout, double* yw, double* fw);
+__global__ void k_tridiag_eig(DJobs jobs, const double* dd, const double* ee, double* theta,
+                              double* yw, double* fw);
+__global__ void k_backtransform(DJobs jobs, const double2* Aw, const double2* tau, const double* yw,
+                                double2* Zout, int cols);
 __global__ void k_chol_inv(DJobs jobs, double2* Gm, double2* Wm, int32_t* info);
 __global__ void k_residual(DJobs jobs, const double2* X, const double2* HX, double2* Rr,
                            const double* theta, const double* kin_all, const int64_t* goff,

@@ -188,89 +188,39 @@ __device__ int sturm_count(const double* d, const double* e, int m, double x, do
   return c;
 }
 
-// LU with partial pivoting of the tridiagonal T - lam I (rows swapped pairwise).
-// U has diagonal D, superdiagonals U1, U2; L has multipliers M; P[i] = 1 if rows i, i+1 swapped.
-__device__ void trid_lu(const double* d, const double* e, int m, double lam, double tiny,
-                        double* D, double* U1, double* U2, double* M, double* P) {
-  for (int i = 0; i < m; ++i) {
-    D[i] = d[i] - lam;
-    U1[i] = i < m - 1 ? e[i] : 0.0;
-    M[i] = i < m - 1 ? e[i] : 0.0;   // subdiagonal before elimination
-    U2[i] = 0.0;
-    P[i] = 0.0;
-  }
-  for (int i = 0; i < m - 1; ++i) {
-    if (fabs(D[i]) >= fabs(M[i])) {
-      const double f = D[i] != 0.0 ? M[i] / D[i] : 0.0;
-      M[i] = f;
-      D[i + 1] -= f * U1[i];
-    } else {
-      const double f = D[i] / M[i];
-      D[i] = M[i];
-      M[i] = f;
-      const double t = U1[i];
-      U1[i] = D[i + 1];
-      D[i + 1] = t - f * D[i + 1];
-      if (i < m - 2) {
-        U2[i] = U1[i + 1];
-        U1[i + 1] = -f * U1[i + 1];
-      }
-      P[i] = 1.0;
-    }
-  }
-  for (int i = 0; i < m; ++i)
-    if (fabs(D[i]) < tiny) D[i] = D[i] < 0.0 ? -tiny : tiny;
-}
-
-__device__ void trid_solve(int m, const double* D, const double* U1, const double* U2,
-                           const double* M, const double* P, double* b) {
-  for (int i = 0; i < m - 1; ++i) {
-    if (P[i] == 0.0) {
-      b[i + 1] -= M[i] * b[i];
-    } else {
-      const double t = b[i];
-      b[i] = b[i + 1];
-      b[i + 1] = t - M[i] * b[i];
-    }
-  }
-  b[m - 1] /= D[m - 1];
-  if (m > 1) b[m - 2] = (b[m - 2] - U1[m - 2] * b[m - 1]) / D[m - 2];
-  for (int i = m - 3; i >= 0; --i) b[i] = (b[i] - U1[i] * b[i + 1] - U2[i] * b[i + 2]) / D[i];
-}
-
-// theta[k][0..nb) ascending; Z[k][i][n] (row i < m, column n < nb).
-// yw: [k][nb][mb] real eigenvectors of T; fw: [k][nb][5][mb] LU workspace.
-__global__ void __launch_bounds__(1024) k_tridiag_eig(DJobs jobs, const double2* __restrict__ Aw,
-                                                      const double* __restrict__ dd,
+// theta[k][0..nb) ascending and real eigenvectors Y[k][i][n] of the tridiagonal (i < m,
+// n < nb; n fastest so the per-eigenvector recurrences of a wave are coalesced).
+// fw: [k][5][mb][nb] LU workspace, same interleaving.  d and e are staged in LDS.
+__global__ void __launch_bounds__(1024) k_tridiag_eig(DJobs jobs, const double* __restrict__ dd,
                                                       const double* __restrict__ ee,
-                                                      const double2* __restrict__ tau,
                                                       double* __restrict__ theta,
-                                                      double2* __restrict__ Zout,
                                                       double* __restrict__ yw,
                                                       double* __restrict__ fw) {
-  extern __shared__ double2 sh[];  // [mb] reflector staging
+  extern __shared__ double sde[];  // d [mb], e [mb]
   const DJob& J = jobs.j[blockIdx.x];
   const int mb = jobs.mb, nb = jobs.nb, m = J.m;
-  const double2* A = Aw + int64_t(J.k) * mb * mb;
-  const double* d = dd + int64_t(J.k) * mb;
-  const double* e = ee + int64_t(J.k) * mb;
-  const double2* tk = tau + int64_t(J.k) * mb;
+  double* sd = sde;
+  double* se = sde + mb;
   double* th = theta + int64_t(J.k) * mb;
-  double2* Z = Zout + int64_t(J.k) * mb * nb;
   double* Y = yw + int64_t(J.k) * nb * mb;
   double* F = fw + int64_t(J.k) * nb * 5 * mb;
   __shared__ double s_lo, s_hi, s_norm;
   __shared__ int s_cl[1025];
   __shared__ int s_ncl;
   const int tid = threadIdx.x;
+  for (int i = tid; i < m; i += blockDim.x) {
+    sd[i] = dd[int64_t(J.k) * mb + i];
+    se[i] = ee[int64_t(J.k) * mb + i];
+  }
+  __syncthreads();
   const int nwant = min(nb, m);
   if (tid == 0) {
     double lo = 1e300, hi = -1e300, nrm = 0.0;
     for (int i = 0; i < m; ++i) {
-      const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i < m - 1 ? fabs(e[i]) : 0.0);
-      lo = fmin(lo, d[i] - r);
-      hi = fmax(hi, d[i] + r);
-      nrm = fmax(nrm, fabs(d[i]) + r);
+      const double r = (i > 0 ? fabs(se[i - 1]) : 0.0) + (i < m - 1 ? fabs(se[i]) : 0.0);
+      lo = fmin(lo, sd[i] - r);
+      hi = fmax(hi, sd[i] + r);
+      nrm = fmax(nrm, fabs(sd[i]) + r);
     }
     s_lo = lo;
     s_hi = hi;
@@ -286,7 +236,7 @@ __global__ void __launch_bounds__(1024) k_tridiag_eig(DJobs jobs, const double2*
       const double mid = 0.5 * (lo + hi);
       if (mid <= lo || mid >= hi) break;
       if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi))) break;
-      if (sturm_count(d, e, m, mid, pivmin) <= n) lo = mid;
+      if (sturm_count(sd, se, m, mid, pivmin) <= n) lo = mid;
       else hi = mid;
     }
     th[n] = 0.5 * (lo + hi);
@@ -303,6 +253,7 @@ __global__ void __launch_bounds__(1024) k_tridiag_eig(DJobs jobs, const double2*
   }
   __syncthreads();
   const double tiny = eps * nrm;
+  const int64_t st = nb;  // stride between consecutive elements of one vector
   for (int c = tid; c < s_ncl; c += blockDim.x) {
     const int n0 = s_cl[c], n1 = s_cl[c + 1];
     double prev = -1e300;
@@ -310,55 +261,131 @@ __global__ void __launch_bounds__(1024) k_tridiag_eig(DJobs jobs, const double2*
       double lam = th[n];
       if (n > n0 && lam - prev < 10.0 * tiny) lam = prev + 10.0 * tiny;
       prev = lam;
-      double* y = Y + int64_t(n) * mb;
-      double* D = F + (int64_t(n) * 5 + 0) * mb;
-      double* U1 = D + mb;
-      double* U2 = U1 + mb;
-      double* M = U2 + mb;
-      double* P = M + mb;
-      trid_lu(d, e, m, lam, tiny, D, U1, U2, M, P);
-      // deterministic start vector with every component nonzero
-      for (int i = 0; i < m; ++i) y[i] = 1.0 + 0.5 * sin(0.7 * double(i + 1) + 1.3 * double(n + 1));
+      double* y = Y + n;
+      double* D = F + n;
+      double* U1 = D + int64_t(mb) * nb;
+      double* U2 = U1 + int64_t(mb) * nb;
+      double* M = U2 + int64_t(mb) * nb;
+      double* P = M + int64_t(mb) * nb;
+      // LU with partial pivoting of T - lam I
+      for (int i = 0; i < m; ++i) {
+        D[i * st] = sd[i] - lam;
+        U1[i * st] = i < m - 1 ? se[i] : 0.0;
+        M[i * st] = i < m - 1 ? se[i] : 0.0;
+        U2[i * st] = 0.0;
+        P[i * st] = 0.0;
+      }
+      double dcur = D[0];
+      for (int i = 0; i < m - 1; ++i) {
+        const double sub = M[i * st];
+        if (fabs(dcur) >= fabs(sub)) {
+          const double f = dcur != 0.0 ? sub / dcur : 0.0;
+          D[i * st] = dcur;
+          M[i * st] = f;
+          dcur = D[(i + 1) * st] - f * U1[i * st];
+        } else {
+          const double f = dcur / sub;
+          D[i * st] = sub;
+          M[i * st] = f;
+          const double t = U1[i * st];
+          const double dn = D[(i + 1) * st];
+          U1[i * st] = dn;
+          dcur = t - f * dn;
+          if (i < m - 2) {
+            U2[i * st] = U1[(i + 1) * st];
+            U1[(i + 1) * st] = -f * U1[(i + 1) * st];
+          }
+          P[i * st] = 1.0;
+        }
+      }
+      D[(m - 1) * st] = dcur;
+      for (int i = 0; i < m; ++i)
+        if (fabs(D[i * st]) < tiny) D[i * st] = D[i * st] < 0.0 ? -tiny : tiny;
+      for (int i = 0; i < m; ++i) y[i * st] = 1.0 + 0.5 * sin(0.7 * double(i + 1) + 1.3 * double(n + 1));
       for (int it = 0; it < 3; ++it) {
-        trid_solve(m, D, U1, U2, M, P, y);
+        for (int i = 0; i < m - 1; ++i) {
+          if (P[i * st] == 0.0) {
+            y[(i + 1) * st] -= M[i * st] * y[i * st];
+          } else {
+            const double t = y[i * st];
+            y[i * st] = y[(i + 1) * st];
+            y[(i + 1) * st] = t - M[i * st] * y[i * st];
+          }
+        }
+        y[(m - 1) * st] /= D[(m - 1) * st];
+        if (m > 1) y[(m - 2) * st] = (y[(m - 2) * st] - U1[(m - 2) * st] * y[(m - 1) * st]) / D[(m - 2) * st];
+        for (int i = m - 3; i >= 0; --i)
+          y[i * st] = (y[i * st] - U1[i * st] * y[(i + 1) * st] - U2[i * st] * y[(i + 2) * st]) / D[i * st];
         for (int q = n0; q < n; ++q) {
-          const double* yq = Y + int64_t(q) * mb;
           double s = 0.0;
-          for (int i = 0; i < m; ++i) s += y[i] * yq[i];
-          for (int i = 0; i < m; ++i) y[i] -= s * yq[i];
+          for (int i = 0; i < m; ++i) s += y[i * st] * Y[i * st + q];
+          for (int i = 0; i < m; ++i) y[i * st] -= s * Y[i * st + q];
         }
         double s = 0.0;
-        for (int i = 0; i < m; ++i) s += y[i] * y[i];
+        for (int i = 0; i < m; ++i) s += y[i * st] * y[i * st];
         s = 1.0 / sqrt(s);
-        for (int i = 0; i < m; ++i) y[i] *= s;
+        for (int i = 0; i < m; ++i) y[i * st] *= s;
       }
     }
   }
-  __syncthreads();
-  // Z = Q y: start from y, apply H_{m-2} ... H_0
-  for (int64_t t = tid; t < int64_t(m) * nwant; t += blockDim.x) {
-    const int i = int(t / nwant), n = int(t % nwant);
-    Z[int64_t(i) * nb + n] = make_double2(Y[int64_t(n) * mb + i], 0.0);
+}
+
+// Z = Q y with Q = H_0 H_1 ... H_{m-2}: one workgroup per (slice of cols columns, k); the
+// slice of Z lives in LDS while every reflector streams through.  Z[k][i][n] complex.
+constexpr int BT_COLS = 8;   // upper bound of cols
+__global__ void __launch_bounds__(256) k_backtransform(DJobs jobs, const double2* __restrict__ Aw,
+                                                       const double2* __restrict__ tau,
+                                                       const double* __restrict__ yw,
+                                                       double2* __restrict__ Zout, int cols) {
+  extern __shared__ double2 shz[];   // [mb][BT_COLS] slice, then [mb] reflector
+  const DJob& J = jobs.j[blockIdx.y];
+  const int mb = jobs.mb, nb = jobs.nb, m = J.m;
+  const int c0 = blockIdx.x * cols;
+  if (c0 >= min(nb, m)) return;
+  const int nc = min(cols, min(nb, m) - c0);
+  const double2* A = Aw + int64_t(J.k) * mb * mb;
+  const double2* tk = tau + int64_t(J.k) * mb;
+  const double* Y = yw + int64_t(J.k) * nb * mb;
+  double2* Z = Zout + int64_t(J.k) * mb * nb;
+  double2* zs = shz;
+  double2* vj = shz + int64_t(mb) * cols;
+  __shared__ double2 s[BT_COLS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  for (int t = tid; t < m * cols; t += blockDim.x) {
+    const int i = t / cols, c = t % cols;
+    zs[t] = c < nc ? make_double2(Y[int64_t(i) * nb + c0 + c], 0.0) : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  double2* vj = sh;
   for (int j = m - 2; j >= 0; --j) {
     const double2 t = tk[j];
     if (t.x == 0.0 && t.y == 0.0) continue;  // uniform
     for (int r = j + 1 + tid; r < m; r += blockDim.x)
       vj[r] = r == j + 1 ? make_double2(1.0, 0.0) : A[int64_t(r) * mb + j];
     __syncthreads();
-    for (int n = tid; n < nwant; n += blockDim.x) {
+    // s_c = sum_r conj(v_r) z_rc : wave w reduces column w (and w + 4)
+    for (int c = wave; c < cols; c += 4) {
       double sr = 0.0, si = 0.0;
-      for (int r = j + 1; r < m; ++r) {
-        const double2 vv = vj[r], z = Z[int64_t(r) * nb + n];
-        sr += vv.x * z.x + vv.y * z.y;   // conj(v) z
-        si += vv.x * z.y - vv.y * z.x;
+      for (int r = j + 1 + lane; r < m; r += 64) {
+        const double2 v = vj[r], z = zs[r * cols + c];
+        sr += v.x * z.x + v.y * z.y;
+        si += v.x * z.y - v.y * z.x;
       }
-      const double2 f = cmul2(t, make_double2(sr, si));
-      for (int r = j + 1; r < m; ++r) Z[int64_t(r) * nb + n] = csub2(Z[int64_t(r) * nb + n], cmul2(vj[r], f));
+      for (int o = 32; o > 0; o >>= 1) {
+        sr += __shfl_down(sr, o, 64);
+        si += __shfl_down(si, o, 64);
+      }
+      if (lane == 0) s[c] = cmul2(t, make_double2(sr, si));
     }
     __syncthreads();
+    for (int q = tid; q < (m - j - 1) * cols; q += blockDim.x) {
+      const int r = j + 1 + q / cols, c = q % cols;
+      zs[r * cols + c] = csub2(zs[r * cols + c], cmul2(vj[r], s[c]));
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < m * cols; t += blockDim.x) {
+    const int i = t / cols, c = t % cols;
+    if (c < nc) Z[int64_t(i) * nb + c0 + c] = zs[t];
   }
 }
 
