@@ -201,6 +201,15 @@ template <int S, typename R> struct Dft<12, S, R> : DftComposite<12, 4, S, R> {}
 template <int S, typename R> struct Dft<14, S, R> : DftComposite<14, 2, S, R> {};
 template <int S, typename R> struct Dft<15, S, R> : DftComposite<15, 3, S, R> {};
 template <int S, typename R> struct Dft<16, S, R> : DftComposite<16, 4, S, R> {};
+template <int S, typename R> struct Dft<18, S, R> : DftComposite<18, 2, S, R> {};
+template <int S, typename R> struct Dft<20, S, R> : DftComposite<20, 4, S, R> {};
+template <int S, typename R> struct Dft<24, S, R> : DftComposite<24, 4, S, R> {};
+template <int S, typename R> struct Dft<32, S, R> : DftComposite<32, 4, S, R> {};
+template <int S, typename R> struct Dft<36, S, R> : DftComposite<36, 4, S, R> {};
+template <int S, typename R> struct Dft<40, S, R> : DftComposite<40, 8, S, R> {};
+template <int S, typename R> struct Dft<48, S, R> : DftComposite<48, 4, S, R> {};
+template <int S, typename R> struct Dft<64, S, R> : DftComposite<64, 8, S, R> {};
+template <int S, typename R> struct Dft<72, S, R> : DftComposite<72, 8, S, R> {};
 
 // Two-factor split used by the LDS line transforms: N = R1 * R2 with R1 <= R2.
 template <int N> struct Split;

@@ -115,8 +115,7 @@ static DavState* dav_create(qm_hpsi_plan* p, int k0, int k1, int nb, int mb) {
     for (hipEvent_t& e : d->ev) QM_HIP(hipEventCreate(&e));
     const void* big[] = {reinterpret_cast<const void*>(&k_tridiag), reinterpret_cast<const void*>(&k_tridiag_eig),
                          reinterpret_cast<const void*>(&k_backtransform)};
-    for (const void* f : big)
-      QM_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024));
+    for (const void* f : big) QM_HIP(allow_full_lds(f));
     d->m.assign(nk, 0);
     d->it.assign(nk, 0);
     d->done.assign(nk, 0);

@@ -19,10 +19,22 @@ struct Error : std::runtime_error {
 #define QM_HIP(call)                                                                   \
   do {                                                                                 \
     hipError_t e_ = (call);                                                            \
-    if (e_ != hipSuccess)                                                              \
+    if (e_ != hipSuccess) {                                                            \
+      (void)hipGetLastError(); /* do not leave the error for the next check */         \
       throw ::qm::Error(e_ == hipErrorOutOfMemory ? QM_E_NOMEM : QM_E_HIP,             \
                         std::string(#call) + ": " + hipGetErrorString(e_));            \
+    }                                                                                  \
   } while (0)
+
+// allow a kernel the whole 160 KiB LDS of a gfx950 CU for dynamic shared memory, minus its
+// static shared memory
+inline hipError_t allow_full_lds(const void* f) {
+  hipFuncAttributes at{};
+  hipError_t e = hipFuncGetAttributes(&at, f);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             int(160 * 1024 - at.sharedSizeBytes));
+}
 
 #define QM_REQUIRE(cond, code, msg) \
   do {                              \
@@ -117,6 +129,7 @@ struct qm_hpsi_plan {
   uint64_t graph_clock = 0;
   hipStream_t capture_stream = nullptr;
   int32_t use_graphs = 1;
+  int32_t xy_mode = 0;   // 0: register-line xy kernel where it applies (float32), 1: two-pass kernel
 };
 
 namespace qm {
