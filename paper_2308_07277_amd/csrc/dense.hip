@@ -75,24 +75,41 @@ __global__ void k_hs_copy(DJobs jobs, const double2* __restrict__ Hs, double2* _
 }
 
 // ---------------------------------------------------------------- tridiagonalisation
+// Householder reduction with the rank-2 update of step j-1 applied lazily: step j first
+// brings column j up to date, builds its reflector, then makes one pass over the trailing
+// block that applies the pending update and accumulates p = tau A v at the same time (one
+// read and one write per element and step).  A (row-major, stride mb, full Hermitian) is
+// destroyed; column j below the subdiagonal receives v_j (v_j[j+1] = 1 implicit).
 __global__ void __launch_bounds__(1024) k_tridiag(DJobs jobs, double2* __restrict__ Aw,
                                                   double* __restrict__ dd, double* __restrict__ ee,
                                                   double2* __restrict__ tau) {
-  extern __shared__ double2 sh[];
+  extern __shared__ double2 sh[];   // vA, vB, pA, pB: [mb] each
   const DJob& J = jobs.j[blockIdx.x];
   const int mb = jobs.mb, m = J.m;
   double2* A = Aw + int64_t(J.k) * mb * mb;
   double* d = dd + int64_t(J.k) * mb;
   double* e = ee + int64_t(J.k) * mb;
   double2* tk = tau + int64_t(J.k) * mb;
-  double2* v = sh;       // [mb]
-  double2* w = sh + mb;  // [mb]
   __shared__ double red[16];
   __shared__ double2 s_tau, s_scale;
   __shared__ double s_beta;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
+  for (int i = tid; i < 4 * mb; i += blockDim.x) sh[i] = make_double2(0.0, 0.0);
+  __syncthreads();
   for (int j = 0; j < m - 1; ++j) {
-    const int n = m - j - 1;
+    double2* vc = sh + (j & 1 ? mb : 0);          // this step's reflector
+    double2* pc = sh + 2 * mb + (j & 1 ? mb : 0);  // this step's p, then w
+    const double2* vq = sh + (j & 1 ? 0 : mb);     // pending reflector (step j-1)
+    const double2* wq = sh + 2 * mb + (j & 1 ? 0 : mb);  // pending w
+    // column j, rows >= j, brought up to date
+    const double2 vqj = vq[j], wqj = wq[j];
+    for (int r = j + tid; r < m; r += blockDim.x) {
+      double2 a = A[int64_t(r) * mb + j];
+      a = csub2(a, cmul2(vq[r], cconj(wqj)));
+      a = csub2(a, cmul2(wq[r], cconj(vqj)));
+      A[int64_t(r) * mb + j] = a;
+    }
+    __syncthreads();
     double xs = 0.0;
     for (int r = j + 2 + tid; r < m; r += blockDim.x) {
       const double2 a = A[int64_t(r) * mb + j];
@@ -120,57 +137,74 @@ __global__ void __launch_bounds__(1024) k_tridiag(DJobs jobs, double2* __restric
     }
     __syncthreads();
     const double2 t = s_tau;
-    if (t.x == 0.0 && t.y == 0.0) continue;  // uniform branch
+    const bool refl = !(t.x == 0.0 && t.y == 0.0);
     for (int r = j + 1 + tid; r < m; r += blockDim.x) {
-      const double2 x = r == j + 1 ? make_double2(1.0, 0.0) : cmul2(A[int64_t(r) * mb + j], s_scale);
-      v[r - j - 1] = x;
-      if (r > j + 1) A[int64_t(r) * mb + j] = x;
+      double2 x = make_double2(0.0, 0.0);
+      if (refl) {
+        x = r == j + 1 ? make_double2(1.0, 0.0) : cmul2(A[int64_t(r) * mb + j], s_scale);
+        if (r > j + 1) A[int64_t(r) * mb + j] = x;
+      }
+      vc[r] = x;
     }
+    if (tid == 0) vc[j] = make_double2(0.0, 0.0);
     __syncthreads();
-    // p = tau A_sub v, one wave per row
-    for (int rr = wave; rr < n; rr += nw) {
-      const double2* row = A + int64_t(j + 1 + rr) * mb + (j + 1);
-      double sr = 0.0, si = 0.0;
-      for (int c = lane; c < n; c += 64) {
-        const double2 a = row[c], b = v[c];
-        sr += a.x * b.x - a.y * b.y;
-        si += a.x * b.y + a.y * b.x;
+    // fused pass over rows/cols [j+1, m): pending update, then p = tau A v.  A wave takes
+    // four rows at a time so the reflector values it reads from LDS serve four rows.
+    for (int r0 = j + 1 + 4 * wave; r0 < m; r0 += 4 * nw) {
+      double sr[4] = {0, 0, 0, 0}, si[4] = {0, 0, 0, 0};
+      double2 vr[4], wr[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = min(r0 + q, m - 1);
+        vr[q] = vq[r];
+        wr[q] = wq[r];
       }
-      for (int o = 32; o > 0; o >>= 1) {
-        sr += __shfl_down(sr, o, 64);
-        si += __shfl_down(si, o, 64);
+      for (int c = j + 1 + lane; c < m; c += 64) {
+        const double2 vqc = cconj(vq[c]), wqc = cconj(wq[c]), b = vc[c];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          if (r0 + q >= m) break;
+          double2* ap = A + int64_t(r0 + q) * mb + c;
+          double2 a = *ap;
+          a = csub2(a, cmul2(vr[q], wqc));
+          a = csub2(a, cmul2(wr[q], vqc));
+          *ap = a;
+          sr[q] += a.x * b.x - a.y * b.y;
+          si[q] += a.x * b.y + a.y * b.x;
+        }
       }
-      if (lane == 0) w[rr] = cmul2(t, make_double2(sr, si));
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        for (int o = 32; o > 0; o >>= 1) {
+          sr[q] += __shfl_down(sr[q], o, 64);
+          si[q] += __shfl_down(si[q], o, 64);
+        }
+        if (lane == 0 && r0 + q < m) pc[r0 + q] = cmul2(t, make_double2(sr[q], si[q]));
+      }
     }
+    if (tid == 0) pc[j] = make_double2(0.0, 0.0);
     __syncthreads();
     double pr = 0.0, pi = 0.0;   // p^H v
-    for (int c = tid; c < n; c += blockDim.x) {
-      const double2 pc = w[c], vc = v[c];
-      pr += pc.x * vc.x + pc.y * vc.y;
-      pi += pc.x * vc.y - pc.y * vc.x;
+    for (int c = j + 1 + tid; c < m; c += blockDim.x) {
+      const double2 pv = pc[c], vv = vc[c];
+      pr += pv.x * vv.x + pv.y * vv.y;
+      pi += pv.x * vv.y - pv.y * vv.x;
     }
     pr = block_sum(pr, red);
     pi = block_sum(pi, red);
     const double2 aw = cmul2(make_double2(-0.5 * t.x, -0.5 * t.y), make_double2(pr, pi));
-    for (int c = tid; c < n; c += blockDim.x) w[c] = cadd2(w[c], cmul2(aw, v[c]));
-    __syncthreads();
-    for (int rr = wave; rr < n; rr += nw) {
-      double2* row = A + int64_t(j + 1 + rr) * mb + (j + 1);
-      const double2 vr = v[rr], wr = w[rr];
-      for (int c = lane; c < n; c += 64) {
-        const double2 vc = v[c], wc = w[c];
-        double2 a = row[c];
-        a = csub2(a, cmul2(vr, cconj(wc)));
-        a = csub2(a, cmul2(wr, cconj(vc)));
-        row[c] = a;
-      }
-    }
+    for (int c = j + 1 + tid; c < m; c += blockDim.x) pc[c] = cadd2(pc[c], cmul2(aw, vc[c]));
     __syncthreads();
   }
   if (tid == 0) {
-    d[m - 1] = A[int64_t(m - 1) * mb + (m - 1)].x;
-    e[m - 1] = 0.0;
-    tk[m - 1] = make_double2(0.0, 0.0);
+    const int j = m - 1;  // pending update of step m-2 on the last diagonal element
+    const double2* vq = sh + ((m - 2) & 1 ? mb : 0);
+    const double2* wq = sh + 2 * mb + ((m - 2) & 1 ? mb : 0);
+    double a = A[int64_t(j) * mb + j].x;
+    if (m >= 2) a -= 2.0 * (vq[j].x * wq[j].x + vq[j].y * wq[j].y);
+    d[j] = a;
+    e[j] = 0.0;
+    tk[j] = make_double2(0.0, 0.0);
   }
 }
 
