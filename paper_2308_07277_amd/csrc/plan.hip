@@ -133,15 +133,19 @@ static void build_plan(qm_hpsi_plan* p, const double cell[9], const int32_t grid
       else ia_of[i1] = -1;
     for (int i1 = 0; i1 < N1; ++i1) col_of_i1[size_t(k) * N1 + i1] = ia_of[i1];
     for (int s2 = 0; s2 < nstick; ++s2) stick_pos.push_back(st_i2[s2] | (ia_of[st_i1[s2]] << 16));
-    // entries ordered by (stick, i3)
+    // entries grouped by stick tile; inside a tile ordered by (i3, stick) so consecutive
+    // threads of the z kernels touch neighbouring x-columns of one plane (adjacent in the
+    // usual G orders)
     std::vector<int32_t> order(npw);
-    std::vector<int64_t> ekey(npw);
+    std::vector<int64_t> ekey(npw), skey(npw);
     for (int g = 0; g < npw; ++g) {
       const int st = stick_of[size_t(ii[3 * g + 1]) * N1 + ii[3 * g]];
-      ekey[g] = int64_t(st) * N3 + ii[3 * g + 2];
+      const int z = ii[3 * g + 2];
+      ekey[g] = int64_t(st) * N3 + z;
+      skey[g] = (int64_t(st / kTileSticks) * N3 + z) * kTileSticks + (st % kTileSticks);
       order[g] = g;
     }
-    std::sort(order.begin(), order.end(), [&](int x, int y) { return ekey[x] < ekey[y]; });
+    std::sort(order.begin(), order.end(), [&](int x, int y) { return skey[x] < skey[y]; });
     const int ntile = (nstick + kTileSticks - 1) / kTileSticks;
     int t = 0;
     for (int e = 0; e < npw; ++e) {
