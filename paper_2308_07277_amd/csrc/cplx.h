@@ -210,6 +210,8 @@ template <int S, typename R> struct Dft<40, S, R> : DftComposite<40, 8, S, R> {}
 template <int S, typename R> struct Dft<48, S, R> : DftComposite<48, 4, S, R> {};
 template <int S, typename R> struct Dft<64, S, R> : DftComposite<64, 8, S, R> {};
 template <int S, typename R> struct Dft<72, S, R> : DftComposite<72, 8, S, R> {};
+template <int S, typename R> struct Dft<27, S, R> : DftComposite<27, 3, S, R> {};
+template <int S, typename R> struct Dft<54, S, R> : DftComposite<54, 6, S, R> {};
 
 // Two-factor split used by the LDS line transforms: N = R1 * R2 with R1 <= R2.
 template <int N> struct Split;

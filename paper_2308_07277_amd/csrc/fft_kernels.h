@@ -376,6 +376,158 @@ __global__ void __launch_bounds__(PL * NX) k_xy_reg(LocalArgs a) {
   }
 }
 
+// ------------------------------------------------------------------ xy plane, lane-group lines
+// Lines of length NX split over L lanes of a wave (H = NX/L complex per lane, in registers).
+// Inverse = decimation in time: lane t holds x[L n + t], runs an H-point DFT, twiddles by
+// w_NX^{t k}, then an L-point DFT across the lane group (xor shuffles) leaves X[H t + k].
+// Forward = decimation in frequency: lane q holds x[H q + n]; the L-point DFT across the group
+// comes first, then the twiddle w_NX^{-t n} and an H-point DFT leave X[L k + t].  The inverse's
+// output distribution is exactly the forward's input distribution, so the x-row transform pair
+// with V(r) in between never leaves registers.  Used for float64 lines up to 72.
+template <typename R>
+__device__ __forceinline__ cplx<R> shflx(cplx<R> v, int m) {
+  return {__shfl_xor(v.re, m, 64), __shfl_xor(v.im, m, 64)};
+}
+// v * (S i)^e for e in 0..3, branch free: (S i)^e = c + i s with c, s in {-1, 0, 1}
+template <int S, typename R>
+__device__ __forceinline__ cplx<R> mul_ipow(cplx<R> v, int e) {
+  e &= 3;
+  const R c = R((e == 0) - (e == 2));
+  const R s = R(S * ((e == 1) - (e == 3)));
+  return {c * v.re - s * v.im, c * v.im + s * v.re};
+}
+// lane t of an L-group: out = sum_{t'} z_{t'} w_L^{S t' t}
+template <int S, int L, typename R>
+__device__ __forceinline__ cplx<R> cross_dft(cplx<R> z, int t) {
+  if (L == 2) {
+    const cplx<R> p = shflx(z, 1);
+    return t ? csub(p, z) : cadd(z, p);
+  } else {  // L == 4: gather the group, w_4 = S i
+    cplx<R> acc = z;
+#pragma unroll
+    for (int x = 1; x < 4; ++x) {
+      const cplx<R> v = shflx(z, x);
+      acc = cadd(acc, mul_ipow<S>(v, (t ^ x) * t));
+    }
+    return acc;
+  }
+}
+
+template <typename R, int NX, int L>
+__device__ __forceinline__ void group_inverse(cplx<R>* y, int t, const cplx<R>* tw) {
+  constexpr int H = NX / L;
+  Dft<H, +1, R>::run(y);
+#pragma unroll
+  for (int k = 1; k < H; ++k) y[k] = cmul(y[k], tw[(t * k) % NX]);
+#pragma unroll
+  for (int k = 0; k < H; ++k) y[k] = cross_dft<+1, L>(y[k], t);
+}
+
+template <typename R, int NX, int L>
+__device__ __forceinline__ void group_forward(cplx<R>* y, int t, const cplx<R>* tw) {
+  constexpr int H = NX / L;
+#pragma unroll
+  for (int n = 0; n < H; ++n) {
+    const cplx<R> a = cross_dft<-1, L>(y[n], t);
+    const cplx<R> w = tw[(t * n) % NX];
+    y[n] = n ? cmul(a, cplx<R>{w.re, -w.im}) : a;
+  }
+  Dft<H, -1, R>::run(y);
+}
+
+template <typename R, int NX, int L>
+__global__ void __launch_bounds__(L * NX) k_xy_group(LocalArgs a) {
+  constexpr int H = NX / L, NT = L * NX, LPW = 64 / L;  // lines per wave
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int ns = a.nax_stride;
+  cplx<R>* Lp = reinterpret_cast<cplx<R>*>(smem_raw);  // [NX rows i2][ns]
+  cplx<R>* tw = Lp + NX * ns;                           // [NX]
+  int* col = reinterpret_cast<int*>(tw + NX);           // [NX]
+  const int tid = threadIdx.x, t = tid % L, line = tid / L;
+  const int N3 = a.N3;
+  int bid = blockIdx.x, kb, p;
+  if ((N3 & 7) == 0) {
+    const int xcd = bid & 7, jj = bid >> 3, per = N3 >> 3;
+    kb = jj / per;
+    p = xcd * per + (jj - kb * per);
+  } else {
+    kb = bid / N3;
+    p = bid - kb * N3;
+  }
+  int si = 0;
+  while (si < a.nsl - 1 && kb >= a.pair0[si + 1]) ++si;
+  const int k = a.sl[si].k, band = kb - a.pair0[si];
+  const KInfo ki = a.kinfo[k];
+  const int nax = ki.nax;
+  for (int i = tid; i < NX; i += NT) {
+    double2 w = a.tw_x[i];
+    tw[i] = {R(w.x), R(w.y)};
+    col[i] = a.col_of_i1[int64_t(k) * NX + i];
+  }
+  for (int i = tid; i < NX * ns; i += NT) Lp[i] = {R(0), R(0)};
+  __syncthreads();
+  cplx<R>* plane = reinterpret_cast<cplx<R>*>(a.sbuf) + ki.sbuf_off +
+                   (int64_t(band) * N3 + p) * ki.nstick;
+  const int32_t* spos = a.stick_pos + ki.stick_off;
+  for (int s = tid; s < ki.nstick; s += NT) {
+    const int ps = spos[s];
+    Lp[(ps & 0xffff) * ns + (ps >> 16)] = plane[s];
+  }
+  __syncthreads();
+  // whole waves take part in the cross-lane steps (lines rounded up to a wave)
+  const int nax_w = ((nax + LPW - 1) / LPW) * LPW;
+  cplx<R> y[H];
+  // inverse y on active columns
+  if (line < nax_w) {
+    const bool live = line < nax;
+#pragma unroll
+    for (int n = 0; n < H; ++n) y[n] = live ? Lp[(L * n + t) * ns + line] : cplx<R>{R(0), R(0)};
+    group_inverse<R, NX, L>(y, t, tw);
+    if (live) {
+#pragma unroll
+      for (int k2 = 0; k2 < H; ++k2) Lp[(H * t + k2) * ns + line] = y[k2];
+    }
+  }
+  __syncthreads();
+  // x rows: inverse, * V / N_r, forward
+  {
+    const int i2 = line;
+    cplx<R>* row = Lp + i2 * ns;
+#pragma unroll
+    for (int n = 0; n < H; ++n) {
+      const int c = col[L * n + t];
+      y[n] = c >= 0 ? row[c] : cplx<R>{R(0), R(0)};
+    }
+    group_inverse<R, NX, L>(y, t, tw);
+    const R* Vrow = reinterpret_cast<const R*>(a.vplan) + (int64_t(p) * NX + i2) * NX + H * t;
+#pragma unroll
+    for (int n = 0; n < H; ++n) y[n] = cscale(y[n], Vrow[n]);
+    group_forward<R, NX, L>(y, t, tw);
+#pragma unroll
+    for (int k2 = 0; k2 < H; ++k2) {
+      const int c = col[L * k2 + t];
+      if (c >= 0) row[c] = y[k2];
+    }
+  }
+  __syncthreads();
+  // forward y on active columns
+  if (line < nax_w) {
+    const bool live = line < nax;
+#pragma unroll
+    for (int n = 0; n < H; ++n) y[n] = live ? Lp[(H * t + n) * ns + line] : cplx<R>{R(0), R(0)};
+    group_forward<R, NX, L>(y, t, tw);
+    if (live) {
+#pragma unroll
+      for (int k2 = 0; k2 < H; ++k2) Lp[(L * k2 + t) * ns + line] = y[k2];
+    }
+  }
+  __syncthreads();
+  for (int s = tid; s < ki.nstick; s += NT) {
+    const int ps = spos[s];
+    plane[s] = Lp[(ps & 0xffff) * ns + (ps >> 16)];
+  }
+}
+
 // ------------------------------------------------------------------ z forward + gather + kinetic
 template <typename R, int N3, int TS>
 __global__ void __launch_bounds__(TS * Split<N3>::R2) k_zfwd(LocalArgs a) {

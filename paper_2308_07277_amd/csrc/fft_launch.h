@@ -80,7 +80,23 @@ void launch_local_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* 
   }
   QM_HIP(hipGetLastError());
   if (ev) ev->mark(0);
-  if (sizeof(R) == 4 && xy_reg_len(NX) && p->xy_mode != 1) {
+  if (sizeof(R) == 8 && (NX == 20 || NX == 40) && p->xy_mode != 1) {
+    const size_t smem_p = sizeof(cplx<R>) * (size_t(NX) * a.nax_stride + NX) + sizeof(int) * NX;
+#define QM_XYP(n, l)                                                                        \
+  case n: {                                                                                 \
+    static bool attr_p = false;                                                             \
+    if (!attr_p) {                                                                          \
+      QM_HIP(allow_full_lds(reinterpret_cast<const void*>(&k_xy_group<R, n, l>)));         \
+      attr_p = true;                                                                        \
+    }                                                                                       \
+    hipLaunchKernelGGL((k_xy_group<R, n, l>), dim3(unsigned(nblk_xy)), dim3(l * n), smem_p, s, a); \
+  } break;
+    switch (NX) {
+      QM_XYP(20, 2) QM_XYP(40, 2)
+      default: throw Error(QM_E_SHAPE, "unsupported N1");
+    }
+#undef QM_XYP
+  } else if (sizeof(R) == 4 && xy_reg_len(NX) && p->xy_mode != 1) {
     const size_t smem_r = sizeof(cplx<R>) * size_t(kXyBands) * NX * a.nax_stride + sizeof(int) * NX;
     const unsigned nb_r = unsigned(ngrp * p->N3);
 #define QM_XYR(n)                                                                           \
