@@ -51,10 +51,24 @@ def test_c1_davidson_vs_dense():
     r = np.linalg.norm(h(xs) - eig[0][:, None] * xs, axis=1)
     assert r.max() <= 1.5e-9
     np.testing.assert_allclose(xs.conj() @ xs.T, np.eye(w.nbnd), atol=1e-10)
+
+
+def test_c1_iteration_count_matches_oracle():
+    """With 10 bands no degenerate level is cut (the 10th is isolated by 0.23 Ha), so the GPU
+    and oracle Davidson from the same start follow the same path up to rounding.  (With the
+    config's 8 bands a triply degenerate level is cut, which makes the path rounding-
+    sensitive; there only the eigenvalues are compared.)"""
+    w = workload.make_workload("c1")
+    nb = 10
+    plan, a = make_plan(w, nb)
+    eig, res, stats, st, x = _solve(plan, w, nb, _start(w, nb), tol=1e-9)
+    assert st == 0
+    h, beta = _oracle_h(w, a, 0)
     kin = ham.kinetic(w.cell, w.k_cryst[0], w.miller[0])
-    ref = odav.davidson_ref(h, _start(w, w.nbnd)[0], kin, tol=1e-9)
+    ref = odav.davidson_ref(h, _start(w, nb)[0], kin, tol=1e-9)
     print("iterations gpu", stats["iterations"], "oracle", ref["iterations"])
-    assert abs(stats["iterations"] - ref["iterations"]) <= 2
+    assert abs(stats["iterations"] - ref["iterations"]) <= 1
+    assert np.abs(eig[0] - ref["eig"]).max() <= 1e-9
 
 
 def test_c2_davidson_all_k():
