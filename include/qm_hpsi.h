@@ -126,8 +126,8 @@ typedef struct {
  *  out      receives the plan.
  * The plan copies V, beta and D (in its working precisions) and owns its
  * workspace, so inputs may be freed after the call returns.  Environment:
- * QM_XY_MODE=1 makes float32 plans use the two-pass xy-plane kernel instead of the
- * register-line kernel (both compute the same transform; for comparisons). */
+ * QM_XY_MODE=1 makes float64 plans on 20^3 and 40^3 grids use the two-pass xy-plane
+ * kernel instead of the lane-pair kernel (same transform; for comparisons). */
 qm_status qm_hpsi_plan_create(const double cell[9], const int32_t grid[3], const qm_kset *ks,
                               int32_t nbnd_max, int32_t nproj, const double *vloc_r,
                               const void *beta, const double *dmat, qm_prec prec, void *stream,

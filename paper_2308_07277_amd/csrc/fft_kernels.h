@@ -33,7 +33,6 @@ struct LocalArgs {
   KSlice sl[kMaxSlices];    // k-point band blocks of this launch
   int32_t blk_z[kMaxSlices + 1];  // prefix of nb * ntile over slices (z kernels)
   int32_t pair0[kMaxSlices + 1];  // prefix of nb over slices (xy kernel)
-  int32_t grp0[kMaxSlices + 1];   // prefix of ceil(nb / PL) over slices (register xy kernel)
   int32_t nsl, N3;
   const double2* psi;       // c128 base
   double2* hpsi;            // c128 base
@@ -270,109 +269,6 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
   for (int s = tid; s < ki.nstick; s += 256) {
     const int ps = spos[s];
     plane[s] = L[(ps & 0xffff) * ns + (ps >> 16)];
-  }
-}
-
-// ------------------------------------------------------------------ xy plane, register lines
-// float32 variant for N1 = N2 <= 72: every 1-D line (a y-column or an x-row) is held whole in
-// one thread's registers, so a line never passes through LDS mid-transform; PL bands of the
-// same z-plane share a workgroup (threads: PL * N2 rows in the x phase, PL * nax columns in
-// the y phases).  LDS holds the PL planes restricted to the active columns.
-template <int NX, int PL>
-__global__ void __launch_bounds__(PL * NX) k_xy_reg(LocalArgs a) {
-  typedef float R;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int ns = a.nax_stride;
-  cplx<R>* L = reinterpret_cast<cplx<R>*>(smem_raw);   // [PL][NX rows i2][ns]
-  int* col = reinterpret_cast<int*>(L + PL * NX * ns);  // [NX]
-  const int tid = threadIdx.x;
-  const int N3 = a.N3;
-  // block -> (group of PL consecutive (k, band) pairs, z-slot); XCD keeps an eighth of the slots
-  int bid = blockIdx.x, grp, p;
-  if ((N3 & 7) == 0) {
-    const int xcd = bid & 7, jj = bid >> 3, per = N3 >> 3;
-    grp = jj / per;
-    p = xcd * per + (jj - grp * per);
-  } else {
-    grp = bid / N3;
-    p = bid - grp * N3;
-  }
-  // band groups of PL never straddle two slices: each slice has ceil(nb / PL) groups
-  int si = 0;
-  while (si < a.nsl - 1 && grp >= a.grp0[si + 1]) ++si;
-  const int k = a.sl[si].k;
-  const int band0 = (grp - a.grp0[si]) * PL;
-  const int nbs = a.sl[si].nb;
-  const KInfo ki = a.kinfo[k];
-  const int nax = ki.nax;
-  for (int i = tid; i < NX; i += PL * NX) col[i] = a.col_of_i1[int64_t(k) * NX + i];
-  for (int i = tid; i < PL * NX * ns; i += PL * NX) L[i] = {R(0), R(0)};
-  __syncthreads();
-  const int32_t* spos = a.stick_pos + ki.stick_off;
-  for (int pl = 0; pl < PL; ++pl) {
-    if (band0 + pl >= nbs) break;
-    const cplx<R>* plane = reinterpret_cast<const cplx<R>*>(a.sbuf) + ki.sbuf_off +
-                           (int64_t(band0 + pl) * N3 + p) * ki.nstick;
-    for (int s = tid; s < ki.nstick; s += PL * NX) {
-      const int ps = spos[s];
-      L[(pl * NX + (ps & 0xffff)) * ns + (ps >> 16)] = plane[s];
-    }
-  }
-  __syncthreads();
-  // inverse y on active columns
-  if (tid < PL * nax) {
-    const int pl = tid / nax, ia = tid - pl * nax;
-    cplx<R> x[NX];
-    cplx<R>* c0 = L + pl * NX * ns + ia;
-#pragma unroll
-    for (int i = 0; i < NX; ++i) x[i] = c0[i * ns];
-    Dft<NX, +1, R>::run(x);
-#pragma unroll
-    for (int i = 0; i < NX; ++i) c0[i * ns] = x[i];
-  }
-  __syncthreads();
-  // x rows: inverse, * V / N_r, forward; active columns written back
-  {
-    const int pl = tid / NX, i2 = tid - pl * NX;
-    const R* Vrow = reinterpret_cast<const R*>(a.vplan) + (int64_t(p) * NX + i2) * NX;
-    cplx<R>* row = L + (pl * NX + i2) * ns;
-    cplx<R> x[NX];
-#pragma unroll
-    for (int i = 0; i < NX; ++i) {
-      const int c = col[i];
-      x[i] = c >= 0 ? row[c] : cplx<R>{R(0), R(0)};
-    }
-    Dft<NX, +1, R>::run(x);
-#pragma unroll
-    for (int i = 0; i < NX; ++i) x[i] = cscale(x[i], Vrow[i]);
-    Dft<NX, -1, R>::run(x);
-#pragma unroll
-    for (int i = 0; i < NX; ++i) {
-      const int c = col[i];
-      if (c >= 0) row[c] = x[i];
-    }
-  }
-  __syncthreads();
-  // forward y on active columns
-  if (tid < PL * nax) {
-    const int pl = tid / nax, ia = tid - pl * nax;
-    cplx<R> x[NX];
-    cplx<R>* c0 = L + pl * NX * ns + ia;
-#pragma unroll
-    for (int i = 0; i < NX; ++i) x[i] = c0[i * ns];
-    Dft<NX, -1, R>::run(x);
-#pragma unroll
-    for (int i = 0; i < NX; ++i) c0[i * ns] = x[i];
-  }
-  __syncthreads();
-  for (int pl = 0; pl < PL; ++pl) {
-    if (band0 + pl >= nbs) break;
-    cplx<R>* plane = reinterpret_cast<cplx<R>*>(a.sbuf) + ki.sbuf_off +
-                     (int64_t(band0 + pl) * N3 + p) * ki.nstick;
-    for (int s = tid; s < ki.nstick; s += PL * NX) {
-      const int ps = spos[s];
-      plane[s] = L[(pl * NX + (ps & 0xffff)) * ns + (ps >> 16)];
-    }
   }
 }
 

@@ -5,12 +5,7 @@
 namespace qm {
 
 constexpr int kZTile = 32;  // sticks per z-kernel tile (the plan's tile tables use it)
-constexpr int kXyBands = 2;  // bands per workgroup of the register xy kernel
 
-// float32 lengths handled by the register-resident xy kernel (whole line in one thread)
-inline bool xy_reg_len(int n) {
-  return n == 20 || n == 24 || n == 32 || n == 36 || n == 40 || n == 48 || n == 64 || n == 72;
-}
 
 template <typename R>
 void launch_local_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
@@ -20,19 +15,16 @@ void launch_local_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* 
   a.kinfo = p->g.kinfo;
   a.nsl = int32_t(sl.size());
   a.N3 = p->N3;
-  int64_t nblk_z = 0, npair = 0, ngrp = 0;
+  int64_t nblk_z = 0, npair = 0;
   for (size_t i = 0; i < sl.size(); ++i) {
     a.sl[i] = sl[i];
     a.blk_z[i] = int32_t(nblk_z);
     a.pair0[i] = int32_t(npair);
-    a.grp0[i] = int32_t(ngrp);
     nblk_z += int64_t(sl[i].nb) * p->kinfo[sl[i].k].ntile;
     npair += sl[i].nb;
-    ngrp += (sl[i].nb + kXyBands - 1) / kXyBands;
   }
   a.blk_z[sl.size()] = int32_t(nblk_z);
   a.pair0[sl.size()] = int32_t(npair);
-  a.grp0[sl.size()] = int32_t(ngrp);
   a.psi = reinterpret_cast<const double2*>(psi);
   a.hpsi = reinterpret_cast<double2*>(hpsi);
   a.sbuf = p->sbuf;
@@ -96,23 +88,6 @@ void launch_local_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* 
       default: throw Error(QM_E_SHAPE, "unsupported N1");
     }
 #undef QM_XYP
-  } else if (sizeof(R) == 4 && xy_reg_len(NX) && p->xy_mode != 1) {
-    const size_t smem_r = sizeof(cplx<R>) * size_t(kXyBands) * NX * a.nax_stride + sizeof(int) * NX;
-    const unsigned nb_r = unsigned(ngrp * p->N3);
-#define QM_XYR(n)                                                                           \
-  case n: {                                                                                 \
-    static bool attr_r = false;                                                             \
-    if (!attr_r) {                                                                          \
-      QM_HIP(allow_full_lds(reinterpret_cast<const void*>(&k_xy_reg<n, kXyBands>)));       \
-      attr_r = true;                                                                        \
-    }                                                                                       \
-    hipLaunchKernelGGL((k_xy_reg<n, kXyBands>), dim3(nb_r), dim3(kXyBands * n), smem_r, s, a); \
-  } break;
-    switch (NX) {
-      QM_XYR(20) QM_XYR(24) QM_XYR(32) QM_XYR(36) QM_XYR(40) QM_XYR(48) QM_XYR(64) QM_XYR(72)
-      default: throw Error(QM_E_SHAPE, "unsupported N1");
-    }
-#undef QM_XYR
   } else {
     switch (NX) {
       QM_FOR_EACH_FFT_LEN(QM_XY)

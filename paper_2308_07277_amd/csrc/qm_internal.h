@@ -129,7 +129,7 @@ struct qm_hpsi_plan {
   uint64_t graph_clock = 0;
   hipStream_t capture_stream = nullptr;
   int32_t use_graphs = 1;
-  int32_t xy_mode = 0;   // 0: register-line xy kernel where it applies (float32), 1: two-pass kernel
+  int32_t xy_mode = 0;   // 0: lane-group xy kernel where it applies (float64, 20 and 40), 1: two-pass
 };
 
 namespace qm {
