@@ -201,7 +201,10 @@ qm_status qm_davidson_solve(qm_hpsi_plan *plan, int32_t k, void *psi, double *ei
  * Davidson; not in the paper).  Inputs f = [x, log(1 + x), (theta_n - T_n)/T_n,
  * |r_n(G)| sqrt(npw_k)/||r_n||, T(G)] with T(G) = 1/2|k+G|^2 (Ha), T_n the
  * band kinetic energy <x_n|T|x_n> and x = T(G)/T_n; hidden layer 128 with SiLU;
- * output the complex gain g = (g_re, g_im); correction t_n(G) = g r_n(G).
+ * two outputs o; complex gain g = K(x) [exp(2 tanh o_0) + 0.5 i tanh o_1] with
+ * K(x) = (27 + 18x + 12x^2 + 8x^3) / (27 + 18x + 12x^2 + 8x^3 + 16x^4) (Teter,
+ * Payne and Allan); correction t_n(G) = g r_n(G).  A zero output layer gives
+ * the Teter preconditioner exactly; the real factor stays within [e^-2, e^2].
  * Weights: one device float32 buffer of QM_MLP_NPARAM numbers laid out
  * W1[128][5], b1[128], W2[2][128], b2[2]. */
 #define QM_MLP_NIN 5

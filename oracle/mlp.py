@@ -7,8 +7,13 @@ and band n with shared weights, so it does not depend on the basis size:
     f(G, n) = [x, log(1 + x), (theta_n - T_n) / T_n, |r_n(G)| sqrt(npw) / ||r_n||, 1/2|k+G|^2]
               x = (1/2|k+G|^2) / T_n,  T_n = <x_n|T|x_n> the band kinetic energy
     h = silu(W1 f + b1)             W1 [128, 5], b1 [128]
-    g = W2 h + b2                   W2 [2, 128], b2 [2];  g = g_re + i g_im
+    o = W2 h + b2                   W2 [2, 128], b2 [2]
+    g = K(x) [exp(2 tanh o_0) + 0.5 i tanh o_1]      K = Teter-Payne-Allan factor
     t_n(G) = g(G, n) r_n(G)
+
+The network only reshapes the Teter preconditioner, by a real factor within
+[e^-2, e^2] and a small imaginary part; with a zero output layer it is Teter
+exactly, which is both its starting point and its fallback.
 
 t is invariant in form under a global phase of r (g depends on phase-free inputs).
 Training target: the direction delta_n the Ritz vector still has to move, with
@@ -18,8 +23,8 @@ the per-band scale- and phase-free loss
 
 Parameter vector layout (float64 here, float32 on the GPU): W1 (row-major),
 b1, W2 (row-major), b2 -> 128*5 + 128 + 2*128 + 2 = 1026 numbers.
-Parity pins: finite differences of the loss, the g = 1 special case (t = r),
-Adam's published update rule.
+Parity pins: finite differences of the loss, the zero-output-layer case (g = Teter's
+K(x), loss written out with np.vdot), the bounds on g, Adam's published update rule.
 """
 import numpy as np
 
@@ -41,14 +46,17 @@ def pack(W1, b1, W2, b2):
     return np.concatenate([W1.ravel(), b1, W2.ravel(), b2])
 
 
-def init_weights(seed=0, teter_like=True):
-    """Small random weights; b2 = (1, 0) so the untrained network passes r through."""
+def init_weights(seed=0):
+    """Random hidden layer, zero output layer: the untrained network is the Teter gain."""
     rng = np.random.Generator(np.random.PCG64(seed))
     W1 = rng.standard_normal((NHID, NIN)) * np.sqrt(1.0 / NIN)
     b1 = np.zeros(NHID)
-    W2 = rng.standard_normal((2, NHID)) * (0.01 / np.sqrt(NHID))
-    b2 = np.array([1.0, 0.0]) if teter_like else np.zeros(2)
-    return pack(W1, b1, W2, b2)
+    return pack(W1, b1, np.zeros((2, NHID)), np.zeros(2))
+
+
+def teter_factor(x):
+    num = 27.0 + x * (18.0 + x * (12.0 + 8.0 * x))
+    return num / (num + 16.0 * x ** 4)
 
 
 def features(kin, r, theta, tkin):
@@ -70,7 +78,9 @@ def forward(w, f):
     """f [..., 5] -> gain [..., 2] (re, im)."""
     W1, b1, W2, b2 = unpack(w)
     h = silu(f @ W1.T + b1)
-    return h @ W2.T + b2
+    o = h @ W2.T + b2
+    k = teter_factor(f[..., 0])
+    return np.stack([k * np.exp(2.0 * np.tanh(o[..., 0])), k * 0.5 * np.tanh(o[..., 1])], -1)
 
 
 def loss(w, f, r, delta, band_ptr):
@@ -92,7 +102,11 @@ def loss_grad(w, f, r, delta, band_ptr):
     z = f @ W1.T + b1
     sg = 1.0 / (1.0 + np.exp(-z))
     h = z * sg
-    g = h @ W2.T + b2
+    o = h @ W2.T + b2
+    k = teter_factor(f[:, 0])
+    th0, th1 = np.tanh(o[:, 0]), np.tanh(o[:, 1])
+    e0 = np.exp(2.0 * th0)
+    g = np.stack([k * e0, k * 0.5 * th1], -1)
     t = (g[:, 0] + 1j * g[:, 1]) * r
     nb = len(band_ptr) - 1
     dt = np.zeros_like(t)
@@ -109,7 +123,10 @@ def loss_grad(w, f, r, delta, band_ptr):
         dt[s] = -dc / nb
     # t = g r:  dL/dg_re = Re(conj(dt) r), dL/dg_im = -Im(conj(dt) r)
     q = np.conj(dt) * r
-    dg = np.stack([q.real, -q.imag], -1)
+    dgain = np.stack([q.real, -q.imag], -1)
+    # through g_re = k exp(2 tanh o0), g_im = 0.5 k tanh o1
+    dg = np.stack([dgain[:, 0] * k * e0 * 2.0 * (1.0 - th0 ** 2),
+                   dgain[:, 1] * k * 0.5 * (1.0 - th1 ** 2)], -1)
     dW2 = dg.T @ h
     db2 = dg.sum(0)
     dh = dg @ W2

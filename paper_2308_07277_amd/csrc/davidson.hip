@@ -99,7 +99,7 @@ static DavState* dav_create(qm_hpsi_plan* p, int k0, int k1, int nb, int mb) {
     d->resn = dalloc<double>(nk * nb);
     d->tkin = dalloc<double>(nk * nb);
     d->yw = dalloc<double>(nk * nb * mb);
-    d->fw = dalloc<double>(nk * nb * 5 * mb);
+    d->fw = dalloc<double>(nk * nb * 3 * mb);
     d->unconv = dalloc<int32_t>(nk * nb);
     d->info = dalloc<int32_t>(nk);
     d->goff = dalloc<int64_t>(nk);
@@ -206,7 +206,8 @@ static void rayleigh_ritz(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipSt
   hipLaunchKernelGGL(k_tridiag, dim3(jobs.n), dim3(1024), size_t(4) * d->mb * sizeof(double2), s,
                      jobs, d->Aw, d->d, d->e, d->tau);
   QM_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_tridiag_eig, dim3(jobs.n), dim3(1024), size_t(2) * d->mb * sizeof(double), s,
+  hipLaunchKernelGGL(k_tridiag_eig, dim3(jobs.n), dim3(1024),
+                     (size_t(3) * d->mb + size_t(2) * d->nb) * sizeof(double), s,
                      jobs, d->d, d->e, d->theta, d->yw, d->fw);
   QM_HIP(hipGetLastError());
   // Z slice + one reflector must fit in the 160 KiB of LDS

@@ -209,158 +209,269 @@ __global__ void __launch_bounds__(1024) k_tridiag(DJobs jobs, double2* __restric
 }
 
 // ---------------------------------------------------------------- tridiagonal eigenpairs
-__device__ int sturm_count(const double* d, const double* e, int m, double x, double pivmin) {
+// Number of eigenvalues of the tridiagonal (diagonal d, squared off-diagonal e2) below x.
+__device__ int sturm_count(const double* d, const double* e2, int m, double x, double pivmin) {
   int c = 0;
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
-  if (q < 0) ++c;
+  c += q < 0.0;
   for (int i = 1; i < m; ++i) {
-    q = d[i] - x - e[i - 1] * e[i - 1] / q;
+    q = (d[i] - x) - e2[i - 1] / q;
     if (fabs(q) < pivmin) q = -pivmin;
-    if (q < 0) ++c;
+    c += q < 0.0;
   }
   return c;
 }
 
+// deterministic start vector of inverse iteration, entries in [0.5, 1.5)
+__device__ __forceinline__ double inviter_start(int i, int n) {
+  uint32_t h = uint32_t(i + 1) * 0x9E3779B1u ^ uint32_t(n + 1) * 0x85EBCA77u;
+  h ^= h >> 15;
+  h *= 0x2C1B3C6Du;
+  h ^= h >> 12;
+  h *= 0x297A2D39u;
+  h ^= h >> 15;
+  return 0.5 + double(h) * 2.3283064365386963e-10;
+}
+
+__device__ __forceinline__ double wave_sum_all(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
 // theta[k][0..nb) ascending and real eigenvectors Y[k][i][n] of the tridiagonal (i < m,
-// n < nb; n fastest so the per-eigenvector recurrences of a wave are coalesced).
-// fw: [k][5][mb][nb] LU workspace, same interleaving.  d and e are staged in LDS.
+// n < nb; n fastest, so lanes working on consecutive eigenvectors touch consecutive
+// addresses).  fw: [k][3][mb][nb] upper factor (diagonal, two superdiagonals) of the
+// pivoted LU of T - lambda_n I, same interleaving.
+//   1. Eigenvalues: multisection on Sturm counts.  S lanes of a wave share one
+//      eigenvalue; each round their S points cut the bracket into S + 1 parts.
+//   2. Eigenvectors: three steps of inverse iteration, one lane per eigenvalue.  The
+//      sweep that eliminates the right-hand side also recomputes the LU factors (from
+//      d and e in LDS), so it never reads what it has written; the back substitution
+//      prefetches a block of rows ahead.  Eigenvalues closer than ortol form clusters
+//      whose vectors are re-orthogonalised (modified Gram-Schmidt, one wave per cluster)
+//      after every step, which gives degenerate levels orthonormal vectors.
+constexpr int kInvBlk = 8;  // rows prefetched ahead in the forward sweep
+constexpr int kBwdBlk = 4;  // and in the back substitution (four streams)
 __global__ void __launch_bounds__(1024) k_tridiag_eig(DJobs jobs, const double* __restrict__ dd,
                                                       const double* __restrict__ ee,
                                                       double* __restrict__ theta,
                                                       double* __restrict__ yw,
                                                       double* __restrict__ fw) {
-  extern __shared__ double sde[];  // d [mb], e [mb]
+  extern __shared__ double sde[];  // d [mb], e [mb], e^2 [mb], eigenvalues [nb], shifts [nb]
   const DJob& J = jobs.j[blockIdx.x];
   const int mb = jobs.mb, nb = jobs.nb, m = J.m;
   double* sd = sde;
-  double* se = sde + mb;
+  double* se = sd + mb;
+  double* se2 = se + mb;
+  double* sth = se2 + mb;
+  double* slam = sth + nb;
   double* th = theta + int64_t(J.k) * mb;
   double* Y = yw + int64_t(J.k) * nb * mb;
-  double* F = fw + int64_t(J.k) * nb * 5 * mb;
+  double* FD = fw + int64_t(J.k) * nb * 3 * mb;
+  double* FU1 = FD + int64_t(mb) * nb;
+  double* FU2 = FU1 + int64_t(mb) * nb;
   __shared__ double s_lo, s_hi, s_norm;
   __shared__ int s_cl[1025];
   __shared__ int s_ncl;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
   for (int i = tid; i < m; i += blockDim.x) {
+    const double ev = ee[int64_t(J.k) * mb + i];
     sd[i] = dd[int64_t(J.k) * mb + i];
-    se[i] = ee[int64_t(J.k) * mb + i];
+    se[i] = ev;
+    se2[i] = ev * ev;
   }
   __syncthreads();
   const int nwant = min(nb, m);
-  if (tid == 0) {
-    double lo = 1e300, hi = -1e300, nrm = 0.0;
-    for (int i = 0; i < m; ++i) {
+  if (wave == 0) {  // Gershgorin bounds and a norm estimate
+    double lo = 1e300, hi = -1e300, nr = 0.0;
+    for (int i = lane; i < m; i += 64) {
       const double r = (i > 0 ? fabs(se[i - 1]) : 0.0) + (i < m - 1 ? fabs(se[i]) : 0.0);
       lo = fmin(lo, sd[i] - r);
       hi = fmax(hi, sd[i] + r);
-      nrm = fmax(nrm, fabs(sd[i]) + r);
+      nr = fmax(nr, fabs(sd[i]) + r);
     }
-    s_lo = lo;
-    s_hi = hi;
-    s_norm = fmax(nrm, 1e-300);
+    for (int o = 32; o > 0; o >>= 1) {
+      lo = fmin(lo, __shfl_xor(lo, o, 64));
+      hi = fmax(hi, __shfl_xor(hi, o, 64));
+      nr = fmax(nr, __shfl_xor(nr, o, 64));
+    }
+    if (lane == 0) {
+      s_lo = lo;
+      s_hi = hi;
+      s_norm = fmax(nr, 1e-300);
+    }
   }
   __syncthreads();
   const double eps = 2.220446049250313e-16;
   const double nrm = s_norm;
   const double pivmin = fmax(1e-290, eps * eps * nrm * nrm * 1e-6);
-  for (int n = tid; n < nwant; n += blockDim.x) {
+  const double atol = 1e-3 * eps * nrm;
+  // 1. multisection: S in {1, 2, 4, 8, 16} lanes per eigenvalue, groups never straddle waves
+  int S = 1;
+  while (S < 16 && nwant * S * 2 <= int(blockDim.x)) S *= 2;
+  const int ngroups = int(blockDim.x) / S, sl = tid % S;
+  const uint64_t gmask = (S == 64 ? ~0ull : ((1ull << S) - 1)) << ((lane / S) * S);
+  for (int n = tid / S; n < nwant; n += ngroups) {
     double lo = s_lo - 4 * eps * nrm, hi = s_hi + 4 * eps * nrm;
     for (int it = 0; it < 256; ++it) {
-      const double mid = 0.5 * (lo + hi);
-      if (mid <= lo || mid >= hi) break;
-      if (hi - lo <= 2.0 * eps * fmax(fabs(lo), fabs(hi))) break;
-      if (sturm_count(sd, se, m, mid, pivmin) <= n) lo = mid;
-      else hi = mid;
+      if (hi - lo <= fmax(2.0 * eps * fmax(fabs(lo), fabs(hi)), atol)) break;
+      const double w = (hi - lo) / double(S + 1);
+      const bool below = sturm_count(sd, se2, m, lo + w * double(sl + 1), pivmin) <= n;
+      // the lanes of this group whose point lies at or below lambda_n form a prefix
+      const int j = __popcll(__ballot(below) & gmask);
+      const double nlo = j == 0 ? lo : lo + w * double(j);
+      const double nhi = j == S ? hi : lo + w * double(j + 1);
+      if (nlo == lo && nhi == hi) break;
+      lo = nlo;
+      hi = nhi;
     }
-    th[n] = 0.5 * (lo + hi);
+    if (sl == 0) {
+      const double t = 0.5 * (lo + hi);
+      th[n] = t;
+      sth[n] = t;
+    }
   }
   __syncthreads();
+  // clusters (gap > ortol starts a new one) and shifts nudged apart inside a cluster
   const double ortol = 1e-5 * nrm;  // inter-cluster orthogonality ~ eps / 1e-5
+  const double tiny = eps * nrm;
   if (tid == 0) {
     int nc = 0;
     s_cl[nc++] = 0;
-    for (int n = 1; n < nwant; ++n)
-      if (th[n] - th[n - 1] > ortol && nc < 1024) s_cl[nc++] = n;
+    double prev = sth[0];
+    slam[0] = prev;
+    for (int n = 1; n < nwant; ++n) {
+      const double t = sth[n];
+      if (t - sth[n - 1] > ortol && nc < 1024) {
+        s_cl[nc++] = n;
+        prev = t;
+      } else {
+        prev = t - prev < 10.0 * tiny ? prev + 10.0 * tiny : t;
+      }
+      slam[n] = prev;
+    }
     s_cl[nc] = nwant;
     s_ncl = nc;
   }
   __syncthreads();
-  const double tiny = eps * nrm;
   const int64_t st = nb;  // stride between consecutive elements of one vector
-  for (int c = tid; c < s_ncl; c += blockDim.x) {
-    const int n0 = s_cl[c], n1 = s_cl[c + 1];
-    double prev = -1e300;
-    for (int n = n0; n < n1; ++n) {
-      double lam = th[n];
-      if (n > n0 && lam - prev < 10.0 * tiny) lam = prev + 10.0 * tiny;
-      prev = lam;
+  for (int step = 0; step < 3; ++step) {
+    for (int n = tid; n < nwant; n += blockDim.x) {
+      const double lam = slam[n];
       double* y = Y + n;
-      double* D = F + n;
-      double* U1 = D + int64_t(mb) * nb;
-      double* U2 = U1 + int64_t(mb) * nb;
-      double* M = U2 + int64_t(mb) * nb;
-      double* P = M + int64_t(mb) * nb;
-      // LU with partial pivoting of T - lam I
-      for (int i = 0; i < m; ++i) {
-        D[i * st] = sd[i] - lam;
-        U1[i * st] = i < m - 1 ? se[i] : 0.0;
-        M[i * st] = i < m - 1 ? se[i] : 0.0;
-        U2[i * st] = 0.0;
-        P[i * st] = 0.0;
+      double* D = FD + n;
+      double* U1 = FU1 + n;
+      double* U2 = FU2 + n;
+      // forward sweep: row i of the LU (partial pivoting) of T - lam I and of the
+      // eliminated right-hand side; b is the previous iterate (start vector at step 0)
+      double dcur = sd[0] - lam, u1 = m > 1 ? se[0] : 0.0;
+      double bcur = step == 0 ? inviter_start(0, n) : y[0];
+      double bq[kInvBlk];
+#pragma unroll
+      for (int q = 0; q < kInvBlk; ++q) {
+        const int r = q + 1;
+        bq[q] = r < m ? (step == 0 ? inviter_start(r, n) : y[r * st]) : 0.0;
       }
-      double dcur = D[0];
-      for (int i = 0; i < m - 1; ++i) {
-        const double sub = M[i * st];
-        if (fabs(dcur) >= fabs(sub)) {
-          const double f = dcur != 0.0 ? sub / dcur : 0.0;
-          D[i * st] = dcur;
-          M[i * st] = f;
-          dcur = D[(i + 1) * st] - f * U1[i * st];
-        } else {
-          const double f = dcur / sub;
-          D[i * st] = sub;
-          M[i * st] = f;
-          const double t = U1[i * st];
-          const double dn = D[(i + 1) * st];
-          U1[i * st] = dn;
-          dcur = t - f * dn;
-          if (i < m - 2) {
-            U2[i * st] = U1[(i + 1) * st];
-            U1[(i + 1) * st] = -f * U1[(i + 1) * st];
-          }
-          P[i * st] = 1.0;
+      for (int ib = 0; ib < m - 1; ib += kInvBlk) {
+        double bn[kInvBlk];
+#pragma unroll
+        for (int q = 0; q < kInvBlk; ++q) {  // next block's right-hand side, ahead of the stores
+          const int r = ib + kInvBlk + q + 1;
+          bn[q] = r < m ? (step == 0 ? inviter_start(r, n) : y[r * st]) : 0.0;
         }
-      }
-      D[(m - 1) * st] = dcur;
-      for (int i = 0; i < m; ++i)
-        if (fabs(D[i * st]) < tiny) D[i * st] = D[i * st] < 0.0 ? -tiny : tiny;
-      for (int i = 0; i < m; ++i) y[i * st] = 1.0 + 0.5 * sin(0.7 * double(i + 1) + 1.3 * double(n + 1));
-      for (int it = 0; it < 3; ++it) {
-        for (int i = 0; i < m - 1; ++i) {
-          if (P[i * st] == 0.0) {
-            y[(i + 1) * st] -= M[i * st] * y[i * st];
+#pragma unroll
+        for (int q = 0; q < kInvBlk; ++q) {
+          const int i = ib + q;
+          if (i >= m - 1) break;
+          const double sub = se[i];
+          const double anext = sd[i + 1] - lam;
+          const double enext = i + 1 < m - 1 ? se[i + 1] : 0.0;
+          const double bnext = bq[q];
+          if (fabs(dcur) >= fabs(sub)) {
+            const double f = dcur != 0.0 ? sub / dcur : 0.0;
+            D[i * st] = fabs(dcur) < tiny ? (dcur < 0.0 ? -tiny : tiny) : dcur;
+            U1[i * st] = u1;
+            U2[i * st] = 0.0;
+            y[i * st] = bcur;
+            bcur = bnext - f * bcur;
+            dcur = anext - f * u1;
+            u1 = enext;
           } else {
-            const double t = y[i * st];
-            y[i * st] = y[(i + 1) * st];
-            y[(i + 1) * st] = t - M[i * st] * y[i * st];
+            const double f = dcur / sub;
+            D[i * st] = fabs(sub) < tiny ? (sub < 0.0 ? -tiny : tiny) : sub;
+            U1[i * st] = anext;
+            U2[i * st] = enext;
+            y[i * st] = bnext;
+            bcur = bcur - f * bnext;
+            dcur = u1 - f * anext;
+            u1 = -f * enext;
           }
         }
-        y[(m - 1) * st] /= D[(m - 1) * st];
-        if (m > 1) y[(m - 2) * st] = (y[(m - 2) * st] - U1[(m - 2) * st] * y[(m - 1) * st]) / D[(m - 2) * st];
-        for (int i = m - 3; i >= 0; --i)
-          y[i * st] = (y[i * st] - U1[i * st] * y[(i + 1) * st] - U2[i * st] * y[(i + 2) * st]) / D[i * st];
-        for (int q = n0; q < n; ++q) {
-          double s = 0.0;
-          for (int i = 0; i < m; ++i) s += y[i * st] * Y[i * st + q];
-          for (int i = 0; i < m; ++i) y[i * st] -= s * Y[i * st + q];
+#pragma unroll
+        for (int q = 0; q < kInvBlk; ++q) bq[q] = bn[q];
+      }
+      // back substitution with U (rows m-1 .. 0), a block of rows prefetched ahead
+      const double dl = fabs(dcur) < tiny ? (dcur < 0.0 ? -tiny : tiny) : dcur;
+      double y1 = bcur / dl, y2 = 0.0;
+      y[(m - 1) * st] = y1;
+      double pz[kBwdBlk], pu1[kBwdBlk], pu2[kBwdBlk], pd[kBwdBlk];
+#pragma unroll
+      for (int q = 0; q < kBwdBlk; ++q) {
+        const int i = m - 2 - q;
+        const bool ok = i >= 0;
+        pz[q] = ok ? y[i * st] : 0.0;
+        pu1[q] = ok ? U1[i * st] : 0.0;
+        pu2[q] = ok ? U2[i * st] : 0.0;
+        pd[q] = ok ? D[i * st] : 1.0;
+      }
+      for (int ib = m - 2; ib >= 0; ib -= kBwdBlk) {
+        double nz[kBwdBlk], nu1[kBwdBlk], nu2[kBwdBlk], nd[kBwdBlk];
+#pragma unroll
+        for (int q = 0; q < kBwdBlk; ++q) {
+          const int i = ib - kBwdBlk - q;
+          const bool ok = i >= 0;
+          nz[q] = ok ? y[i * st] : 0.0;
+          nu1[q] = ok ? U1[i * st] : 0.0;
+          nu2[q] = ok ? U2[i * st] : 0.0;
+          nd[q] = ok ? D[i * st] : 1.0;
         }
-        double s = 0.0;
-        for (int i = 0; i < m; ++i) s += y[i * st] * y[i * st];
-        s = 1.0 / sqrt(s);
-        for (int i = 0; i < m; ++i) y[i * st] *= s;
+#pragma unroll
+        for (int q = 0; q < kBwdBlk; ++q) {
+          const int i = ib - q;
+          if (i < 0) break;
+          const double yi = (pz[q] - pu1[q] * y1 - pu2[q] * y2) / pd[q];
+          y[i * st] = yi;
+          y2 = y1;
+          y1 = yi;
+        }
+#pragma unroll
+        for (int q = 0; q < kBwdBlk; ++q) {
+          pz[q] = nz[q];
+          pu1[q] = nu1[q];
+          pu2[q] = nu2[q];
+          pd[q] = nd[q];
+        }
       }
     }
+    __syncthreads();
+    // modified Gram-Schmidt inside each cluster, then unit norm; one wave per cluster
+    for (int c = wave; c < s_ncl; c += nwaves) {
+      const int n0 = s_cl[c], n1 = s_cl[c + 1];
+      for (int n = n0; n < n1; ++n) {
+        for (int q = n0; q < n; ++q) {
+          double s = 0.0;
+          for (int i = lane; i < m; i += 64) s += Y[i * st + n] * Y[i * st + q];
+          s = wave_sum_all(s);
+          for (int i = lane; i < m; i += 64) Y[i * st + n] -= s * Y[i * st + q];
+        }
+        double s = 0.0;
+        for (int i = lane; i < m; i += 64) s += Y[i * st + n] * Y[i * st + n];
+        s = 1.0 / sqrt(wave_sum_all(s));
+        for (int i = lane; i < m; i += 64) Y[i * st + n] *= s;
+      }
+    }
+    __syncthreads();
   }
 }
 

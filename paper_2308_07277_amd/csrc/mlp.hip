@@ -1,7 +1,9 @@
 // Learned residual -> correction preconditioner for the Davidson (an extension of
 // the paper's solver, Sec. 5 'dft' module): a per-(G, band) network with shared
-// weights, 5 inputs -> 128 SiLU -> 2 outputs (re, im of a complex gain g), and the
-// correction t_n(G) = g(G, n) r_n(G).  Features:
+// weights, 5 inputs -> 128 SiLU -> 2 outputs o, a complex gain
+//   g = K(x) [exp(2 tanh o_0) + 0.5 i tanh o_1],   K(x) the Teter-Payne-Allan factor,
+// and the correction t_n(G) = g(G, n) r_n(G).  The network only reshapes Teter, by a
+// real factor in [e^-2, e^2]; with a zero output layer it is Teter exactly.  Features:
 //   x = T(G)/T_n, log(1 + x), (theta_n - T_n)/T_n, |r_n(G)| sqrt(npw)/||r_n||, T(G)
 // with T(G) = 1/2|k+G|^2 and T_n = <x_n|T|x_n>.  Weights are float32:
 // W1[128][5], b1[128], W2[2][128], b2[2].
@@ -22,7 +24,13 @@ constexpr int OW1 = 0, OB1 = NH * NIN, OW2 = OB1 + NH, OB2 = OW2 + 2 * NH;
 
 __device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
 
-__device__ __forceinline__ void mlp_fwd(const float* __restrict__ w, const float f[NIN], float& g0,
+__device__ __forceinline__ float teter_k(float x) {
+  const float num = 27.0f + x * (18.0f + x * (12.0f + 8.0f * x));
+  return num / (num + 16.0f * x * x * x * x);
+}
+
+// raw network outputs o_0, o_1
+__device__ __forceinline__ void mlp_out(const float* __restrict__ w, const float f[NIN], float& g0,
                                         float& g1) {
   float a0 = w[OB2], a1 = w[OB2 + 1];
 #pragma unroll 8
@@ -36,6 +44,16 @@ __device__ __forceinline__ void mlp_fwd(const float* __restrict__ w, const float
   }
   g0 = a0;
   g1 = a1;
+}
+
+// gain (re, im) from the features (f[0] = x)
+__device__ __forceinline__ void mlp_fwd(const float* __restrict__ w, const float f[NIN], float& g0,
+                                        float& g1) {
+  float o0, o1;
+  mlp_out(w, f, o0, o1);
+  const float k = teter_k(f[0]);
+  g0 = k * __expf(2.0f * tanhf(o0));
+  g1 = 0.5f * k * tanhf(o1);
 }
 
 __device__ __forceinline__ void make_feat(double kin, double tn, double theta, double ramp, float f[NIN]) {
@@ -185,7 +203,7 @@ __global__ void __launch_bounds__(256) k_mlp_loss_grad(const float* __restrict__
         f[i] = feat[int64_t(r) * NIN + i];
         sf[tid][i] = f[i];
       }
-      float g0 = w[OB2], g1 = w[OB2 + 1];
+      float o0 = w[OB2], o1 = w[OB2 + 1];
       for (int u = 0; u < NH; ++u) {
         float z = w[OB1 + u];
 #pragma unroll
@@ -194,18 +212,21 @@ __global__ void __launch_bounds__(256) k_mlp_loss_grad(const float* __restrict__
         const float h = z * sg;
         sh[tid][u] = h;
         sdz[tid][u] = sg * (1.0f + z * (1.0f - sg));  // silu'(z), scaled by dh below
-        g0 += w[OW2 + u] * h;
-        g1 += w[OW2 + NH + u] * h;
+        o0 += w[OW2 + u] * h;
+        o1 += w[OW2 + NH + u] * h;
       }
+      const float kx = teter_k(f[0]), th0 = tanhf(o0), th1 = tanhf(o1);
+      const float e0 = __expf(2.0f * th0);
+      const float g0 = kx * e0, g1 = 0.5f * kx * th1;
       const double rr = resid[2 * int64_t(r)], ri = resid[2 * int64_t(r) + 1];
       const double tr = g0 * rr - g1 * ri, ti = g0 * ri + g1 * rr;
       const double dr = target[2 * int64_t(r)], di = target[2 * int64_t(r) + 1];
       // conj(a) delta = (ar - i ai)(dr + i di)
       const double cr = ar * dr + ai * di, ci = ar * di - ai * dr;
       const double dtr = -inv * (s1 * cr - s2 * tr), dti = -inv * (s1 * ci - s2 * ti);
-      // dL/dg_re = Re(conj(dt) r), dL/dg_im = -Im(conj(dt) r)
-      const float dg0 = float(dtr * rr + dti * ri);
-      const float dg1 = float(-(dtr * ri - dti * rr));
+      // dL/dg_re = Re(conj(dt) r), dL/dg_im = -Im(conj(dt) r); then through the output map
+      const float dg0 = float(dtr * rr + dti * ri) * kx * e0 * 2.0f * (1.0f - th0 * th0);
+      const float dg1 = float(-(dtr * ri - dti * rr)) * 0.5f * kx * (1.0f - th1 * th1);
       sdg[tid][0] = dg0;
       sdg[tid][1] = dg1;
       for (int u = 0; u < NH; ++u) {

@@ -16,13 +16,11 @@ from . import (QM_MLP_NPARAM, qm_davidson_solve, qm_davidson_step, qm_dav_traini
 
 
 def init_weights(seed=0):
-    """W1 ~ N(0, 1/5), W2 ~ 0.01 N(0, 1/128), b1 = 0, b2 = (1, 0): starts as the plain residual."""
+    """W1 ~ N(0, 1/5), b1 = 0, W2 = 0, b2 = 0: the untrained network is the Teter gain."""
     import torch
     rng = np.random.Generator(np.random.PCG64(seed))
     w = np.zeros(QM_MLP_NPARAM, np.float32)
     w[:640] = rng.standard_normal(640) * np.sqrt(1.0 / 5.0)
-    w[768:1024] = rng.standard_normal(256) * (0.01 / np.sqrt(128.0))
-    w[1024] = 1.0
     return torch.from_numpy(w).cuda()
 
 

@@ -35,7 +35,7 @@ def test_forward_and_grad_vs_oracle():
     import paper_2308_07277_amd as qm
     f, r, d, ptr = _data()
     w = omlp.init_weights(2)
-    w[768:1024] = np.random.default_rng(3).standard_normal(256) * 0.2
+    w[768:1026] = np.random.default_rng(3).standard_normal(258) * 0.2   # non-zero output layer
     w32 = w.astype(np.float32).astype(np.float64)   # compare on the float32-rounded weights
     gain = torch.empty((f.shape[0], 2), dtype=torch.float32, device="cuda")
     qm.qm_mlp_forward(_t(w32, np.float32), _t(f, np.float32), gain, f.shape[0])

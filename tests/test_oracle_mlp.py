@@ -19,7 +19,7 @@ def _data(seed=0, nb=3, npw=40):
 def test_gradient_matches_finite_differences():
     f, r, d, ptr = _data()
     w = mlp.init_weights(3)
-    w[-256 - 2:-2] = np.random.default_rng(1).standard_normal(256) * 0.3   # non-trivial W2
+    w[-256 - 2:] = np.random.default_rng(1).standard_normal(258) * 0.3   # non-trivial W2, b2
     L, g = mlp.loss_grad(w, f, r, d, ptr)
     assert abs(L - mlp.loss(w, f, r, d, ptr)) < 1e-14
     rng = np.random.default_rng(2)
@@ -33,17 +33,31 @@ def test_gradient_matches_finite_differences():
         assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (i, fd, g[i])
 
 
-def test_unit_gain_is_plain_residual():
-    """W2 = 0, b2 = (1, 0): g = 1, t = r, so the loss is 1 - cos^2(r, delta) per band."""
+def test_zero_output_layer_is_teter():
+    """W2 = 0, b2 = 0: g = K(x) (Teter, Payne and Allan), so t = K(x) r; the loss is the
+    cosine loss of the Teter correction, written out with np.vdot."""
     f, r, d, ptr = _data(4)
-    W1, b1, W2, b2 = mlp.unpack(mlp.init_weights(0))
-    w = mlp.pack(W1, b1, np.zeros_like(W2), np.array([1.0, 0.0]))
-    np.testing.assert_allclose(mlp.forward(w, f), np.tile([1.0, 0.0], (f.shape[0], 1)), atol=0)
+    w = mlp.init_weights(0)
+    x = f[:, 0]
+    num = 27 + 18 * x + 12 * x ** 2 + 8 * x ** 3
+    kx = num / (num + 16 * x ** 4)
+    np.testing.assert_allclose(mlp.forward(w, f), np.stack([kx, np.zeros_like(kx)], -1), rtol=1e-15)
     exp = 0.0
     for b in range(len(ptr) - 1):
         s = slice(ptr[b], ptr[b + 1])
-        exp += 1 - abs(np.vdot(r[s], d[s])) ** 2 / (np.linalg.norm(r[s]) ** 2 * np.linalg.norm(d[s]) ** 2)
+        t = kx[s] * r[s]
+        exp += 1 - abs(np.vdot(t, d[s])) ** 2 / (np.linalg.norm(t) ** 2 * np.linalg.norm(d[s]) ** 2)
     assert abs(mlp.loss(w, f, r, d, ptr) - exp / (len(ptr) - 1)) < 1e-14
+
+
+def test_gain_is_bounded_around_teter():
+    """Whatever the weights, e^-2 K(x) <= Re g <= e^2 K(x) and |Im g| <= K(x)/2."""
+    f, r, d, ptr = _data(8)
+    w = np.random.default_rng(9).standard_normal(mlp.NPARAM) * 3.0
+    g = mlp.forward(w, f)
+    kx = mlp.teter_factor(f[:, 0])
+    assert np.all(g[:, 0] >= np.exp(-2) * kx * (1 - 1e-12)) and np.all(g[:, 0] <= np.exp(2) * kx * (1 + 1e-12))
+    assert np.all(np.abs(g[:, 1]) <= 0.5 * kx * (1 + 1e-12))
 
 
 def test_loss_is_phase_and_scale_free():
@@ -53,6 +67,8 @@ def test_loss_is_phase_and_scale_free():
     assert abs(mlp.loss(w, f, r, d * (2.5 * np.exp(0.7j)), ptr) - L0) < 1e-13
     # a gain proportional to delta/r gives zero loss
     assert abs(mlp.loss(w, f, r, r * 3j, ptr) - mlp.loss(w, f, r, r, ptr)) < 1e-13
+    # the loss is invariant under a common phase of r and delta
+    assert abs(mlp.loss(w, f, r * np.exp(0.3j), d * np.exp(0.3j), ptr) - L0) < 1e-13
 
 
 def test_adam_first_step():
