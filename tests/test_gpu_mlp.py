@@ -71,3 +71,58 @@ def test_adam_vs_oracle():
                                 v.astype(np.float64), 3, lr=0.01)
     assert np.abs(tw.cpu().numpy() - wr).max() <= 1e-6
     assert np.abs(tm.cpu().numpy() - mr).max() <= 1e-6
+
+
+def _dav_iters(plan, w, start, **kw):
+    import paper_2308_07277_amd as qm
+    psi = start.clone()
+    eig, res, stats, st = qm.qm_davidson_solve(plan, -1, psi, w.nbnd, tol=1e-8, max_iter=300,
+                                               max_basis=4 * w.nbnd, **kw)
+    assert st == 0 and res.max() <= 1e-8
+    return stats["iterations"], eig
+
+
+def test_untrained_network_is_teter_inside_davidson():
+    """Zero output layer: the gain is K(x) (computed in float32 in the kernel), so the
+    Davidson with the network takes Teter's path: same iteration count within one, same
+    eigenvalues within 1e-10 Ha (both runs converge to a 1e-8 Ha residual)."""
+    import torch
+    import workload
+    import bench
+    import paper_2308_07277_amd as qm
+    from paper_2308_07277_amd import train as tr
+    w = workload.make_workload("c2")
+    plan = bench._plan_for(w)
+    start = torch.cat([torch.from_numpy(w.psi(ik, purpose=5).reshape(-1)) for ik in range(w.nk)]).cuda()
+    it_t, eig_t = _dav_iters(plan, w, start, precond=qm.QM_PRECOND_TETER)
+    it_m, eig_m = _dav_iters(plan, w, start, precond=qm.QM_PRECOND_MLP, mlp_weights=tr.init_weights(0))
+    plan.close()
+    print("teter", it_t, "untrained network", it_m)
+    assert abs(it_t - it_m) <= 1
+    assert np.abs(eig_t - eig_m).max() <= 1e-10
+
+
+def test_trained_network_gain_on_small_cell():
+    """What the trained network gains: trained on the two 8-atom cells (start vectors of
+    seed purpose 2), then a Davidson on the 8-atom 25 Ry cell from a different start
+    (purpose 5).  Measured on MI355X: 22-23 iterations against Teter's 31 over three
+    training seeds and two start vectors.  The test asserts
+    fewer iterations than Teter and eigenvalues within 1e-9 Ha of Teter's.  (On the
+    64-atom cell the same network takes more iterations than Teter; the benchmark
+    reports both arms.)"""
+    import torch
+    import workload
+    import bench
+    import paper_2308_07277_amd as qm
+    weights, info = bench.train_preconditioner()
+    print(info)
+    assert info["loss_final"] < info["loss_teter"]
+    w = workload.make_workload("c2")
+    plan = bench._plan_for(w)
+    start = torch.cat([torch.from_numpy(w.psi(ik, purpose=5).reshape(-1)) for ik in range(w.nk)]).cuda()
+    it_t, eig_t = _dav_iters(plan, w, start, precond=qm.QM_PRECOND_TETER)
+    it_m, eig_m = _dav_iters(plan, w, start, precond=qm.QM_PRECOND_MLP, mlp_weights=weights)
+    plan.close()
+    print("teter", it_t, "trained network", it_m)
+    assert it_m < it_t
+    assert np.abs(eig_t - eig_m).max() <= 1e-9

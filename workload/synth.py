@@ -201,7 +201,8 @@ def config_names():
 def make_workload(name: str, nk_limit: int | None = None) -> Workload:
     """The five workload shapes: c1 fcc 2-atom 12 Ry 20^3 Gamma 8 bands; c2 8-atom cubic
     25 Ry 40^3 4 k 32 bands; c3 64-atom 30 Ry 72^3 16 k 160 bands; c4 the c3 cell with
-    Gamma + 16 k; c5 216-atom 30 Ry 108^3 Gamma 500 bands."""
+    Gamma + 16 k; c5 216-atom 30 Ry 108^3 Gamma 500 bands; t2 the 8-atom cell at 30 Ry with
+    12 k and 20 bands (training data for the learned preconditioner)."""
     name = name.lower()
     if name == "c1":
         cell, atoms = cell_fcc2()
@@ -216,6 +217,14 @@ def make_workload(name: str, nk_limit: int | None = None) -> Workload:
         cell, atoms = cell_sc_diamond(2)
         w = dict(ecut_ry=30.0, grid=(72, 72, 72),
                  k_cryst=np.concatenate([np.zeros((1, 3)), kmesh_c3()]), nbnd=160, index=4)
+    elif name == "t2":
+        # training cell for the learned preconditioner: the 8-atom cell at the 64-atom
+        # cell's cutoff, k-points {0, 1/2}^3 (the 64-atom Gamma point unfolded) plus the
+        # c2 mesh, 20 bands per k (the 64-atom cell's 160 bands per 8 unfolded k-points)
+        cell, atoms = cell_sc_diamond(1)
+        kf = np.array([[a, b, c] for a in (0, .5) for b in (0, .5) for c in (0, .5)], float)
+        w = dict(ecut_ry=30.0, grid=(40, 40, 40), k_cryst=np.concatenate([kf, kmesh_c2()]),
+                 nbnd=20, index=6)
     elif name == "c5":
         cell, atoms = cell_sc_diamond(3)
         w = dict(ecut_ry=30.0, grid=(108, 108, 108), k_cryst=np.zeros((1, 3)), nbnd=500, index=5)
