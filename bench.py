@@ -85,23 +85,62 @@ def algorithmic_model(w, prec):
     return out, tot_bands, nst
 
 
-def cpu_baseline(w, nb_sample):
-    """The FP64 oracle on one k-point and nb_sample bands, single thread."""
+# Files whose contents define the H|psi> kernels; the HBM traffic recorded from hardware
+# counters is reported only while their hash matches the one stored with the counters.
+KERNEL_SOURCES = ["cplx.h", "fft_kernels.h", "fft_launch.h", "fft_common.hip", "fft_f64.hip",
+                  "fft_f32.hip", "gemm.hip", "nonlocal.hip", "plan.hip", "qm_internal.h"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hpsi_c3_hbm_traffic.txt")
+
+
+def kernel_sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2308_07277_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(workload_name, prec, stage):
+    """HBM bytes per launch of the stage's kernel from the committed FETCH_SIZE /
+    WRITE_SIZE counter summary (each scaled by the copy calibration), or None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec, meta = None, {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if line.startswith("#") or "=" not in line:
+                continue
+            kv = dict(t.split("=", 1) for t in line.split())
+            if "sources_sha256" in kv:
+                meta = kv
+            elif kv.get("workload") == workload_name and kv.get("prec") == prec and kv.get("stage") == stage:
+                rec = kv
+    if rec is None or meta.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    return 1024.0 * (float(rec["fetch_kib"]) * float(meta["fetch_scale"]) +
+                     float(rec["write_kib"]) * float(meta["write_scale"]))
+
+
+def cpu_baseline(w, nb_sample, nk_sample=8):
+    """The FP64 oracle on the first nk_sample k-points with nb_sample bands each, one thread."""
     from threadpoolctl import threadpool_limits
     from oracle import hamiltonian as ham
-    ik = 0
-    m = w.miller[ik]
-    beta = w.beta(ik)
     v = w.vloc_r()
     d = w.dmat()
-    psi = w.psi(ik)[:nb_sample]
+    nk = min(nk_sample, w.nk)
+    dt = 0.0
     with threadpool_limits(1):
-        t0 = time.perf_counter()
-        ham.apply_h_ref(w.cell, w.grid, w.k_cryst[ik], m, v, beta, d, psi)
-        dt = time.perf_counter() - t0
-    return {"value": nb_sample / dt, "unit": "bands/s", "cores": 1, "kind": "oracle",
-            "sample": f"apply_h_ref (numpy FFT + BLAS, float64) on k-point 0 of the {w.name} "
-                      f"workload, {nb_sample} bands, {dt:.1f} s"}
+        for ik in range(nk):
+            beta = w.beta(ik)
+            psi = w.psi(ik)[:nb_sample]
+            t0 = time.perf_counter()
+            ham.apply_h_ref(w.cell, w.grid, w.k_cryst[ik], w.miller[ik], v, beta, d, psi)
+            dt += time.perf_counter() - t0
+    return {"value": nk * nb_sample / dt, "unit": "bands/s", "cores": 1, "kind": "oracle",
+            "sample": f"apply_h_ref (numpy FFT + BLAS, float64, one thread) on k-points 0-{nk - 1} "
+                      f"of the {w.name} workload, {nb_sample} bands each: {nk * nb_sample} band "
+                      f"applications in {dt:.1f} s"}
 
 
 def _plan_for(w, prec=0):
@@ -200,6 +239,8 @@ def main():
                     help="also time the FP64 Teter Davidson to 1e-8 Ha on the Gamma + 16 k cell")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample-bands", type=int, default=160)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy a MIB-sized device buffer (reference for HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -211,6 +252,13 @@ def main():
     import workload
     import paper_2308_07277_amd as qm
 
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration * 131072, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"copy calibration: {args.copy_calibration} MiB read and written", file=sys.stderr)
+        del src, dst
     w = workload.make_workload(args.workload)
     miller, beta, vloc, psi = build_inputs(w)
     plan = qm.qm_hpsi_plan_create(w.cell, w.grid, w.k_cart, w.npw, miller, w.nbnd, w.nproj,
@@ -257,16 +305,19 @@ def main():
     if bound == "hbm":
         achieved = amount / sec / 1e9
         roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": dom}
+                "frac": achieved / HBM_PEAK_GBS, "traffic": recorded_traffic(w.name, args.prec, dom),
+                "kernel": dom}
     elif bound == "alu":
         achieved = amount / sec / 1e12
         roof = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / ALU_PEAK_TFLOPS, "traffic": None, "kernel": dom}
+                "frac": achieved / ALU_PEAK_TFLOPS, "traffic": recorded_traffic(w.name, args.prec, dom),
+                "kernel": dom}
     else:
         dt_ = {"fp64": "f64", "fp32": "f32", "mixed": "bf16"}[args.prec]
         achieved = amount / sec / 1e12
         roof = {"bound": "mfma", "achieved": achieved, "peak": PEAK_TFLOPS[dt_], "unit": "TFLOP/s",
-                "frac": achieved / PEAK_TFLOPS[dt_], "traffic": None, "kernel": dom}
+                "frac": achieved / PEAK_TFLOPS[dt_], "traffic": recorded_traffic(w.name, args.prec, dom),
+                "kernel": dom}
     stage_rates = {}
     for k, (b, a) in model.items():
         if stages.get(k, 0) > 0:
