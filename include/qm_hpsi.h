@@ -126,8 +126,9 @@ typedef struct {
  *  out      receives the plan.
  * The plan copies V, beta and D (in its working precisions) and owns its
  * workspace, so inputs may be freed after the call returns.  Environment:
- * QM_XY_MODE=1 makes float64 plans on 20^3 and 40^3 grids use the two-pass xy-plane
- * kernel instead of the lane-pair kernel (same transform; for comparisons). */
+ * QM_XY_MODE=1 forces the two-pass xy-plane kernel, QM_XY_MODE=2 the lane-group kernel
+ * (grids of 20, 40 and 72 points along x; same transform, for comparisons); otherwise
+ * qm_hpsi_plan_autotune picks one per precision. */
 qm_status qm_hpsi_plan_create(const double cell[9], const int32_t grid[3], const qm_kset *ks,
                               int32_t nbnd_max, int32_t nproj, const double *vloc_r,
                               const void *beta, const double *dmat, qm_prec prec, void *stream,
@@ -148,10 +149,12 @@ qm_status qm_hpsi_plan_set_precision(qm_hpsi_plan *plan, qm_prec prec, void *str
  * kernels one by one.  Changing the mode drops the cached graphs. */
 qm_status qm_hpsi_plan_set_graphs(qm_hpsi_plan *plan, int32_t enable);
 
-/* Autotune the launch parameters of the projector GEMM (split-K count) for nbnd bands in
- * every precision, timing the candidates with HIP events on stream; the choice is kept in
- * the plan.  If the environment variable QM_AUTOTUNE_CACHE names a file, choices are read
- * from and written to it (one JSON object keyed by problem shape).  Synchronous. */
+/* Autotune for nbnd bands, timing the candidates with HIP events on stream: the split-K
+ * count of the projector GEMM in every precision, and the xy-plane FFT kernel (two-pass or
+ * lane-group, where the grid has both) of the float64 and float32 local parts.  The
+ * choices are kept in the plan.  If the environment variable QM_AUTOTUNE_CACHE names a
+ * file, choices are read from and written to it (one JSON object keyed by problem shape).
+ * Synchronous. */
 qm_status qm_hpsi_plan_autotune(qm_hpsi_plan *plan, int32_t nbnd, void *stream);
 
 /* ------------------------------------------------------------------ H|psi> */

@@ -203,7 +203,7 @@ static void rayleigh_ritz(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipSt
   hipLaunchKernelGGL(k_hs_copy, dim3(64, jobs.n), dim3(256), 0, s, jobs, d->Hs, d->Aw);
   QM_HIP(hipGetLastError());
   QM_HIP(hipEventRecord(d->ev[2], s));
-  hipLaunchKernelGGL(k_tridiag, dim3(jobs.n), dim3(1024), size_t(4) * d->mb * sizeof(double2), s,
+  hipLaunchKernelGGL(k_tridiag, dim3(jobs.n), dim3(1024), size_t(5) * d->mb * sizeof(double2), s,
                      jobs, d->Aw, d->d, d->e, d->tau);
   QM_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_tridiag_eig, dim3(jobs.n), dim3(1024),
@@ -304,7 +304,7 @@ static qm_status dav_step(qm_hpsi_plan* p, int k, void* psi, double* eig, double
   const double tol = (o && o->tol > 0) ? o->tol : 1e-8;
   int mb = (o && o->max_basis > 0) ? o->max_basis : 4 * nb;
   QM_REQUIRE(mb >= 2 * nb, QM_E_ARG, "max_basis must be at least 2 nbnd");
-  QM_REQUIRE(mb <= 2400, QM_E_ARG, "max_basis above 2400 is not supported");
+  QM_REQUIRE(mb <= 2000, QM_E_ARG, "max_basis above 2000 is not supported");
   const int precond = o ? o->precond : QM_PRECOND_TETER;
   QM_REQUIRE(precond == QM_PRECOND_TETER || (precond == QM_PRECOND_MLP && o->mlp_weights),
              QM_E_ARG, "QM_PRECOND_MLP needs mlp_weights");

@@ -38,6 +38,29 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
+// two block-wide sums at once (red holds 2 * waves values)
+__device__ void block_sum2(double& a, double& b, double* red) {
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_down(a, o, 64);
+    b += __shfl_down(b, o, 64);
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if (lane == 0) {
+    red[w] = a;
+    red[nw + w] = b;
+  }
+  __syncthreads();
+  double sa = 0.0, sb = 0.0;
+  for (int i = 0; i < nw; ++i) {
+    sa += red[i];
+    sb += red[nw + i];
+  }
+  __syncthreads();
+  a = sa;
+  b = sb;
+}
+
 // ---------------------------------------------------------------- Hermitian fill
 __global__ void k_hs_fill(DJobs jobs, double2* __restrict__ Hs) {
   const DJob& J = jobs.j[blockIdx.y];
@@ -76,48 +99,57 @@ __global__ void k_hs_copy(DJobs jobs, const double2* __restrict__ Hs, double2* _
 
 // ---------------------------------------------------------------- tridiagonalisation
 // Householder reduction with the rank-2 update of step j-1 applied lazily: step j first
-// brings column j up to date, builds its reflector, then makes one pass over the trailing
-// block that applies the pending update and accumulates p = tau A v at the same time (one
-// read and one write per element and step).  A (row-major, stride mb, full Hermitian) is
-// destroyed; column j below the subdiagonal receives v_j (v_j[j+1] = 1 implicit).
+// brings column j up to date, builds its reflector, then makes one pass over the lower
+// triangle of the trailing block that applies the pending update and accumulates
+// p = tau A v at the same time (one read and one write per stored element and step).
+// A stored element a_rc (c < r) serves both halves of the Hermitian product: a_rc v_c
+// goes to p_r (summed in the wave that owns row r) and conj(a_rc) v_r to p_c (summed
+// across waves with LDS atomics).  A (row-major, stride mb) holds the Hermitian matrix in
+// its lower triangle (the upper one is never read) and is destroyed; column j below the
+// subdiagonal receives v_j (v_j[j+1] = 1 implicit).
 __global__ void __launch_bounds__(1024) k_tridiag(DJobs jobs, double2* __restrict__ Aw,
                                                   double* __restrict__ dd, double* __restrict__ ee,
                                                   double2* __restrict__ tau) {
-  extern __shared__ double2 sh[];   // vA, vB, pA, pB: [mb] each
+  extern __shared__ double2 sh[];   // vA, vB, pA, pB, column sums: [mb] each
   const DJob& J = jobs.j[blockIdx.x];
   const int mb = jobs.mb, m = J.m;
   double2* A = Aw + int64_t(J.k) * mb * mb;
+  double2* colsum = sh + 4 * mb;
   double* d = dd + int64_t(J.k) * mb;
   double* e = ee + int64_t(J.k) * mb;
   double2* tk = tau + int64_t(J.k) * mb;
-  __shared__ double red[16];
-  __shared__ double2 s_tau, s_scale;
-  __shared__ double s_beta;
+  __shared__ double red[32];
+  __shared__ double2 s_tau, s_scale, s_alpha;
+  __shared__ double s_beta, s_dj;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-  for (int i = tid; i < 4 * mb; i += blockDim.x) sh[i] = make_double2(0.0, 0.0);
+  for (int i = tid; i < 5 * mb; i += blockDim.x) sh[i] = make_double2(0.0, 0.0);
   __syncthreads();
   for (int j = 0; j < m - 1; ++j) {
     double2* vc = sh + (j & 1 ? mb : 0);          // this step's reflector
     double2* pc = sh + 2 * mb + (j & 1 ? mb : 0);  // this step's p, then w
     const double2* vq = sh + (j & 1 ? 0 : mb);     // pending reflector (step j-1)
     const double2* wq = sh + 2 * mb + (j & 1 ? 0 : mb);  // pending w
-    // column j, rows >= j, brought up to date
+    // column j, rows >= j, brought up to date and kept in registers (m <= 2 blockDim)
     const double2 vqj = vq[j], wqj = wq[j];
-    for (int r = j + tid; r < m; r += blockDim.x) {
-      double2 a = A[int64_t(r) * mb + j];
-      a = csub2(a, cmul2(vq[r], cconj(wqj)));
-      a = csub2(a, cmul2(wq[r], cconj(vqj)));
-      A[int64_t(r) * mb + j] = a;
-    }
-    __syncthreads();
+    double2 colv[2];
     double xs = 0.0;
-    for (int r = j + 2 + tid; r < m; r += blockDim.x) {
-      const double2 a = A[int64_t(r) * mb + j];
-      xs += a.x * a.x + a.y * a.y;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int r = j + tid + q * int(blockDim.x);
+      colv[q] = make_double2(0.0, 0.0);
+      if (r < m) {
+        double2 a = A[int64_t(r) * mb + j];
+        a = csub2(a, cmul2(vq[r], cconj(wqj)));
+        a = csub2(a, cmul2(wq[r], cconj(vqj)));
+        colv[q] = a;
+        if (r == j) s_dj = a.x;
+        else if (r == j + 1) s_alpha = a;
+        else xs += a.x * a.x + a.y * a.y;
+      }
     }
-    xs = block_sum(xs, red);
+    xs = block_sum(xs, red);   // its barriers also publish s_dj and s_alpha
     if (tid == 0) {
-      const double2 alpha = A[int64_t(j + 1) * mb + j];
+      const double2 alpha = s_alpha;
       if (xs == 0.0 && alpha.y == 0.0) {
         s_tau = make_double2(0.0, 0.0);
         s_beta = alpha.x;
@@ -131,26 +163,36 @@ __global__ void __launch_bounds__(1024) k_tridiag(DJobs jobs, double2* __restric
         s_scale = make_double2(den.x / dn, -den.y / dn);
         s_beta = beta;
       }
-      d[j] = A[int64_t(j) * mb + j].x;
+      d[j] = s_dj;
       e[j] = s_beta;
       tk[j] = s_tau;
     }
     __syncthreads();
     const double2 t = s_tau;
     const bool refl = !(t.x == 0.0 && t.y == 0.0);
-    for (int r = j + 1 + tid; r < m; r += blockDim.x) {
-      double2 x = make_double2(0.0, 0.0);
-      if (refl) {
-        x = r == j + 1 ? make_double2(1.0, 0.0) : cmul2(A[int64_t(r) * mb + j], s_scale);
-        if (r > j + 1) A[int64_t(r) * mb + j] = x;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int r = j + tid + q * int(blockDim.x);
+      if (r > j && r < m) {
+        double2 x = make_double2(0.0, 0.0);
+        if (refl) {
+          x = r == j + 1 ? make_double2(1.0, 0.0) : cmul2(colv[q], s_scale);
+          if (r > j + 1) A[int64_t(r) * mb + j] = x;
+        }
+        vc[r] = x;
+        colsum[r] = make_double2(0.0, 0.0);
       }
-      vc[r] = x;
     }
     if (tid == 0) vc[j] = make_double2(0.0, 0.0);
     __syncthreads();
-    // fused pass over rows/cols [j+1, m): pending update, then p = tau A v.  A wave takes
-    // four rows at a time so the reflector values it reads from LDS serve four rows.
-    for (int r0 = j + 1 + 4 * wave; r0 < m; r0 += 4 * nw) {
+    // fused pass over the lower triangle of [j+1, m): pending update, then A v.  A wave
+    // takes four rows at a time so the reflector values it reads from LDS serve four rows.
+    // Row groups go to waves in snake order (the lower triangle's rows grow in length).
+    const int ngroups = (m - j - 1 + 3) / 4;
+    for (int rd = 0; rd * nw < ngroups; ++rd) {
+      const int g = rd * nw + ((rd & 1) ? nw - 1 - wave : wave);
+      if (g >= ngroups) continue;
+      const int r0 = j + 1 + 4 * g;
       double sr[4] = {0, 0, 0, 0}, si[4] = {0, 0, 0, 0};
       double2 vr[4], wr[4];
 #pragma unroll
@@ -159,18 +201,30 @@ __global__ void __launch_bounds__(1024) k_tridiag(DJobs jobs, double2* __restric
         vr[q] = vq[r];
         wr[q] = wq[r];
       }
-      for (int c = j + 1 + lane; c < m; c += 64) {
+      const int rmax = min(r0 + 3, m - 1);
+      for (int c = j + 1 + lane; c <= rmax; c += 64) {
         const double2 vqc = cconj(vq[c]), wqc = cconj(wq[c]), b = vc[c];
+        double tr = 0.0, ti = 0.0;   // sum over this wave's rows r > c of conj(a_rc) v_r
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          if (r0 + q >= m) break;
-          double2* ap = A + int64_t(r0 + q) * mb + c;
+          const int r = r0 + q;
+          if (r > rmax || c > r) continue;
+          double2* ap = A + int64_t(r) * mb + c;
           double2 a = *ap;
           a = csub2(a, cmul2(vr[q], wqc));
           a = csub2(a, cmul2(wr[q], vqc));
           *ap = a;
           sr[q] += a.x * b.x - a.y * b.y;
           si[q] += a.x * b.y + a.y * b.x;
+          if (c < r) {
+            const double2 br = vc[r];   // same address on every lane: an LDS broadcast
+            tr += a.x * br.x + a.y * br.y;
+            ti += a.x * br.y - a.y * br.x;
+          }
+        }
+        if (c < rmax) {
+          atomicAdd(&colsum[c].x, tr);
+          atomicAdd(&colsum[c].y, ti);
         }
       }
 #pragma unroll
@@ -179,19 +233,19 @@ __global__ void __launch_bounds__(1024) k_tridiag(DJobs jobs, double2* __restric
           sr[q] += __shfl_down(sr[q], o, 64);
           si[q] += __shfl_down(si[q], o, 64);
         }
-        if (lane == 0 && r0 + q < m) pc[r0 + q] = cmul2(t, make_double2(sr[q], si[q]));
+        if (lane == 0 && r0 + q < m) pc[r0 + q] = make_double2(sr[q], si[q]);
       }
     }
     if (tid == 0) pc[j] = make_double2(0.0, 0.0);
     __syncthreads();
-    double pr = 0.0, pi = 0.0;   // p^H v
+    double pr = 0.0, pi = 0.0;   // p = tau (row part + column part); p^H v
     for (int c = j + 1 + tid; c < m; c += blockDim.x) {
-      const double2 pv = pc[c], vv = vc[c];
+      const double2 pv = cmul2(t, cadd2(pc[c], colsum[c])), vv = vc[c];
+      pc[c] = pv;
       pr += pv.x * vv.x + pv.y * vv.y;
       pi += pv.x * vv.y - pv.y * vv.x;
     }
-    pr = block_sum(pr, red);
-    pi = block_sum(pi, red);
+    block_sum2(pr, pi, red);
     const double2 aw = cmul2(make_double2(-0.5 * t.x, -0.5 * t.y), make_double2(pr, pi));
     for (int c = j + 1 + tid; c < m; c += blockDim.x) pc[c] = cadd2(pc[c], cmul2(aw, vc[c]));
     __syncthreads();

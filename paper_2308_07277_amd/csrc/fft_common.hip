@@ -46,6 +46,18 @@ void launch_hpsi_local(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const voi
     launch_local_f64(p, sl, psi, hpsi, s, ev);
 }
 
+int xy_group_lanes(int nx) { return nx == 20 || nx == 40 ? 2 : (nx == 72 ? 8 : 0); }
+
+int xy_pick(const qm_hpsi_plan* p, int rt) {
+  const bool group_ok = xy_group_lanes(p->N1) > 0;
+  if (p->xy_forced == 1) return 1;
+  if (p->xy_forced == 2) return group_ok ? 2 : 1;
+  if (p->xy_variant[rt] == 2 && group_ok) return 2;
+  if (p->xy_variant[rt] == 1) return 1;
+  // built-in choice, as measured on the workloads: lane pairs for float64 20 and 40
+  return rt == 0 && (p->N1 == 20 || p->N1 == 40) ? 2 : 1;
+}
+
 std::vector<KSlice> contiguous_slices(const qm_hpsi_plan* p, int k0, int k1, int nbnd) {
   std::vector<KSlice> out;
   const int64_t g0 = p->kinfo[k0].g_off;

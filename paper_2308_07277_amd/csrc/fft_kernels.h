@@ -279,7 +279,10 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
 // Forward = decimation in frequency: lane q holds x[H q + n]; the L-point DFT across the group
 // comes first, then the twiddle w_NX^{-t n} and an H-point DFT leave X[L k + t].  The inverse's
 // output distribution is exactly the forward's input distribution, so the x-row transform pair
-// with V(r) in between never leaves registers.  Used for float64 lines up to 72.
+// with V(r) in between never leaves registers.  For L = 8 the cross-lane DFT is three radix-2
+// stages of xor shuffles: decimation in frequency for the inverse (natural order in, lane l
+// ends with block rev3(l)) and decimation in time for the forward (block rev3(l) in, natural
+// order out), so the bit-reversed block order only shows where the data is addressed.
 template <typename R>
 __device__ __forceinline__ cplx<R> shflx(cplx<R> v, int m) {
   return {__shfl_xor(v.re, m, 64), __shfl_xor(v.im, m, 64)};
@@ -309,6 +312,46 @@ __device__ __forceinline__ cplx<R> cross_dft(cplx<R> z, int t) {
   }
 }
 
+// v * w_8^{S j} for j in 0..3, branch free
+template <int S, typename R>
+__device__ __forceinline__ cplx<R> mul_w8(cplx<R> v, int j) {
+  const R r = R(0.707106781186547524400844362104849039);
+  const R c = R(j == 0) + r * R((j == 1) - (j == 3));
+  const R sn = R(S) * (R(j == 2) + r * R((j == 1) + (j == 3)));
+  return {c * v.re - sn * v.im, c * v.im + sn * v.re};
+}
+// twiddle w_{2h}^{S j} of a radix-2 stage across lanes (h = 1, 2, 4)
+template <int S, typename R>
+__device__ __forceinline__ cplx<R> stage_tw(cplx<R> v, int h, int j) {
+  return h == 4 ? mul_w8<S>(v, j) : (h == 2 ? mul_ipow<S>(v, j) : v);
+}
+// 8-lane DFT, decimation in frequency: natural input, lane l ends with output rev3(l)
+template <int S, typename R>
+__device__ __forceinline__ cplx<R> cross_dif8(cplx<R> z, int t) {
+#pragma unroll
+  for (int h = 4; h >= 1; h >>= 1) {
+    const cplx<R> p = shflx(z, h);
+    z = (t & h) ? stage_tw<S>(csub(p, z), h, t & (h - 1)) : cadd(z, p);
+  }
+  return z;
+}
+// 8-lane DFT, decimation in time: lane l holds input rev3(l), natural output
+template <int S, typename R>
+__device__ __forceinline__ cplx<R> cross_dit8(cplx<R> z, int t) {
+#pragma unroll
+  for (int h = 1; h <= 4; h <<= 1) {
+    const cplx<R> zt = (t & h) ? stage_tw<S>(z, h, t & (h - 1)) : z;
+    const cplx<R> p = shflx(zt, h);
+    z = (t & h) ? csub(p, zt) : cadd(z, p);
+  }
+  return z;
+}
+// output block held by lane t after group_inverse (and expected by group_forward)
+template <int L>
+__device__ __forceinline__ int lane_block(int t) {
+  return L == 8 ? (((t & 1) << 2) | (t & 2) | ((t >> 2) & 1)) : t;
+}
+
 template <typename R, int NX, int L>
 __device__ __forceinline__ void group_inverse(cplx<R>* y, int t, const cplx<R>* tw) {
   constexpr int H = NX / L;
@@ -316,7 +359,7 @@ __device__ __forceinline__ void group_inverse(cplx<R>* y, int t, const cplx<R>* 
 #pragma unroll
   for (int k = 1; k < H; ++k) y[k] = cmul(y[k], tw[(t * k) % NX]);
 #pragma unroll
-  for (int k = 0; k < H; ++k) y[k] = cross_dft<+1, L>(y[k], t);
+  for (int k = 0; k < H; ++k) y[k] = L == 8 ? cross_dif8<+1>(y[k], t) : cross_dft<+1, L>(y[k], t);
 }
 
 template <typename R, int NX, int L>
@@ -324,7 +367,7 @@ __device__ __forceinline__ void group_forward(cplx<R>* y, int t, const cplx<R>* 
   constexpr int H = NX / L;
 #pragma unroll
   for (int n = 0; n < H; ++n) {
-    const cplx<R> a = cross_dft<-1, L>(y[n], t);
+    const cplx<R> a = L == 8 ? cross_dit8<-1>(y[n], t) : cross_dft<-1, L>(y[n], t);
     const cplx<R> w = tw[(t * n) % NX];
     y[n] = n ? cmul(a, cplx<R>{w.re, -w.im}) : a;
   }
@@ -339,7 +382,7 @@ __global__ void __launch_bounds__(L * NX) k_xy_group(LocalArgs a) {
   cplx<R>* Lp = reinterpret_cast<cplx<R>*>(smem_raw);  // [NX rows i2][ns]
   cplx<R>* tw = Lp + NX * ns;                           // [NX]
   int* col = reinterpret_cast<int*>(tw + NX);           // [NX]
-  const int tid = threadIdx.x, t = tid % L, line = tid / L;
+  const int tid = threadIdx.x, t = tid % L, line = tid / L, tb = lane_block<L>(t);
   const int N3 = a.N3;
   int bid = blockIdx.x, kb, p;
   if ((N3 & 7) == 0) {
@@ -381,7 +424,7 @@ __global__ void __launch_bounds__(L * NX) k_xy_group(LocalArgs a) {
     group_inverse<R, NX, L>(y, t, tw);
     if (live) {
 #pragma unroll
-      for (int k2 = 0; k2 < H; ++k2) Lp[(H * t + k2) * ns + line] = y[k2];
+      for (int k2 = 0; k2 < H; ++k2) Lp[(H * tb + k2) * ns + line] = y[k2];
     }
   }
   __syncthreads();
@@ -395,7 +438,7 @@ __global__ void __launch_bounds__(L * NX) k_xy_group(LocalArgs a) {
       y[n] = c >= 0 ? row[c] : cplx<R>{R(0), R(0)};
     }
     group_inverse<R, NX, L>(y, t, tw);
-    const R* Vrow = reinterpret_cast<const R*>(a.vplan) + (int64_t(p) * NX + i2) * NX + H * t;
+    const R* Vrow = reinterpret_cast<const R*>(a.vplan) + (int64_t(p) * NX + i2) * NX + H * tb;
 #pragma unroll
     for (int n = 0; n < H; ++n) y[n] = cscale(y[n], Vrow[n]);
     group_forward<R, NX, L>(y, t, tw);
@@ -410,7 +453,7 @@ __global__ void __launch_bounds__(L * NX) k_xy_group(LocalArgs a) {
   if (line < nax_w) {
     const bool live = line < nax;
 #pragma unroll
-    for (int n = 0; n < H; ++n) y[n] = live ? Lp[(H * t + n) * ns + line] : cplx<R>{R(0), R(0)};
+    for (int n = 0; n < H; ++n) y[n] = live ? Lp[(H * tb + n) * ns + line] : cplx<R>{R(0), R(0)};
     group_forward<R, NX, L>(y, t, tw);
     if (live) {
 #pragma unroll

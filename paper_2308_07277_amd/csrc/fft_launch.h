@@ -72,7 +72,7 @@ void launch_local_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* 
   }
   QM_HIP(hipGetLastError());
   if (ev) ev->mark(0);
-  if (sizeof(R) == 8 && (NX == 20 || NX == 40) && p->xy_mode != 1) {
+  if (xy_pick(p, sizeof(R) == 8 ? 0 : 1) == 2) {
     const size_t smem_p = sizeof(cplx<R>) * (size_t(NX) * a.nax_stride + NX) + sizeof(int) * NX;
 #define QM_XYP(n, l)                                                                        \
   case n: {                                                                                 \
@@ -84,7 +84,7 @@ void launch_local_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* 
     hipLaunchKernelGGL((k_xy_group<R, n, l>), dim3(unsigned(nblk_xy)), dim3(l * n), smem_p, s, a); \
   } break;
     switch (NX) {
-      QM_XYP(20, 2) QM_XYP(40, 2)
+      QM_XYP(20, 2) QM_XYP(40, 2) QM_XYP(72, 8)
       default: throw Error(QM_E_SHAPE, "unsupported N1");
     }
 #undef QM_XYP

@@ -173,6 +173,62 @@ void autotune_projection(qm_hpsi_plan* p, int nbnd, hipStream_t s, int lp, doubl
   save_cache(path, cache);
 }
 
+// time the local part (scatter, FFTs, V, gather) of min(nk, 32) k-points at nbnd bands with
+// each xy-plane kernel, per real type; keep the faster one
+static void autotune_xy(qm_hpsi_plan* p, int nbnd, hipStream_t s) {
+  if (p->xy_forced != 0 || xy_group_lanes(p->N1) == 0) return;
+  const char* path = std::getenv("QM_AUTOTUNE_CACHE");
+  std::map<std::string, int> cache = load_cache(path);
+  const int k1 = std::min(p->nk, kMaxSlices);
+  const std::vector<KSlice> sl = contiguous_slices(p, 0, k1, nbnd);
+  const int64_t npw = p->kinfo[k1 - 1].g_off + p->kinfo[k1 - 1].npw - p->kinfo[0].g_off;
+  void* psi = nullptr;
+  void* out = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bool dirty = false;
+  for (int rt = 0; rt < 2; ++rt) {
+    std::ostringstream key;
+    key << "xy/" << rt << "/" << p->N1 << "x" << p->N2 << "x" << p->N3 << "/" << nbnd << "/" << k1
+        << "/" << npw;
+    auto it = cache.find(key.str());
+    if (it != cache.end()) {
+      p->xy_variant[rt] = it->second;
+      continue;
+    }
+    if (!psi) {
+      QM_HIP(hipMalloc(&psi, size_t(nbnd) * size_t(npw) * 16));
+      QM_HIP(hipMalloc(&out, size_t(nbnd) * size_t(npw) * 16));
+      QM_HIP(hipMemsetAsync(psi, 0, size_t(nbnd) * size_t(npw) * 16, s));
+      QM_HIP(hipEventCreate(&e0));
+      QM_HIP(hipEventCreate(&e1));
+    }
+    int best = 1;
+    double bms = 1e30;
+    for (int v = 1; v <= 2; ++v) {
+      p->xy_variant[rt] = v;
+      launch_hpsi_local(p, sl, psi, out, s, rt == 1, nullptr);  // warm
+      QM_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < 3; ++r) launch_hpsi_local(p, sl, psi, out, s, rt == 1, nullptr);
+      QM_HIP(hipEventRecord(e1, s));
+      QM_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      QM_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < bms) {
+        bms = ms;
+        best = v;
+      }
+    }
+    p->xy_variant[rt] = best;
+    cache[key.str()] = best;
+    dirty = true;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (psi) (void)hipFree(psi);
+  if (out) (void)hipFree(out);
+  if (dirty) save_cache(path, cache);
+}
+
 }  // namespace qm
 
 extern "C" qm_status qm_hpsi_plan_autotune(qm_hpsi_plan* plan, int32_t nbnd, void* stream) {
@@ -183,6 +239,7 @@ extern "C" qm_status qm_hpsi_plan_autotune(qm_hpsi_plan* plan, int32_t nbnd, voi
     plan->graphs.clear();
     for (int lp = 0; lp < 3; ++lp)
       qm::autotune_projection(plan, nbnd, reinterpret_cast<hipStream_t>(stream), lp, nullptr);
+    qm::autotune_xy(plan, nbnd, reinterpret_cast<hipStream_t>(stream));
     return QM_OK;
   } catch (const qm::Error& e) {
     plan->err = e.what();

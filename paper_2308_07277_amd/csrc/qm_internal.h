@@ -129,7 +129,11 @@ struct qm_hpsi_plan {
   uint64_t graph_clock = 0;
   hipStream_t capture_stream = nullptr;
   int32_t use_graphs = 1;
-  int32_t xy_mode = 0;   // 0: lane-group xy kernel where it applies (float64, 20 and 40), 1: two-pass
+  // xy-plane kernel per real type of the local part (0 float64, 1 float32): 1 the two-pass
+  // kernel, 2 the lane-group kernel (grids 20, 40, 72), 0 the built-in choice; set by the
+  // autotuner.  xy_forced (environment QM_XY_MODE = 1 or 2) overrides both.
+  int32_t xy_variant[2] = {0, 0};
+  int32_t xy_forced = 0;
 };
 
 namespace qm {
@@ -143,6 +147,8 @@ void launch_nonlocal(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void*
 void apply_h_slices(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
                     hipStream_t s, qm_prec prec, StageEvents* ev = nullptr);
 std::vector<KSlice> contiguous_slices(const qm_hpsi_plan* p, int k0, int k1, int nbnd);
+int xy_group_lanes(int nx);                       // lanes per line of the lane-group kernel, 0: none
+int xy_pick(const qm_hpsi_plan* p, int real_type);  // 1 two-pass, 2 lane-group
 void convert_beta(qm_hpsi_plan* p, qm_prec prec, hipStream_t s);
 bool fft_len_supported(int n);
 int fft_split_r1(int n);

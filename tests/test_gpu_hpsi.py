@@ -184,8 +184,8 @@ def test_graph_replays_match_eager():
 
 
 def test_autotune_keeps_results(tmp_path, monkeypatch):
-    """Autotuning changes only the split-K schedule: results stay within float64 rounding
-    and a second plan reads the choice back from the cache file."""
+    """Autotuning changes only the split-K schedule and the xy-plane kernel: results stay
+    within float64 rounding and a second plan reads the choices back from the cache file."""
     import json
     import torch
     import paper_2308_07277_amd as qm
@@ -199,6 +199,29 @@ def test_autotune_keeps_results(tmp_path, monkeypatch):
     assert np.abs(after - before).max() <= 1e-13 * np.abs(before).max()
     cache = json.load(open(tmp_path / "tune.json"))
     assert any(k.startswith("cn/0/") for k in cache)
+    assert any(k.startswith("xy/0/") for k in cache) and any(k.startswith("xy/1/") for k in cache)
     plan2, _ = make_plan(w, w.nbnd, arrays=a)
     qm.qm_hpsi_plan_autotune(plan2, w.nbnd)          # served from the cache file
     assert np.abs(_run(plan2, w, w.nbnd, psi_flat=flat) - after).max() == 0.0
+
+
+@pytest.mark.parametrize("name,prec,tol", [("c2", 0, 1e-13), ("c2", 1, 3e-6), ("c3", 0, 1e-13), ("c3", 1, 3e-6)])
+def test_xy_kernel_variants_agree(name, prec, tol, monkeypatch):
+    """The two-pass and the lane-group xy-plane kernels (lane pairs on the 40-point grid,
+    8-lane groups with radix-2 cross-lane stages on the 72-point grid) compute the same
+    transform: per-band relative difference within float64 (1e-13) or float32 (3e-6)
+    rounding.  The 64-atom grid is taken with two of its k-points."""
+    w = workload.make_workload(name, nk_limit=2)
+    flat, per = psi_block(w, w.nbnd)
+    outs = []
+    a = None
+    for mode in ("1", "2"):
+        monkeypatch.setenv("QM_XY_MODE", mode)
+        plan, a = make_plan(w, w.nbnd, prec=prec, arrays=a)
+        outs.append(_run(plan, w, w.nbnd, psi_flat=flat))
+        plan.close()
+    monkeypatch.delenv("QM_XY_MODE")
+    err = band_rel_err(np.asarray(split_k(outs[1], w, w.nbnd)[0]), np.asarray(split_k(outs[0], w, w.nbnd)[0]))
+    err2 = band_rel_err(np.asarray(split_k(outs[1], w, w.nbnd)[1]), np.asarray(split_k(outs[0], w, w.nbnd)[1]))
+    print(name, prec, "max band rel diff", max(err.max(), err2.max()))
+    assert max(err.max(), err2.max()) <= tol
