@@ -111,15 +111,25 @@ __global__ void __launch_bounds__(256) k_cgemm_cn(const CNBatch batch, int nspli
   const bool arow = (i0 + lrow) < P.M, brow = (j0 + lrow) < P.N;
   const SA* Ar = A + int64_t(i0 + lrow) * P.lda;
   const SB* Br = B + int64_t(j0 + lrow) * P.ldb;
-  for (int c = c0; c < c1; ++c) {
-    const int kb = c * KC + lseg;
+  // the next chunk's operands are loaded into registers while this chunk's MFMAs run
+  cplx<T> pa[4], pb[4];
+  auto fetch = [&](int c) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int g = kb + q;
-      As[lrow][lseg + q] = (arow && g < P.K) ? ld<T>(Ar + g) : cplx<T>{T(0), T(0)};
-      Bs[lrow][lseg + q] = (brow && g < P.K) ? ld<T>(Br + g) : cplx<T>{T(0), T(0)};
+      const int g = c * KC + lseg + q;
+      pa[q] = (arow && g < P.K) ? ld<T>(Ar + g) : cplx<T>{T(0), T(0)};
+      pb[q] = (brow && g < P.K) ? ld<T>(Br + g) : cplx<T>{T(0), T(0)};
+    }
+  };
+  if (c0 < c1) fetch(c0);
+  for (int c = c0; c < c1; ++c) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      As[lrow][lseg + q] = pa[q];
+      Bs[lrow][lseg + q] = pb[q];
     }
     __syncthreads();
+    if (c + 1 < c1) fetch(c + 1);
 #pragma unroll
     for (int kk = 0; kk < KC / 4; ++kk) {
       const int kq = kk * 4 + (lane >> 4);
@@ -205,16 +215,27 @@ __global__ void __launch_bounds__(256) k_cgemm_ex(const EXBatch batch, double al
       ci[a][b] = AV{0, 0, 0, 0};
     }
   const int nch = (P.K + KC - 1) / KC;
-  for (int c = 0; c < nch; ++c) {
+  // the next chunk's operands are loaded into registers while this chunk's MFMAs run
+  cplx<T> pw[4], pa[4];
+  auto fetch = [&](int c) {
     const int i = c * KC + lr;
     const bool irow = i < P.K;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int m = m0 + lc + q, n = n0 + lc + q;
-      Ws[lr][lc + q] = (irow && m < P.M) ? ld<T>(Wp + int64_t(i) * P.ldw + m) : cplx<T>{T(0), T(0)};
-      As[lr][lc + q] = (irow && n < P.N) ? ld<T>(Ap + int64_t(i) * P.lda + n) : cplx<T>{T(0), T(0)};
+      pw[q] = (irow && m < P.M) ? ld<T>(Wp + int64_t(i) * P.ldw + m) : cplx<T>{T(0), T(0)};
+      pa[q] = (irow && n < P.N) ? ld<T>(Ap + int64_t(i) * P.lda + n) : cplx<T>{T(0), T(0)};
+    }
+  };
+  if (nch > 0) fetch(0);
+  for (int c = 0; c < nch; ++c) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      Ws[lr][lc + q] = pw[q];
+      As[lr][lc + q] = pa[q];
     }
     __syncthreads();
+    if (c + 1 < nch) fetch(c + 1);
 #pragma unroll
     for (int kk = 0; kk < KC / 4; ++kk) {
       const int kq = kk * 4 + (lane >> 4);
