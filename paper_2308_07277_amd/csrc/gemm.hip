@@ -72,6 +72,15 @@ struct CNOut;
 constexpr int BT = 64;   // tile edge
 constexpr int KC = 16;   // K chunk (complex elements)
 
+// Workgroups are handed to the 8 XCDs round-robin (block b to XCD b % 8), and each XCD has
+// its own L2.  This maps the hardware block index to a logical tile index so that every
+// XCD works through one contiguous range of logical tiles; tiles that share an operand
+// slab are numbered consecutively and so run on the same XCD at about the same time.
+__device__ __forceinline__ int xcd_logical_block(int bid, int nblk) {
+  const int full = nblk >> 3, rem = nblk & 7, x = bid & 7;
+  return x * full + min(x, rem) + (bid >> 3);
+}
+
 template <typename B>
 __device__ __forceinline__ int find_prob(const B& b, int bid) {
   int pi = 0;
@@ -86,12 +95,13 @@ __global__ void __launch_bounds__(256) k_cgemm_cn(const CNBatch batch, int nspli
   typedef typename Acc<T>::type AV;
   __shared__ cplx<T> As[BT][KC + 1];
   __shared__ cplx<T> Bs[BT][KC + 1];
-  const int pi = find_prob(batch, blockIdx.x);
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int pi = find_prob(batch, lb);
   const CNDev& P = batch.p[pi];
-  int bid = blockIdx.x - P.blk0;
-  const int split = bid % nsplit;
-  const int tile = bid / nsplit;
-  const int i0 = (tile % P.tm) * BT, j0 = (tile / P.tm) * BT;
+  // row tiles fastest: the row tiles of one (column tile, K split) share the B slab
+  const int bid = lb - P.blk0, rest = bid / P.tm;
+  const int split = rest % nsplit;
+  const int i0 = (bid % P.tm) * BT, j0 = (rest / nsplit) * BT;
   const int nch = (P.K + KC - 1) / KC;
   const int per = (nch + nsplit - 1) / nsplit;
   const int c0 = split * per, c1 = min(nch, c0 + per);
@@ -109,16 +119,27 @@ __global__ void __launch_bounds__(256) k_cgemm_cn(const CNBatch batch, int nspli
       ci[a][b] = AV{0, 0, 0, 0};
     }
   const bool arow = (i0 + lrow) < P.M, brow = (j0 + lrow) < P.N;
-  const SA* Ar = A + int64_t(i0 + lrow) * P.lda;
-  const SB* Br = B + int64_t(j0 + lrow) * P.ldb;
+  // rows past the matrix read row i0 / j0 (which exists) and are zeroed after the load
+  const SA* Ar = A + int64_t(arow ? i0 + lrow : i0) * P.lda;
+  const SB* Br = B + int64_t(brow ? j0 + lrow : j0) * P.ldb;
   // the next chunk's operands are loaded into registers while this chunk's MFMAs run
   cplx<T> pa[4], pb[4];
   auto fetch = [&](int c) {
+    const int kb = c * KC + lseg;
+    if (kb + 4 <= P.K) {   // whole run inside K: one bounds test per row
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int g = c * KC + lseg + q;
-      pa[q] = (arow && g < P.K) ? ld<T>(Ar + g) : cplx<T>{T(0), T(0)};
-      pb[q] = (brow && g < P.K) ? ld<T>(Br + g) : cplx<T>{T(0), T(0)};
+      for (int q = 0; q < 4; ++q) {
+        const cplx<T> av = ld<T>(Ar + kb + q), bv = ld<T>(Br + kb + q);
+        pa[q] = arow ? av : cplx<T>{T(0), T(0)};
+        pb[q] = brow ? bv : cplx<T>{T(0), T(0)};
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int g = kb + q;
+        pa[q] = (arow && g < P.K) ? ld<T>(Ar + g) : cplx<T>{T(0), T(0)};
+        pb[q] = (brow && g < P.K) ? ld<T>(Br + g) : cplx<T>{T(0), T(0)};
+      }
     }
   };
   if (c0 < c1) fetch(c0);
@@ -197,9 +218,11 @@ __global__ void __launch_bounds__(256) k_cgemm_ex(const EXBatch batch, double al
   typedef typename Acc<T>::type AV;
   __shared__ cplx<T> Ws[KC][BT + 1];
   __shared__ cplx<T> As[KC][BT + 1];
-  const int pi = find_prob(batch, blockIdx.x);
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int pi = find_prob(batch, lb);
   const EXDev& P = batch.p[pi];
-  const int tile = blockIdx.x - P.blk0;
+  // row tiles fastest: the row tiles of one column tile share the A slab
+  const int tile = lb - P.blk0;
   const int m0 = (tile % P.tm) * BT, n0 = (tile / P.tm) * BT;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = (wave & 1) * 32, wj = (wave >> 1) * 32;
@@ -220,11 +243,19 @@ __global__ void __launch_bounds__(256) k_cgemm_ex(const EXBatch batch, double al
   auto fetch = [&](int c) {
     const int i = c * KC + lr;
     const bool irow = i < P.K;
+    if (irow && m0 + lc + 4 <= P.M && n0 + lc + 4 <= P.N) {   // interior: no element tests
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int m = m0 + lc + q, n = n0 + lc + q;
-      pw[q] = (irow && m < P.M) ? ld<T>(Wp + int64_t(i) * P.ldw + m) : cplx<T>{T(0), T(0)};
-      pa[q] = (irow && n < P.N) ? ld<T>(Ap + int64_t(i) * P.lda + n) : cplx<T>{T(0), T(0)};
+      for (int q = 0; q < 4; ++q) {
+        pw[q] = ld<T>(Wp + int64_t(i) * P.ldw + m0 + lc + q);
+        pa[q] = ld<T>(Ap + int64_t(i) * P.lda + n0 + lc + q);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + lc + q, n = n0 + lc + q;
+        pw[q] = (irow && m < P.M) ? ld<T>(Wp + int64_t(i) * P.ldw + m) : cplx<T>{T(0), T(0)};
+        pa[q] = (irow && n < P.N) ? ld<T>(Ap + int64_t(i) * P.lda + n) : cplx<T>{T(0), T(0)};
+      }
     }
   };
   if (nch > 0) fetch(0);
@@ -307,6 +338,28 @@ __device__ __forceinline__ f4v mfma32(bf8v a, bf8v b, f4v c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+// two floats -> two bfloat16 (round to nearest even) packed low, high
+__device__ __forceinline__ uint32_t pk_bf16(float lo, float hi) {
+  bf2v b = __builtin_convertvector((f2v){lo, hi}, bf2v);
+  return *reinterpret_cast<uint32_t*>(&b);
+}
+// eight stored bf16 complex (re | im << 16) -> the re plane and the im plane, 16 bytes each
+__device__ __forceinline__ void split_bf2(const uint32_t* v, uint4& re, uint4& im) {
+  re = make_uint4((v[0] & 0xffffu) | (v[1] << 16), (v[2] & 0xffffu) | (v[3] << 16),
+                  (v[4] & 0xffffu) | (v[5] << 16), (v[6] & 0xffffu) | (v[7] << 16));
+  im = make_uint4((v[0] >> 16) | (v[1] & 0xffff0000u), (v[2] >> 16) | (v[3] & 0xffff0000u),
+                  (v[4] >> 16) | (v[5] & 0xffff0000u), (v[6] >> 16) | (v[7] & 0xffff0000u));
+}
+// eight c128 -> bfloat16 re plane and im plane
+__device__ __forceinline__ void pack_c128(const double2* v, uint4& re, uint4& im) {
+  re = make_uint4(pk_bf16(float(v[0].x), float(v[1].x)), pk_bf16(float(v[2].x), float(v[3].x)),
+                  pk_bf16(float(v[4].x), float(v[5].x)), pk_bf16(float(v[6].x), float(v[7].x)));
+  im = make_uint4(pk_bf16(float(v[0].y), float(v[1].y)), pk_bf16(float(v[2].y), float(v[3].y)),
+                  pk_bf16(float(v[4].y), float(v[5].y)), pk_bf16(float(v[6].y), float(v[7].y)));
+}
+
 constexpr int KB = 32;       // K chunk of the bf16 kernels (complex elements)
 constexpr int KBP = KB + 8;  // padded LDS row (bf16 elements), keeps 16-byte alignment
 
@@ -314,12 +367,13 @@ constexpr int KBP = KB + 8;  // padded LDS row (bf16 elements), keeps 16-byte al
 __global__ void __launch_bounds__(256) k_cgemm_cn_bf16(const CNBatch batch, int nsplit,
                                                        cplx<float>* __restrict__ work) {
   __shared__ __align__(16) u16 Ar[BT][KBP], Ai[BT][KBP], Br[BT][KBP], Bi[BT][KBP];
-  const int pi = find_prob(batch, blockIdx.x);
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int pi = find_prob(batch, lb);
   const CNDev& P = batch.p[pi];
-  int bid = blockIdx.x - P.blk0;
-  const int split = bid % nsplit;
-  const int tile = bid / nsplit;
-  const int i0 = (tile % P.tm) * BT, j0 = (tile / P.tm) * BT;
+  // row tiles fastest: the row tiles of one (column tile, K split) share the B slab
+  const int bid = lb - P.blk0, rest = bid / P.tm;
+  const int split = rest % nsplit;
+  const int i0 = (bid % P.tm) * BT, j0 = (rest / nsplit) * BT;
   const int nch = (P.K + KB - 1) / KB;
   const int per = (nch + nsplit - 1) / nsplit;
   const int c0 = split * per, c1 = min(nch, c0 + per);
@@ -337,23 +391,43 @@ __global__ void __launch_bounds__(256) k_cgemm_cn_bf16(const CNBatch batch, int 
       ci[a][b] = f4v{0, 0, 0, 0};
     }
   const bool arow = (i0 + lrow) < P.M, brow = (j0 + lrow) < P.N;
-  const bf2* Arow = A + int64_t(i0 + lrow) * P.lda;
-  const double2* Brow = B + int64_t(j0 + lrow) * P.ldb;
-  for (int c = c0; c < c1; ++c) {
+  // rows past the matrix read row i0 / j0 (which exists) and are zeroed after the load
+  const bf2* Arow = A + int64_t(arow ? i0 + lrow : i0) * P.lda;
+  const double2* Brow = B + int64_t(brow ? j0 + lrow : j0) * P.ldb;
+  // raw operands of the next two chunks are in flight while this chunk's MFMAs run
+  // (two register sets, used alternately); converted and stored to LDS as 16-byte re and
+  // im runs of eight K values
+  uint32_t pa0[8], pa1[8];
+  double2 pb0[8], pb1[8];
+  auto fetch = [&](uint32_t* pa, double2* pb, int c) {
     const int kb = c * KB + lseg;
+    if (kb + 8 <= P.K) {   // whole run inside K: one bounds test per row
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int g = kb + q;
-      bf2 av = {0, 0};
-      if (arow && g < P.K) av = Arow[g];
-      Ar[lrow][lseg + q] = av.re;
-      Ai[lrow][lseg + q] = av.im;
-      double2 bv = make_double2(0.0, 0.0);
-      if (brow && g < P.K) bv = Brow[g];
-      Br[lrow][lseg + q] = f2bf(float(bv.x));
-      Bi[lrow][lseg + q] = f2bf(float(bv.y));
+      for (int q = 0; q < 8; ++q) {
+        const uint32_t av = *reinterpret_cast<const uint32_t*>(Arow + kb + q);
+        const double2 bv = Brow[kb + q];
+        pa[q] = arow ? av : 0u;
+        pb[q] = brow ? bv : make_double2(0.0, 0.0);
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int g = kb + q;
+        pa[q] = (arow && g < P.K) ? *reinterpret_cast<const uint32_t*>(Arow + g) : 0u;
+        pb[q] = (brow && g < P.K) ? Brow[g] : make_double2(0.0, 0.0);
+      }
     }
-    __syncthreads();
+  };
+  auto stage = [&](const uint32_t* pa, const double2* pb) {
+    uint4 re, im;
+    split_bf2(pa, re, im);
+    *reinterpret_cast<uint4*>(&Ar[lrow][lseg]) = re;
+    *reinterpret_cast<uint4*>(&Ai[lrow][lseg]) = im;
+    pack_c128(pb, re, im);
+    *reinterpret_cast<uint4*>(&Br[lrow][lseg]) = re;
+    *reinterpret_cast<uint4*>(&Bi[lrow][lseg]) = im;
+  };
+  auto compute = [&]() {
     const int ko = 8 * (lane >> 4);
     bf8v ar[2], ai[2], nai[2], br[2], bi[2];
 #pragma unroll
@@ -373,6 +447,20 @@ __global__ void __launch_bounds__(256) k_cgemm_cn_bf16(const CNBatch batch, int 
         ci[ti][tj] = mfma32(ar[ti], bi[tj], ci[ti][tj]);
         ci[ti][tj] = mfma32(nai[ti], br[tj], ci[ti][tj]);
       }
+  };
+  if (c0 < c1) fetch(pa0, pb0, c0);
+  if (c0 + 1 < c1) fetch(pa1, pb1, c0 + 1);
+  for (int c = c0; c < c1; c += 2) {
+    stage(pa0, pb0);
+    __syncthreads();
+    if (c + 2 < c1) fetch(pa0, pb0, c + 2);
+    compute();
+    __syncthreads();
+    if (c + 1 >= c1) break;
+    stage(pa1, pb1);
+    __syncthreads();
+    if (c + 3 < c1) fetch(pa1, pb1, c + 3);
+    compute();
     __syncthreads();
   }
   cplx<float>* W = work + P.work_off + int64_t(split) * P.M * P.N;
@@ -391,9 +479,11 @@ __global__ void __launch_bounds__(256) k_cgemm_cn_bf16(const CNBatch batch, int 
 // EX with W = c128 (Q, converted on load), A = bf16 complex (beta); Y c128 accumulated
 __global__ void __launch_bounds__(256) k_cgemm_ex_bf16(const EXBatch batch, double alpha, double beta) {
   __shared__ __align__(16) u16 Wr[BT][KBP], Wi[BT][KBP], Ar[BT][KBP], Ai[BT][KBP];
-  const int pi = find_prob(batch, blockIdx.x);
+  const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
+  const int pi = find_prob(batch, lb);
   const EXDev& P = batch.p[pi];
-  const int tile = blockIdx.x - P.blk0;
+  // row tiles fastest: the row tiles of one column tile share the A slab
+  const int tile = lb - P.blk0;
   const int m0 = (tile % P.tm) * BT, n0 = (tile / P.tm) * BT;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wi = (wave & 1) * 32, wj = (wave >> 1) * 32;
@@ -408,24 +498,49 @@ __global__ void __launch_bounds__(256) k_cgemm_ex_bf16(const EXBatch batch, doub
       ci[a][b] = f4v{0, 0, 0, 0};
     }
   const int nch = (P.K + KB - 1) / KB;
-  // staging: 32 K-rows x 64 columns; thread t -> K-row t/8, columns 8*(t%8) .. +7
-  const int lr = tid >> 3, lc = (tid & 7) * 8;
-  for (int c = 0; c < nch; ++c) {
-    const int i = c * KB + lr;
-    const bool irow = i < P.K;
+  // staging: thread t takes column t%64 of both tiles and the eight K rows 8 (t/64) .. +7,
+  // so its values form the K-contiguous run one LDS row needs (16-byte stores); lanes hold
+  // consecutive columns, so every global load is coalesced.  The next chunk is loaded
+  // while this chunk's MFMAs run.
+  const int col = tid & 63, kg = (tid >> 6) * 8;
+  const bool wcol = m0 + col < P.M, acol = n0 + col < P.N;
+  // columns past the matrix read column m0 / n0 (which exists) and are zeroed after the load
+  const int wc = wcol ? m0 + col : m0, ac = acol ? n0 + col : n0;
+  double2 pw[8];
+  uint32_t pa[8];
+  auto fetch = [&](int c) {
+    const int i0 = c * KB + kg;
+    if (i0 + 8 <= P.K) {   // all eight K rows exist: one bounds test per column
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int m = m0 + lc + q, n = n0 + lc + q;
-      double2 wv = make_double2(0.0, 0.0);
-      if (irow && m < P.M) wv = Wp[int64_t(i) * P.ldw + m];
-      Wr[lc + q][lr] = f2bf(float(wv.x));
-      Wi[lc + q][lr] = f2bf(float(wv.y));
-      bf2 av = {0, 0};
-      if (irow && n < P.N) av = Ap[int64_t(i) * P.lda + n];
-      Ar[lc + q][lr] = av.re;
-      Ai[lc + q][lr] = av.im;
+      for (int q = 0; q < 8; ++q) {
+        const double2 wv = Wp[int64_t(i0 + q) * P.ldw + wc];
+        const uint32_t av = *reinterpret_cast<const uint32_t*>(Ap + int64_t(i0 + q) * P.lda + ac);
+        pw[q] = wcol ? wv : make_double2(0.0, 0.0);
+        pa[q] = acol ? av : 0u;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int i = i0 + q;
+        pw[q] = (i < P.K && wcol) ? Wp[int64_t(i) * P.ldw + m0 + col] : make_double2(0.0, 0.0);
+        pa[q] = (i < P.K && acol) ? *reinterpret_cast<const uint32_t*>(Ap + int64_t(i) * P.lda + n0 + col)
+                                  : 0u;
+      }
+    }
+  };
+  if (nch > 0) fetch(0);
+  for (int c = 0; c < nch; ++c) {
+    {
+      uint4 re, im;
+      pack_c128(pw, re, im);
+      *reinterpret_cast<uint4*>(&Wr[col][kg]) = re;
+      *reinterpret_cast<uint4*>(&Wi[col][kg]) = im;
+      split_bf2(pa, re, im);
+      *reinterpret_cast<uint4*>(&Ar[col][kg]) = re;
+      *reinterpret_cast<uint4*>(&Ai[col][kg]) = im;
     }
     __syncthreads();
+    if (c + 1 < nch) fetch(c + 1);
     const int ko = 8 * (lane >> 4);
     bf8v wr[2], wim[2], nwi[2], ar[2], ai[2];
 #pragma unroll

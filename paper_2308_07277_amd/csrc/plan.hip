@@ -244,7 +244,10 @@ static void build_plan(qm_hpsi_plan* p, const double cell[9], const int32_t grid
     std::vector<GemmCN> cn;
     for (int k = 0; k < p->nk; ++k)
       cn.push_back(GemmCN{nullptr, nullptr, nullptr, nproj, nbnd_max, p->kinfo[k].npw, 0, 0, 0});
-    p->proj_part_bytes = std::max<int64_t>(zgemm_cn_work_bytes(cn), 16);
+    // room for up to 16 K splits of every k (the autotuner tries 1 .. 16)
+    int64_t mn = 0;
+    for (const GemmCN& g : cn) mn += int64_t(g.M) * g.N;
+    p->proj_part_bytes = std::max<int64_t>(zgemm_cn_work_bytes(cn), 16 * mn * 16);
     QM_HIP(hipMalloc(&p->proj_part, p->proj_part_bytes));
   }
   if (prec != QM_PREC_FP64) convert_beta(p, prec, s);
