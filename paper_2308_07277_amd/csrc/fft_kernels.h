@@ -115,6 +115,14 @@ __global__ void __launch_bounds__(TS * Split<N3>::R2) k_zinv(LocalArgs a) {
 }
 
 // ------------------------------------------------------------------ xy plane
+// Orders the LDS accesses of one wave: every lane's earlier LDS writes are complete and
+// visible to the other lanes of the wave before any later LDS access.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename R, int NX>
 __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
   constexpr int R1 = Split<NX>::R1, R2 = Split<NX>::R2;
@@ -182,64 +190,69 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
   }
   __syncthreads();
   // ---- x rows: inverse x, * V / N_r, forward x; active columns only written back.
-  // Lanes run over the intra-row index q first (consecutive LDS columns, consecutive V
-  // entries), then over the rows of the group; the row scratch X is row-major [r][NX + 1].
+  // Each wave owns whole rows (R2 lanes per row, 64 / R2 rows at a time) and its own row
+  // scratch, so the exchanges between the two passes of a row need only wave-level ordering.
+  // Lanes run over the intra-row index q (consecutive LDS columns, consecutive V entries).
   const R* V = reinterpret_cast<const R*>(a.vplan) + int64_t(p) * NX * NX;  // [i2][i1]
-  constexpr int NXP = NX + 1;
-  const int q = tid % R2, r = tid / R2;
-  for (int r0 = 0; r0 < NX; r0 += RG) {
-    const int i2 = r0 + r;
-    const bool act = (r < RG) && (i2 < NX);
-    const int lrow = act ? (i2 / R2) + R1 * (i2 % R2) : 0;
-    cplx<R>* Xr = X + r * NXP;
-    if (act && q < R1) {
-      cplx<R> x[R2];
+  constexpr int NXP = NX + 1, RW = 64 / R2;
+  {
+    const int wave = tid >> 6, lane = tid & 63;
+    const int q = lane % R2, rs = lane / R2;
+    cplx<R>* Xr = X + (wave * RW + (rs < RW ? rs : 0)) * NXP;
+    for (int r0 = wave * RW; r0 < NX; r0 += 4 * RW) {
+      const int i2 = r0 + rs;
+      const bool act = rs < RW && i2 < NX;
+      const int lrow = act ? (i2 / R2) + R1 * (i2 % R2) : 0;
+      if (act && q < R1) {
+        cplx<R> x[R2];
 #pragma unroll
-      for (int n2 = 0; n2 < R2; ++n2) {
-        const int c = col[q + R1 * n2];
-        x[n2] = c >= 0 ? L[lrow * ns + c] : cplx<R>{R(0), R(0)};
+        for (int n2 = 0; n2 < R2; ++n2) {
+          const int c = col[q + R1 * n2];
+          x[n2] = c >= 0 ? L[lrow * ns + c] : cplx<R>{R(0), R(0)};
+        }
+        Dft<R2, +1, R>::run(x);
+#pragma unroll
+        for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tw[(q * k2) % NX]);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) Xr[q + R1 * k2] = x[k2];
       }
-      Dft<R2, +1, R>::run(x);
+      wave_lds_sync();
+      cplx<R> y[R1];
+      if (act) {
 #pragma unroll
-      for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tw[(q * k2) % NX]);
+        for (int n1 = 0; n1 < R1; ++n1) y[n1] = Xr[n1 + R1 * q];
+        Dft<R1, +1, R>::run(y);  // y[k1] is the row value at i1 = q + R2 k1
+        const R* Vrow = V + i2 * NX;
 #pragma unroll
-      for (int k2 = 0; k2 < R2; ++k2) Xr[q + R1 * k2] = x[k2];
-    }
-    __syncthreads();
-    cplx<R> y[R1];
-    if (act) {
+        for (int k1 = 0; k1 < R1; ++k1) y[k1] = cscale(y[k1], Vrow[q + R2 * k1]);
+        Dft<R1, -1, R>::run(y);  // forward, factorisation (R2, R1): first pass over n2' = k1
 #pragma unroll
-      for (int n1 = 0; n1 < R1; ++n1) y[n1] = Xr[n1 + R1 * q];
-      Dft<R1, +1, R>::run(y);  // y[k1] is the row value at i1 = q + R2 k1
-      const R* Vrow = V + i2 * NX;
-#pragma unroll
-      for (int k1 = 0; k1 < R1; ++k1) y[k1] = cscale(y[k1], Vrow[q + R2 * k1]);
-      Dft<R1, -1, R>::run(y);  // forward, factorisation (R2, R1): first pass over n2' = k1
-#pragma unroll
-      for (int k2 = 1; k2 < R1; ++k2) {
-        const cplx<R> w = tw[(q * k2) % NX];
-        y[k2] = cmul(y[k2], cplx<R>{w.re, -w.im});
+        for (int k2 = 1; k2 < R1; ++k2) {
+          const cplx<R> w = tw[(q * k2) % NX];
+          y[k2] = cmul(y[k2], cplx<R>{w.re, -w.im});
+        }
       }
-    }
-    __syncthreads();
-    if (act) {
+      wave_lds_sync();
+      if (act) {
 #pragma unroll
-      for (int k2 = 0; k2 < R1; ++k2) Xr[q + R2 * k2] = y[k2];
-    }
-    __syncthreads();
-    if (act && q < R1) {
-      cplx<R> z[R2];
-#pragma unroll
-      for (int n1 = 0; n1 < R2; ++n1) z[n1] = Xr[n1 + R2 * q];
-      Dft<R2, -1, R>::run(z);  // natural output at i1 = q + R1 k1
-#pragma unroll
-      for (int k1 = 0; k1 < R2; ++k1) {
-        const int c = col[q + R1 * k1];
-        if (c >= 0) L[lrow * ns + c] = z[k1];
+        for (int k2 = 0; k2 < R1; ++k2) Xr[q + R2 * k2] = y[k2];
       }
+      wave_lds_sync();
+      if (act && q < R1) {
+        cplx<R> z[R2];
+#pragma unroll
+        for (int n1 = 0; n1 < R2; ++n1) z[n1] = Xr[n1 + R2 * q];
+        Dft<R2, -1, R>::run(z);  // natural output at i1 = q + R1 k1
+#pragma unroll
+        for (int k1 = 0; k1 < R2; ++k1) {
+          const int c = col[q + R1 * k1];
+          if (c >= 0) L[lrow * ns + c] = z[k1];
+        }
+      }
+      wave_lds_sync();
     }
-    __syncthreads();
   }
+  __syncthreads();
   // ---- forward y on active columns, input in the transposed order left above
   for (int w = tid; w < nax * R2; w += 256) {
     const int ia = w % nax, n1 = w / nax;  // n1 in [0, R2)
