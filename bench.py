@@ -183,7 +183,7 @@ def train_preconditioner(steps=1200, max_resid=1e-3):
                      "loss_teter": l_init, "loss_final": l_final}
 
 
-def davidson_run(name, weights=None, tol=1e-8, max_basis_factor=4, switch_resid=1e-3):
+def davidson_run(name, weights=None, tol=1e-8, max_basis_factor=4, switch_resid=1e-3, lanes=2):
     """Block Davidson from a seeded random start to max residual <= tol over every k-point
     and band: arm A float64 H + Teter; arm B float32-FFT/bf16-GEMM H while the residual is
     above switch_resid (float64 H below) + the learned preconditioner."""
@@ -196,6 +196,7 @@ def davidson_run(name, weights=None, tol=1e-8, max_basis_factor=4, switch_resid=
     arms = {}
     eigs = {}
     cfgs = [("fp64+teter", dict(precond=qm.QM_PRECOND_TETER, switch_resid=0.0)),
+            ("fp64+teter, one lane", dict(precond=qm.QM_PRECOND_TETER, switch_resid=0.0, lanes=1)),
             ("mixed+teter", dict(precond=qm.QM_PRECOND_TETER, switch_resid=switch_resid))]
     if weights is not None:
         cfgs.append(("fp64+mlp", dict(precond=qm.QM_PRECOND_MLP, mlp_weights=weights,
@@ -206,6 +207,8 @@ def davidson_run(name, weights=None, tol=1e-8, max_basis_factor=4, switch_resid=
         psi = start.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        kw = dict(kw)
+        kw.setdefault("lanes", lanes)
         eig, res, stats, st = qm.qm_davidson_solve(plan, -1, psi, w.nbnd, tol=tol, max_iter=400,
                                                    max_basis=max_basis_factor * w.nbnd, **kw)
         torch.cuda.synchronize()
@@ -221,7 +224,8 @@ def davidson_run(name, weights=None, tol=1e-8, max_basis_factor=4, switch_resid=
             arms[arm]["max_abs_eig_diff_vs_fp64_teter"] = float(np.abs(eigs[arm] - eigs["fp64+teter"]).max())
     plan.close()
     return {"workload": f"{name}: {len(w.atoms)}-atom cell, {w.nk} k-points (Gamma + 16), "
-                        f"{w.nbnd} bands, tol {tol:g} Ha, max_basis {max_basis_factor} nbnd",
+                        f"{w.nbnd} bands, tol {tol:g} Ha, max_basis {max_basis_factor} nbnd, "
+                        f"k-points in {lanes} concurrent lanes unless the arm says otherwise",
             "arms": arms, "lowest_eig_gamma": float(eigs["fp64+teter"][0][0]),
             "eig_error_bound_note": "every eigenvalue of every arm is within its residual norm "
                                     "(<= tol) of an exact eigenvalue (Krylov-Weinstein)"}

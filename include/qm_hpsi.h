@@ -93,6 +93,12 @@ typedef struct {
                              0 = float64 throughout [0] */
   const void *mlp_weights;/* device float32 weights of the learned preconditioner
                              (layout in qm_mlp_*), required for QM_PRECOND_MLP */
+  int32_t lanes;          /* qm_davidson_solve with k = -1: split the k-points into this
+                             many contiguous groups and solve them at the same time, each
+                             on its own stream and host thread (k-points are independent
+                             problems, so results equal the one-group solve up to
+                             rounding; the precision ladder switches per group).  0 or 1:
+                             one group [0] */
 } qm_dav_opts;
 
 /* Davidson statistics (host), filled by qm_davidson_solve. */

@@ -13,6 +13,9 @@
 #include <cmath>
 #include <cstring>
 
+#include <string>
+#include <thread>
+
 #include "dense.h"
 
 namespace qm {
@@ -23,6 +26,8 @@ void mlp_precondition(qm_hpsi_plan* p, const DJobs& jobs, const void* weights, h
 
 struct DavState {
   int nb = 0, mb = 0, k0 = 0, k1 = 0, nk = 0;
+  int64_t g0 = 0, npl = 0;   // G offset of k0 and plane waves of k0..k1-1 (band block base)
+  ProjScratch ps;            // own projector scratch (lanes only; else the plan's)
   bool ready = false;
   bool lowp = false;
   double2 *V = nullptr, *HV = nullptr, *X = nullptr, *HX = nullptr, *R = nullptr, *TS = nullptr;
@@ -48,7 +53,7 @@ struct DavState {
 static void dav_release(DavState* d) {
   void* dev[] = {d->V, d->HV, d->X, d->HX, d->R, d->TS, d->Hs, d->Aw, d->Z, d->tau, d->Cw, d->G,
                  d->W, d->theta, d->d, d->e, d->resn, d->tkin, d->yw, d->fw, d->unconv, d->info,
-                 d->goff, d->work, d->estar};
+                 d->goff, d->work, d->estar, d->ps.part};
   for (void* q : dev)
     if (q) (void)hipFree(q);
   void* host[] = {d->h_resn, d->h_theta, d->h_unconv, d->h_info};
@@ -62,6 +67,12 @@ static void dav_release(DavState* d) {
 void davidson_free(qm_hpsi_plan* p) {
   if (p->dav) dav_release(p->dav);
   p->dav = nullptr;
+  for (DavState* d : p->dav_lanes)
+    if (d) dav_release(d);
+  p->dav_lanes.clear();
+  for (hipStream_t q : p->lane_streams)
+    if (q) (void)hipStreamDestroy(q);
+  p->lane_streams.clear();
 }
 
 template <typename T>
@@ -71,7 +82,7 @@ static T* dalloc(size_t n) {
   return q;
 }
 
-static DavState* dav_create(qm_hpsi_plan* p, int k0, int k1, int nb, int mb) {
+static DavState* dav_create(qm_hpsi_plan* p, int k0, int k1, int nb, int mb, bool own_scratch) {
   DavState* d = new DavState();
   try {
     d->nb = nb;
@@ -79,7 +90,13 @@ static DavState* dav_create(qm_hpsi_plan* p, int k0, int k1, int nb, int mb) {
     d->k0 = k0;
     d->k1 = k1;
     d->nk = p->nk;
-    const size_t np = size_t(p->npw_total), nk = size_t(p->nk);
+    d->g0 = p->kinfo[k0].g_off;
+    d->npl = p->kinfo[k1 - 1].g_off + p->kinfo[k1 - 1].npw - d->g0;
+    const size_t np = size_t(d->npl), nk = size_t(p->nk);
+    if (own_scratch && p->proj_part_bytes > 0) {
+      d->ps.bytes = p->proj_part_bytes;
+      d->ps.part = dalloc<char>(size_t(d->ps.bytes));
+    }
     d->V = dalloc<double2>(size_t(mb) * np);
     d->HV = dalloc<double2>(size_t(mb) * np);
     d->X = dalloc<double2>(size_t(nb) * np);
@@ -133,7 +150,7 @@ static double2* vrow(DavState* d, double2* base, const DJob& j, int row) {
 static void timed_apply(qm_hpsi_plan* p, DavState* d, const std::vector<KSlice>& sl, const void* in,
                         void* out, hipStream_t s, bool lowp) {
   QM_HIP(hipEventRecord(d->ev[0], s));
-  apply_h_slices(p, sl, in, out, s, lowp ? p->prec : QM_PREC_FP64);
+  apply_h_slices(p, sl, in, out, s, lowp ? p->prec : QM_PREC_FP64, nullptr, d->ps.part ? &d->ps : nullptr);
   QM_HIP(hipEventRecord(d->ev[1], s));
   QM_HIP(hipEventSynchronize(d->ev[1]));
   float ms = 0.f;
@@ -240,8 +257,8 @@ static DJob make_job(qm_hpsi_plan* p, DavState* d, int k) {
   DJob j{};
   j.k = k;
   j.npw = p->kinfo[k].npw;
-  j.voff = int64_t(d->mb) * p->kinfo[k].g_off;
-  j.xoff = int64_t(d->nb) * p->kinfo[k].g_off;
+  j.voff = int64_t(d->mb) * (p->kinfo[k].g_off - d->g0);
+  j.xoff = int64_t(d->nb) * (p->kinfo[k].g_off - d->g0);
   return j;
 }
 
@@ -286,7 +303,7 @@ static void write_outputs(qm_hpsi_plan* p, DavState* d, void* psi, double* eig, 
     const KInfo& ki = p->kinfo[k];
     if (psi)
       QM_HIP(hipMemcpyAsync(reinterpret_cast<double2*>(psi) + int64_t(d->nb) * (ki.g_off - g0),
-                            d->X + int64_t(d->nb) * ki.g_off, sizeof(double2) * d->nb * ki.npw,
+                            d->X + int64_t(d->nb) * (ki.g_off - g0), sizeof(double2) * d->nb * ki.npw,
                             hipMemcpyDeviceToDevice, s));
     for (int n = 0; n < d->nb; ++n) {
       if (eig) eig[int64_t(k - d->k0) * d->nb + n] = d->h_theta[int64_t(k) * d->mb + n];
@@ -296,10 +313,13 @@ static void write_outputs(qm_hpsi_plan* p, DavState* d, void* psi, double* eig, 
   QM_HIP(hipStreamSynchronize(s));
 }
 
-static qm_status dav_step(qm_hpsi_plan* p, int k, void* psi, double* eig, double* resnorm, int nb,
-                          const qm_dav_opts* o, int32_t* n_unconv, hipStream_t s) {
+// One Davidson iteration on k-points k0..k1-1 with the state in *slot (created or rebuilt as
+// needed).  psi points at k0's first band, eig and resnorm at k0's first entry.
+static qm_status dav_step_range(qm_hpsi_plan* p, DavState** slot, bool own_scratch, int k0, int k1,
+                                void* psi, double* eig, double* resnorm, int nb,
+                                const qm_dav_opts* o, int32_t* n_unconv, hipStream_t s) {
   QM_REQUIRE(nb >= 1 && nb <= p->nbnd_max, QM_E_ARG, "need 1 <= nbnd <= nbnd_max");
-  QM_REQUIRE(k >= -1 && k < p->nk, QM_E_ARG, "k out of range");
+  QM_REQUIRE(k0 >= 0 && k0 < k1 && k1 <= p->nk, QM_E_ARG, "k out of range");
   QM_REQUIRE(psi, QM_E_ARG, "psi must be non-NULL");
   const double tol = (o && o->tol > 0) ? o->tol : 1e-8;
   int mb = (o && o->max_basis > 0) ? o->max_basis : 4 * nb;
@@ -308,15 +328,15 @@ static qm_status dav_step(qm_hpsi_plan* p, int k, void* psi, double* eig, double
   const int precond = o ? o->precond : QM_PRECOND_TETER;
   QM_REQUIRE(precond == QM_PRECOND_TETER || (precond == QM_PRECOND_MLP && o->mlp_weights),
              QM_E_ARG, "QM_PRECOND_MLP needs mlp_weights");
-  const int k0 = k < 0 ? 0 : k, k1 = k < 0 ? p->nk : k + 1;
   QM_REQUIRE(k1 - k0 <= kMaxSlices, QM_E_ARG, "at most 32 k-points per Davidson call");
-  DavState* d = p->dav;
+  DavState* d = *slot;
   const bool fresh = !d || !d->ready || (o && o->restart) || d->k0 != k0 || d->k1 != k1 ||
                      d->nb != nb || d->mb != mb;
   if (fresh) {
     if (!d || d->k0 != k0 || d->k1 != k1 || d->nb != nb || d->mb != mb) {
-      davidson_free(p);
-      p->dav = d = dav_create(p, k0, k1, nb, mb);
+      if (d) dav_release(d);
+      *slot = d = nullptr;
+      *slot = d = dav_create(p, k0, k1, nb, mb, own_scratch);
     }
     d->ready = false;
     std::fill(d->m.begin(), d->m.end(), 0);
@@ -433,6 +453,13 @@ static qm_status dav_step(qm_hpsi_plan* p, int k, void* psi, double* eig, double
   if (n_unconv) *n_unconv = r.n_unconv;
   if (r.nan) throw Error(QM_E_NAN, "non-finite residual norm");
   return QM_OK;
+}
+
+static qm_status dav_step(qm_hpsi_plan* p, int k, void* psi, double* eig, double* resnorm, int nb,
+                          const qm_dav_opts* o, int32_t* n_unconv, hipStream_t s) {
+  QM_REQUIRE(k >= -1 && k < p->nk, QM_E_ARG, "k out of range");
+  const int k0 = k < 0 ? 0 : k, k1 = k < 0 ? p->nk : k + 1;
+  return dav_step_range(p, &p->dav, false, k0, k1, psi, eig, resnorm, nb, o, n_unconv, s);
 }
 
 DavState* dav_of(qm_hpsi_plan* p) { return p->dav; }
@@ -561,6 +588,42 @@ static void training_pairs(qm_hpsi_plan* p, const void* xstar, const double* est
 
 }  // namespace qm
 
+namespace qm {
+
+struct SolveResult {
+  qm_status st = QM_OK;
+  int32_t nun = 0;
+  std::string err;
+};
+
+// the Davidson loop on k0..k1-1 with the state in *slot: a restart step, then steps until
+// every band of the range has converged or max_iter is reached
+static SolveResult solve_range(qm_hpsi_plan* p, DavState** slot, bool own_scratch, int k0, int k1,
+                               void* psi, double* eig, double* resnorm, int nb, qm_dav_opts o,
+                               hipStream_t s) {
+  SolveResult r;
+  const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
+  auto step = [&]() {
+    try {
+      r.st = dav_step_range(p, slot, own_scratch, k0, k1, psi, eig, resnorm, nb, &o, &r.nun, s);
+    } catch (const Error& e) {
+      r.err = e.what();
+      r.st = e.code;
+    } catch (const std::exception& e) {
+      r.err = e.what();
+      r.st = QM_E_STATE;
+    }
+    if (r.st != QM_OK && *slot) (*slot)->ready = false;
+  };
+  o.restart = 1;
+  step();
+  o.restart = 0;
+  for (int iter = 0; r.st == QM_OK && r.nun > 0 && iter < max_iter; ++iter) step();
+  return r;
+}
+
+}  // namespace qm
+
 using namespace qm;
 
 extern "C" {
@@ -590,34 +653,80 @@ qm_status qm_davidson_solve(qm_hpsi_plan* plan, int32_t k, void* psi, double* ei
   const auto t0 = std::chrono::steady_clock::now();
   qm_dav_opts o{};
   if (opts) o = *opts;
-  const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
-  int32_t nun = 0;
-  o.restart = 1;
-  qm_status st = qm_davidson_step(plan, k, psi, eig, resnorm, nbnd, &o, &nun, stream);
-  o.restart = 0;
-  int iter = 0;
-  while (st == QM_OK && nun > 0 && iter < max_iter) {
-    st = qm_davidson_step(plan, k, psi, eig, resnorm, nbnd, &o, &nun, stream);
-    ++iter;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (k < -1 || k >= plan->nk) {
+    plan->err = "k out of range";
+    return QM_E_ARG;
   }
-  if (stats && plan->dav) {
-    DavState* d = plan->dav;
+  const int nlanes = (k < 0 && o.lanes >= 2) ? std::min<int>(o.lanes, plan->nk) : 1;
+  std::vector<int> kb(nlanes + 1);
+  for (int i = 0; i <= nlanes; ++i) kb[i] = k < 0 ? (i * plan->nk) / nlanes : (i == 0 ? k : k + 1);
+  std::vector<SolveResult> res(nlanes);
+  try {
+    if (nlanes == 1) {
+      res[0] = solve_range(plan, &plan->dav, false, kb[0], kb[1], psi, eig, resnorm, nbnd, o, s);
+    } else {
+      // every lane reads the reduced-precision beta: convert it before they start
+      if (o.switch_resid > 0.0 && plan->prec != QM_PREC_FP64) convert_beta(plan, plan->prec, s);
+      plan->dav_lanes.resize(nlanes, nullptr);
+      plan->lane_streams.resize(nlanes, nullptr);
+      for (hipStream_t& q : plan->lane_streams)
+        if (!q) QM_HIP(hipStreamCreateWithFlags(&q, hipStreamNonBlocking));
+      hipEvent_t ready;
+      QM_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+      QM_HIP(hipEventRecord(ready, s));  // psi and earlier work on the caller's stream
+      for (hipStream_t q : plan->lane_streams) QM_HIP(hipStreamWaitEvent(q, ready, 0));
+      std::vector<std::thread> th;
+      const int64_t gbase = plan->kinfo[0].g_off;
+      for (int i = 0; i < nlanes; ++i) {
+        double2* lp = reinterpret_cast<double2*>(psi) + int64_t(nbnd) * (plan->kinfo[kb[i]].g_off - gbase);
+        th.emplace_back([&, i, lp]() {
+          res[i] = solve_range(plan, &plan->dav_lanes[i], true, kb[i], kb[i + 1], lp,
+                               eig ? eig + int64_t(kb[i]) * nbnd : nullptr,
+                               resnorm ? resnorm + int64_t(kb[i]) * nbnd : nullptr, nbnd, o,
+                               plan->lane_streams[i]);
+        });
+      }
+      for (std::thread& t : th) t.join();
+      (void)hipEventDestroy(ready);
+    }
+  } catch (const Error& e) {
+    plan->err = e.what();
+    return e.code;
+  }
+  qm_status st = QM_OK;
+  int32_t nun = 0;
+  for (const SolveResult& r : res) {
+    if (r.st != QM_OK && st == QM_OK) {
+      st = r.st;
+      plan->err = r.err;
+    }
+    nun += r.nun;
+  }
+  if (stats) {
     std::memset(stats, 0, sizeof(*stats));
+    double mr = 0.0, th = 0.0, te = 0.0;
     int itmax = 0;
-    for (int kk = d->k0; kk < d->k1; ++kk) itmax = std::max(itmax, d->it[kk]);
+    for (int i = 0; i < nlanes; ++i) {
+      const DavState* d = nlanes == 1 ? plan->dav : plan->dav_lanes[i];
+      if (!d) continue;
+      for (int kk = d->k0; kk < d->k1; ++kk) {
+        itmax = std::max(itmax, d->it[kk]);
+        for (int n = 0; n < d->nb; ++n) mr = std::max(mr, d->h_resn[int64_t(kk) * d->nb + n]);
+      }
+      stats->n_hpsi_bands += d->n_hpsi;
+      stats->n_hpsi_bands_lowp += d->n_hpsi_lowp;
+      th = std::max(th, d->t_hpsi);   // lanes overlap in time: the slowest lane's phases
+      te = std::max(te, d->t_eig);
+    }
     stats->iterations = itmax;
     stats->converged = (st == QM_OK && nun == 0) ? 1 : 0;
-    stats->n_hpsi_bands = d->n_hpsi;
-    stats->n_hpsi_bands_lowp = d->n_hpsi_lowp;
-    double mr = 0.0;
-    for (int kk = d->k0; kk < d->k1; ++kk)
-      for (int n = 0; n < d->nb; ++n) mr = std::max(mr, d->h_resn[int64_t(kk) * d->nb + n]);
     stats->max_resnorm = mr;
-    stats->t_hpsi_ms = d->t_hpsi;
-    stats->t_eig_ms = d->t_eig;
+    stats->t_hpsi_ms = th;
+    stats->t_eig_ms = te;
     stats->t_total_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    stats->t_subspace_ms = stats->t_total_ms - d->t_hpsi - d->t_eig;
+    stats->t_subspace_ms = stats->t_total_ms - th - te;
   }
   if (st == QM_OK && nun > 0) {
     plan->err = "Davidson did not converge within max_iter";

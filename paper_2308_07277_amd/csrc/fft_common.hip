@@ -69,7 +69,7 @@ std::vector<KSlice> contiguous_slices(const qm_hpsi_plan* p, int k0, int k1, int
 }
 
 void apply_h_slices(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
-                    hipStream_t s, qm_prec prec, StageEvents* ev) {
+                    hipStream_t s, qm_prec prec, StageEvents* ev, const ProjScratch* ps) {
   for (size_t b = 0; b < sl.size(); b += kMaxSlices) {
     std::vector<KSlice> chunk(sl.begin() + b, sl.begin() + std::min(sl.size(), b + kMaxSlices));
     std::vector<KSlice> nz;
@@ -77,7 +77,7 @@ void apply_h_slices(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* 
       if (x.nb > 0) nz.push_back(x);
     if (nz.empty()) continue;
     launch_hpsi_local(p, nz, psi, hpsi, s, prec != QM_PREC_FP64, ev);
-    launch_nonlocal(p, nz, psi, hpsi, s, prec, ev);
+    launch_nonlocal(p, nz, psi, hpsi, s, prec, ev, ps);
   }
 }
 

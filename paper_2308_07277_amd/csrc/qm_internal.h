@@ -117,6 +117,9 @@ struct qm_hpsi_plan {
   int32_t tuned_splits[3] = {0, 0, 0};  // projector split-K chosen by the autotuner, per precision
   std::string err;
   qm::DavState* dav = nullptr;
+  // concurrent Davidson lanes of qm_davidson_solve (disjoint k ranges), their streams
+  std::vector<qm::DavState*> dav_lanes;
+  std::vector<hipStream_t> lane_streams;
   // captured qm_apply_h launch sequences (kernel nodes only), replayed on the caller's stream
   struct GraphEntry {
     int32_t k, nbnd, prec;
@@ -141,11 +144,20 @@ namespace qm {
 void launch_hpsi_local(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
                        hipStream_t s, bool fp32, StageEvents* ev = nullptr);
 void launch_vplan(qm_hpsi_plan* p, const double* vloc_r, hipStream_t s);
+// Split-K scratch of the projector GEMM.  Calls that may run at the same time on different
+// streams (Davidson lanes, which own disjoint k-points) each pass their own.
+struct ProjScratch {
+  void* part = nullptr;
+  int64_t bytes = 0;
+};
 void launch_nonlocal(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
-                     hipStream_t s, qm_prec prec, StageEvents* ev = nullptr);
-// H applied to every slice (local + non-local), in chunks of kMaxSlices
+                     hipStream_t s, qm_prec prec, StageEvents* ev = nullptr,
+                     const ProjScratch* ps = nullptr);
+// H applied to every slice (local + non-local), in chunks of kMaxSlices.  At most one slice
+// per k-point per call (stick buffer, P and Q are addressed per k).
 void apply_h_slices(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
-                    hipStream_t s, qm_prec prec, StageEvents* ev = nullptr);
+                    hipStream_t s, qm_prec prec, StageEvents* ev = nullptr,
+                    const ProjScratch* ps = nullptr);
 std::vector<KSlice> contiguous_slices(const qm_hpsi_plan* p, int k0, int k1, int nbnd);
 int xy_group_lanes(int nx);                       // lanes per line of the lane-group kernel, 0: none
 int xy_pick(const qm_hpsi_plan* p, int real_type);  // 1 two-pass, 2 lane-group

@@ -7,6 +7,8 @@ import pytest
 
 import paper_2308_07277_amd as qm
 
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
 
 def _declared():
     src = open(qm.HEADER_PATH).read()
@@ -48,9 +50,26 @@ def test_binding_names_match_abi():
         assert callable(getattr(qm, n))
 
 
-def test_struct_sizes_match_header():
+def test_struct_sizes_match_header(tmp_path):
+    """The binding's ctypes structures have the sizes and field offsets the C compiler gives
+    the header's structures (a small C program built with gcc prints them)."""
     import ctypes
-    # qm_dav_opts: double, 4 x int32, double, pointer
-    assert ctypes.sizeof(qm.qm_dav_opts) == 8 + 16 + 8 + 8
-    assert ctypes.sizeof(qm.qm_dav_stats) == 4 + 4 + 8 + 8 + 5 * 8
-    assert ctypes.sizeof(qm.qm_kset) == 8 + 3 * 8
+    import subprocess
+    structs = {"qm_dav_opts": qm.qm_dav_opts, "qm_dav_stats": qm.qm_dav_stats, "qm_kset": qm.qm_kset}
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "qm_hpsi.h"', "int main(void) {"]
+    for name, cls in structs.items():
+        lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{name}.{fname} %zu\\n", offsetof({name}, {fname}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    inc = os.path.join(ROOT, "include")
+    subprocess.run(["gcc", "-std=c11", f"-I{inc}", str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                  check=True).stdout.splitlines())
+    for name, cls in structs.items():
+        assert ctypes.sizeof(cls) == int(got[name]), name
+        for fname, _ in cls._fields_:
+            assert getattr(cls, fname).offset == int(got[f"{name}.{fname}"]), (name, fname)
