@@ -183,7 +183,7 @@ def train_preconditioner(steps=1200, max_resid=1e-3):
                      "loss_teter": l_init, "loss_final": l_final}
 
 
-def davidson_run(name, weights=None, tol=1e-8, max_basis_factor=4, switch_resid=1e-3, lanes=2):
+def davidson_run(name, weights=None, tol=1e-8, max_basis_factor=4, switch_resid=1e-3, lanes=3):
     """Block Davidson from a seeded random start to max residual <= tol over every k-point
     and band: arm A float64 H + Teter; arm B float32-FFT/bf16-GEMM H while the residual is
     above switch_resid (float64 H below) + the learned preconditioner."""

@@ -50,6 +50,14 @@ struct LocalArgs {
   int32_t nax_stride;       // row stride of the xy-plane buffer (elements)
 };
 
+// This k's stick buffer.  Its region starts at the same byte offset (sbuf_off complex
+// double elements) whatever the working precision, so k-points that run in different
+// precisions at the same time (concurrent Davidson lanes) never share bytes.
+template <typename R>
+__device__ __forceinline__ cplx<R>* stick_base(void* sbuf, const KInfo& ki) {
+  return reinterpret_cast<cplx<R>*>(reinterpret_cast<char*>(sbuf) + ki.sbuf_off * int64_t(16));
+}
+
 // slice holding z-kernel block bid; bid becomes the block index within the slice
 __device__ __forceinline__ int locate_tile_block(const LocalArgs& a, int& bid) {
   int s = 0;
@@ -107,7 +115,7 @@ __global__ void __launch_bounds__(TS * Split<N3>::R2) k_zinv(LocalArgs a) {
 #pragma unroll
     for (int n1 = 0; n1 < R1; ++n1) y[n1] = tile[(n1 + R1 * j) * TS + sl];
     Dft<R1, +1, R>::run(y);
-    cplx<R>* out = reinterpret_cast<cplx<R>*>(a.sbuf) + ki.sbuf_off +
+    cplx<R>* out = stick_base<R>(a.sbuf, ki) +
                    int64_t(band) * N3 * ki.nstick + s0 + sl;
 #pragma unroll
     for (int k1 = 0; k1 < R1; ++k1) out[int64_t(k1 + R1 * j) * ki.nstick] = y[k1];
@@ -157,7 +165,7 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
   }
   for (int i = tid; i < NX * ns; i += 256) L[i] = {R(0), R(0)};
   __syncthreads();
-  cplx<R>* plane = reinterpret_cast<cplx<R>*>(a.sbuf) + ki.sbuf_off +
+  cplx<R>* plane = stick_base<R>(a.sbuf, ki) +
                    (int64_t(band) * N3 + p) * ki.nstick;
   const int32_t* spos = a.stick_pos + ki.stick_off;
   for (int s = tid; s < ki.nstick; s += 256) {
@@ -418,7 +426,7 @@ __global__ void __launch_bounds__(L * NX) k_xy_group(LocalArgs a) {
   }
   for (int i = tid; i < NX * ns; i += NT) Lp[i] = {R(0), R(0)};
   __syncthreads();
-  cplx<R>* plane = reinterpret_cast<cplx<R>*>(a.sbuf) + ki.sbuf_off +
+  cplx<R>* plane = stick_base<R>(a.sbuf, ki) +
                    (int64_t(band) * N3 + p) * ki.nstick;
   const int32_t* spos = a.stick_pos + ki.stick_off;
   for (int s = tid; s < ki.nstick; s += NT) {
@@ -501,7 +509,7 @@ __global__ void __launch_bounds__(TS * Split<N3>::R2) k_zfwd(LocalArgs a) {
   __syncthreads();
   const int sl = tid % TS, j = tid / TS;  // j in [0, R2)
   {
-    const cplx<R>* in = reinterpret_cast<const cplx<R>*>(a.sbuf) + ki.sbuf_off +
+    const cplx<R>* in = static_cast<const cplx<R>*>(stick_base<R>(a.sbuf, ki)) +
                         int64_t(band) * N3 * ki.nstick + s0 + sl;
     cplx<R> x[R1];
 #pragma unroll

@@ -50,7 +50,7 @@ struct KInfo {
   int64_t g_off;    // prefix sum of npw over earlier k
   int64_t stick_off;// prefix sum of nstick
   int64_t tile_off; // prefix sum of (ntile + 1)
-  int64_t sbuf_off; // element offset of this k's stick buffer (band 0)
+  int64_t sbuf_off; // offset of this k's stick buffer (band 0), in complex-double elements
   int64_t beta_off; // element offset of beta_k (= nproj * g_off)
 };
 

@@ -163,3 +163,28 @@ def test_lanes_match_single_group():
         bound = 2.0 * np.sqrt(c + 1) * 1e-8 / gap
         print(f"k {ik}: bands 0-{c}, gap {gap:.3e}, projector diff {np.abs(p1 - p2).max():.2e} <= {bound:.2e}")
         assert np.abs(p1 - p2).max() <= bound
+
+
+def test_lanes_with_precision_ladder():
+    """Lanes switch from the reduced-precision H to float64 at different times, so one
+    lane's float32 stick buffers coexist with another's float64 ones: each k-point's
+    region starts at the same byte offset in both precisions, so they never overlap.  Four
+    lanes (one k-point each) on the 8-atom cell with the ladder: every band converges and
+    the eigenvalues match the one-group float64 solve within 1e-10 Ha."""
+    import torch
+    import paper_2308_07277_amd as qm
+    w = workload.make_workload("c2")
+    a = plan_arrays(w)
+    plan, _ = make_plan(w, w.nbnd, prec=2, arrays=a)
+    start = torch.cat([torch.from_numpy(w.psi(ik, purpose=2).reshape(-1)) for ik in range(w.nk)]).cuda()
+    psi = start.clone()
+    e1, r1, s1, st1 = qm.qm_davidson_solve(plan, -1, psi, w.nbnd, tol=1e-8, lanes=1)
+    psi = start.clone()
+    e4, r4, s4, st4 = qm.qm_davidson_solve(plan, -1, psi, w.nbnd, tol=1e-8, lanes=4,
+                                           switch_resid=1e-3)
+    plan.close()
+    print("one group", s1["iterations"], "four lanes + ladder", s4["iterations"],
+          "low-precision bands", s4["n_hpsi_bands_lowp"], "max eig diff", np.abs(e1 - e4).max())
+    assert st1 == 0 and st4 == 0 and r4.max() <= 1e-8
+    assert s4["n_hpsi_bands_lowp"] > 0
+    assert np.abs(e1 - e4).max() <= 1e-10
