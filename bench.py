@@ -183,7 +183,76 @@ def train_preconditioner(steps=1200, max_resid=1e-3):
                      "loss_teter": l_init, "loss_final": l_final}
 
 
-def davidson_run(name, weights=None, tol=1e-8, max_basis_factor=4, switch_resid=1e-3, lanes=3):
+def hpsi_rates(name, steps=20, warmup=3):
+    """H|psi> bands/s of one workload in each precision (all k, all bands per call)."""
+    import torch
+    import workload
+    import paper_2308_07277_amd as qm
+    w = workload.make_workload(name)
+    miller, beta, vloc, psi = build_inputs(w)
+    plan = qm.qm_hpsi_plan_create(w.cell, w.grid, w.k_cart, w.npw, miller, w.nbnd, w.nproj,
+                                  vloc, beta, w.dmat(), 0)
+    del beta, vloc
+    hpsi = torch.empty_like(psi)
+    qm.qm_hpsi_plan_autotune(plan, w.nbnd)
+    out = {"grid": list(w.grid), "nk": w.nk, "nbnd": w.nbnd, "nproj": w.nproj,
+           "npw": [int(w.npw.min()), int(w.npw.max())]}
+    for prec in PREC_CODE:
+        qm.qm_hpsi_plan_set_precision(plan, PREC_CODE[prec])
+        for _ in range(warmup):
+            qm.qm_apply_h(plan, -1, psi, hpsi, w.nbnd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            qm.qm_apply_h(plan, -1, psi, hpsi, w.nbnd)
+        torch.cuda.synchronize()
+        ms_ = 1000.0 * (time.perf_counter() - t0) / steps
+        out[prec] = {"bands_per_s": w.nk * w.nbnd / (ms_ / 1000.0), "ms_per_call": ms_}
+    plan.close()
+    return out
+
+
+def davidson_cpu_baseline(name="c2", tol=1e-8):
+    """The FP64 oracle Davidson (one thread) against the GPU solve from the same start on a
+    cell the oracle finishes in seconds; returns times, iterations and eigenvalue agreement."""
+    import torch
+    from threadpoolctl import threadpool_limits
+    import workload
+    import paper_2308_07277_amd as qm
+    from oracle import davidson as odav, hamiltonian as ham
+    w = workload.make_workload(name)
+    v = w.vloc_r()
+    d = w.dmat()
+    eig_cpu, its, t_cpu = [], [], 0.0
+    with threadpool_limits(1):
+        for ik in range(w.nk):
+            m = w.miller[ik]
+            beta = w.beta(ik)
+            kin = ham.kinetic(w.cell, w.k_cryst[ik], m)
+            h = lambda x, ik=ik, m=m, beta=beta: ham.apply_h_ref(w.cell, w.grid, w.k_cryst[ik], m, v,
+                                                                 beta, d, x)
+            t0 = time.perf_counter()
+            r = odav.davidson_ref(h, w.psi(ik, purpose=2), kin, tol=tol)
+            t_cpu += time.perf_counter() - t0
+            eig_cpu.append(r["eig"])
+            its.append(int(r["iterations"]))
+    plan = _plan_for(w)
+    start = torch.cat([torch.from_numpy(w.psi(ik, purpose=2).reshape(-1)) for ik in range(w.nk)]).cuda()
+    psi = start.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    eig, res, stats, st = qm.qm_davidson_solve(plan, -1, psi, w.nbnd, tol=tol, max_iter=400)
+    torch.cuda.synchronize()
+    t_gpu = time.perf_counter() - t0
+    plan.close()
+    return {"workload": f"{name}: {len(w.atoms)} atoms, {w.nk} k, {w.nbnd} bands, tol {tol:g} Ha",
+            "cpu_oracle_s": t_cpu, "cpu_cores": 1, "cpu_iterations": its, "gpu_s": t_gpu,
+            "gpu_iterations": stats["iterations"], "gpu_status": int(st),
+            "max_abs_eig_diff": float(np.abs(np.array(eig_cpu) - eig).max())}
+
+
+def davidson_run(name, weights=None, tol=1e-8, max_basis_factor=4, switch_resid=1e-3, lanes=3,
+                 only=None):
     """Block Davidson from a seeded random start to max residual <= tol over every k-point
     and band: arm A float64 H + Teter; arm B float32-FFT/bf16-GEMM H while the residual is
     above switch_resid (float64 H below) + the learned preconditioner."""
@@ -203,6 +272,8 @@ def davidson_run(name, weights=None, tol=1e-8, max_basis_factor=4, switch_resid=
                                       switch_resid=0.0)))
         cfgs.append(("mixed+mlp", dict(precond=qm.QM_PRECOND_MLP, mlp_weights=weights,
                                        switch_resid=switch_resid)))
+    if only is not None:
+        cfgs = [c for c in cfgs if c[0] in only]
     for arm, kw in cfgs:
         psi = start.clone()
         torch.cuda.synchronize()
@@ -223,12 +294,16 @@ def davidson_run(name, weights=None, tol=1e-8, max_basis_factor=4, switch_resid=
         if arm != "fp64+teter":
             arms[arm]["max_abs_eig_diff_vs_fp64_teter"] = float(np.abs(eigs[arm] - eigs["fp64+teter"]).max())
     plan.close()
-    return {"workload": f"{name}: {len(w.atoms)}-atom cell, {w.nk} k-points (Gamma + 16), "
+    return {"workload": f"{name}: {len(w.atoms)}-atom cell, {w.nk} k-points, "
                         f"{w.nbnd} bands, tol {tol:g} Ha, max_basis {max_basis_factor} nbnd, "
                         f"k-points in {lanes} concurrent lanes unless the arm says otherwise",
             "arms": arms, "lowest_eig_gamma": float(eigs["fp64+teter"][0][0]),
             "eig_error_bound_note": "every eigenvalue of every arm is within its residual norm "
                                     "(<= tol) of an exact eigenvalue (Krylov-Weinstein)"}
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def main():
@@ -243,6 +318,10 @@ def main():
                     help="also time the FP64 Teter Davidson to 1e-8 Ha on the Gamma + 16 k cell")
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--cpu-sample-bands", type=int, default=160)
+    ap.add_argument("--other-workloads", type=int, default=1,
+                    help="also measure H|psi> bands/s on the 2-, 8- and 216-atom workloads")
+    ap.add_argument("--davidson-c5", type=int, default=0,
+                    help="also time the Davidson on the 216-atom Gamma-point cell (about a minute)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized device buffer (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -343,12 +422,28 @@ def main():
     plan.close()
     del psi, hpsi
     torch.cuda.empty_cache()
+    progress("H|psi> on the 64-atom cell measured")
+    if args.other_workloads:
+        out["hpsi_other_workloads"] = {}
+        for n in ("c1", "c2", "c5"):
+            out["hpsi_other_workloads"][n] = hpsi_rates(n)
+            progress(f"H|psi> on {n} measured")
     if args.davidson:
         weights, tinfo = train_preconditioner()
         out["mlp_training"] = tinfo
+        progress("learned preconditioner trained")
         out["davidson"] = davidson_run("c4", weights=weights)
+        progress("Davidson on the 64-atom cell done")
+        if args.davidson_c5:
+            out["davidson_c5"] = davidson_run("c5", weights=weights, max_basis_factor=3,
+                                              only=("fp64+teter", "mixed+mlp"))
+            progress("Davidson on the 216-atom cell done")
+        if args.cpu_baseline:
+            out["davidson_cpu_baseline"] = davidson_cpu_baseline("c2")
+            progress("Davidson CPU baseline done")
     if args.cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_bands)
+        progress("H|psi> CPU baseline done")
     print(json.dumps(out), flush=True)
 
 
