@@ -37,6 +37,7 @@ struct DavState {
          *yw = nullptr, *fw = nullptr;
   int32_t *unconv = nullptr, *info = nullptr;
   int64_t* goff = nullptr;
+  TrdWork trd{};
   void* work = nullptr;
   int64_t work_bytes = 0;
   double *h_resn = nullptr, *h_theta = nullptr;
@@ -53,7 +54,7 @@ struct DavState {
 static void dav_release(DavState* d) {
   void* dev[] = {d->V, d->HV, d->X, d->HX, d->R, d->TS, d->Hs, d->Aw, d->Z, d->tau, d->Cw, d->G,
                  d->W, d->theta, d->d, d->e, d->resn, d->tkin, d->yw, d->fw, d->unconv, d->info,
-                 d->goff, d->work, d->estar, d->ps.part};
+                 d->goff, d->work, d->estar, d->ps.part, d->trd.v, d->trd.w, d->trd.p, d->trd.cnt};
   for (void* q : dev)
     if (q) (void)hipFree(q);
   void* host[] = {d->h_resn, d->h_theta, d->h_unconv, d->h_info};
@@ -120,6 +121,11 @@ static DavState* dav_create(qm_hpsi_plan* p, int k0, int k1, int nb, int mb, boo
     d->unconv = dalloc<int32_t>(nk * nb);
     d->info = dalloc<int32_t>(nk);
     d->goff = dalloc<int64_t>(nk);
+    QM_REQUIRE(mb <= kTrdMaxBasis, QM_E_ARG, "max_basis above the tridiagonalisation limit (2048)");
+    d->trd.v = dalloc<double2>(nk * 2 * mb);
+    d->trd.w = dalloc<double2>(nk * mb);
+    d->trd.p = dalloc<double2>(nk * mb);
+    d->trd.cnt = dalloc<uint32_t>(nk);
     std::vector<int64_t> go(nk);
     for (size_t k = 0; k < nk; ++k) go[k] = p->kinfo[k].g_off;
     QM_HIP(hipMemcpy(d->goff, go.data(), nk * sizeof(int64_t), hipMemcpyHostToDevice));
@@ -206,6 +212,37 @@ static bool orthonormalise(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipS
   return true;
 }
 
+// Basis size from which the tridiagonalisation runs on many workgroups per k-point (one
+// launch per step) instead of one workgroup per k-point.
+constexpr int kTrdMultiMin = 192;
+
+static void tridiagonalise(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipStream_t s) {
+  int mmax = 0;
+  for (int i = 0; i < jobs.n; ++i) mmax = std::max(mmax, jobs.j[i].m);
+  const bool multi = p->trd_forced == 2 || (p->trd_forced != 1 && mmax >= kTrdMultiMin);
+  if (!multi) {
+    hipLaunchKernelGGL(k_tridiag, dim3(jobs.n), dim3(1024), size_t(5) * d->mb * sizeof(double2), s,
+                       jobs, d->Aw, d->d, d->e, d->tau);
+    QM_HIP(hipGetLastError());
+    return;
+  }
+  hipLaunchKernelGGL(k_trd_start, dim3(jobs.n), dim3(256), 0, s, jobs, d->Aw, d->d, d->e, d->tau,
+                     d->trd);
+  QM_HIP(hipGetLastError());
+  for (int j = 0; j <= mmax - 2; ++j) {
+    int gx = 0;
+    for (int i = 0; i < jobs.n; ++i) {
+      const int m = jobs.j[i].m;
+      if (j >= m - 1) continue;
+      const int nt = (m - 1) / kTrdTile - (j + 1) / kTrdTile + 1;
+      gx = std::max(gx, nt * (nt + 1) / 2);
+    }
+    hipLaunchKernelGGL(k_trd_step, dim3(gx, jobs.n), dim3(256), 0, s, jobs, j, d->Aw, d->d, d->e,
+                       d->tau, d->trd);
+  }
+  QM_HIP(hipGetLastError());
+}
+
 // Projected matrix columns [m_old, m), eigenproblem, Ritz vectors and residuals.
 static void rayleigh_ritz(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipStream_t s) {
   std::vector<GemmCN> cn;
@@ -220,9 +257,7 @@ static void rayleigh_ritz(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipSt
   hipLaunchKernelGGL(k_hs_copy, dim3(64, jobs.n), dim3(256), 0, s, jobs, d->Hs, d->Aw);
   QM_HIP(hipGetLastError());
   QM_HIP(hipEventRecord(d->ev[2], s));
-  hipLaunchKernelGGL(k_tridiag, dim3(jobs.n), dim3(1024), size_t(5) * d->mb * sizeof(double2), s,
-                     jobs, d->Aw, d->d, d->e, d->tau);
-  QM_HIP(hipGetLastError());
+  tridiagonalise(p, d, jobs, s);
   hipLaunchKernelGGL(k_tridiag_eig, dim3(jobs.n), dim3(1024),
                      (size_t(3) * d->mb + size_t(2) * d->nb) * sizeof(double), s,
                      jobs, d->d, d->e, d->theta, d->yw, d->fw);

@@ -19,6 +19,15 @@ struct DJobs {
   DJob j[kMaxSlices];
   int32_t n, nb, mb, pad;
 };
+// Scratch of the many-workgroup tridiagonalisation, per k (mb = basis capacity).
+constexpr int kTrdTile = 64;       // tile edge of a step launch
+constexpr int kTrdMaxBasis = 2048; // rows of a column one 256-thread workgroup holds in registers
+struct TrdWork {
+  double2* v;      // [k][2][mb] reflectors of the current and the previous step (slot j & 1)
+  double2* w;      // [k][mb]    w of the previous step (the pending rank-2 update is v w^H + w v^H)
+  double2* p;      // [k][mb]    accumulator of A v (returned to zero after every step)
+  uint32_t* cnt;   // [k]        workgroups of the current step that have finished
+};
 
 }  // namespace qm
 
@@ -26,6 +35,9 @@ namespace qm {
 __global__ void k_hs_fill(DJobs jobs, double2* Hs);
 __global__ void k_hs_copy(DJobs jobs, const double2* Hs, double2* Aw);
 __global__ void k_tridiag(DJobs jobs, double2* Aw, double* dd, double* ee, double2* tau);
+__global__ void k_trd_start(DJobs jobs, double2* Aw, double* dd, double* ee, double2* tau, TrdWork tw);
+__global__ void k_trd_step(DJobs jobs, int j, double2* Aw, double* dd, double* ee, double2* tau,
+                           TrdWork tw);
 __global__ void k_tridiag_eig(DJobs jobs, const double* dd, const double* ee, double* theta,
                               double* yw, double* fw);
 __global__ void k_backtransform(DJobs jobs, const double2* Aw, const double2* tau, const double* yw,

@@ -262,6 +262,320 @@ __global__ void __launch_bounds__(1024) k_tridiag(DJobs jobs, double2* __restric
   }
 }
 
+// ---------------------------------------------------------------- tridiagonalisation, many CUs
+// The same reduction (same reflectors, same lazy rank-2 update) spread over the whole GPU:
+// one launch per step j, one 256-thread workgroup per 64 x 64 tile of the lower triangle of
+// the trailing block [j+1, m).  A tile applies the pending update of step j-1 to its
+// elements and adds its share of A v_j to a global accumulator p (row part a_rc v_c,
+// column part conj(a_rc) v_r); the workgroup that finishes last (arrival counter) forms
+// p = tau A v and w = p - (tau/2)(p^H v) v, brings column j+1 up to date and builds the
+// next reflector, so the following launch can start at once.  Only the order of the
+// floating-point additions into p differs from the one-workgroup kernel.
+// Cross-workgroup traffic inside a launch is atomics only, so no workgroup needs a memory
+// fence (an agent-scope release writes back the whole L2 and costs ~70 ns per workgroup,
+// serialised): a tile's additions into p return their old values, and its counter increment
+// is issued only once every value is back; the last workgroup reads p with atomic swaps
+// (which also zero it for the next step).  Column j+1 is never stored by the tiles (it is
+// dead after this step): the last workgroup rebuilds it from the values of the previous
+// launch with both pending updates.
+constexpr int kTrdRows = kTrdMaxBasis / 256;   // column rows per tail thread
+
+// v where ok, else 0 (two scalar selects: a select between double2 values can be compiled
+// into a load through a pointer to a zero kept in private memory)
+__device__ __forceinline__ double2 keep(double2 v, bool ok) {
+  return make_double2(ok ? v.x : 0.0, ok ? v.y : 0.0);
+}
+
+// Column jc (rows jc + tid + 256 q in register q, q < kTrdRows) -> d[jc], e[jc], tau[jc] and
+// the reflector v (vout[r], r in (jc, m); stored in A below the subdiagonal too).
+__device__ void trd_reflector(int jc, int m, int mb, double2* A, double2 (&a)[kTrdRows],
+                              double2* vout, double* d, double* e, double2* tk, double* red) {
+  __shared__ double2 s_alpha, s_tau, s_scale;
+  __shared__ double s_dj, s_beta;
+  const int tid = threadIdx.x;
+  double xs = 0.0;
+#pragma unroll
+  for (int q = 0; q < kTrdRows; ++q) {
+    const int r = jc + tid + q * 256;
+    if (r >= m) continue;
+    if (r == jc) s_dj = a[q].x;
+    else if (r == jc + 1) s_alpha = a[q];
+    else xs += a[q].x * a[q].x + a[q].y * a[q].y;
+  }
+  xs = block_sum(xs, red);   // its barriers publish s_dj and s_alpha
+  if (tid == 0) {
+    if (jc == m - 1) {       // last column: no reflector
+      s_tau = make_double2(0.0, 0.0);
+      s_beta = 0.0;
+      s_scale = make_double2(0.0, 0.0);
+    } else {
+      const double2 alpha = s_alpha;
+      if (xs == 0.0 && alpha.y == 0.0) {
+        s_tau = make_double2(0.0, 0.0);
+        s_beta = alpha.x;
+        s_scale = make_double2(0.0, 0.0);
+      } else {
+        double beta = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + xs);
+        if (alpha.x >= 0.0) beta = -beta;
+        s_tau = make_double2((beta - alpha.x) / beta, -alpha.y / beta);
+        const double2 den = make_double2(alpha.x - beta, alpha.y);
+        const double dn = den.x * den.x + den.y * den.y;
+        s_scale = make_double2(den.x / dn, -den.y / dn);
+        s_beta = beta;
+      }
+    }
+    d[jc] = s_dj;
+    e[jc] = s_beta;
+    tk[jc] = s_tau;
+  }
+  __syncthreads();
+  const double2 t = s_tau, sc = s_scale;
+  const bool refl = !(t.x == 0.0 && t.y == 0.0);
+#pragma unroll
+  for (int q = 0; q < kTrdRows; ++q) {
+    const int r = jc + tid + q * 256;
+    if (r <= jc || r >= m) continue;
+    double2 x = make_double2(0.0, 0.0);
+    if (refl) {
+      x = r == jc + 1 ? make_double2(1.0, 0.0) : cmul2(a[q], sc);
+      if (r > jc + 1) A[int64_t(r) * mb + jc] = x;
+    }
+    vout[r] = x;
+  }
+}
+
+// First reflector (column 0) and a zero accumulator; one workgroup per job.
+__global__ void __launch_bounds__(256) k_trd_start(DJobs jobs, double2* __restrict__ Aw,
+                                                   double* __restrict__ dd, double* __restrict__ ee,
+                                                   double2* __restrict__ tau, TrdWork tw) {
+  __shared__ double red[32];
+  const DJob& J = jobs.j[blockIdx.x];
+  const int mb = jobs.mb, m = J.m, k = J.k;
+  double2* A = Aw + int64_t(k) * mb * mb;
+  for (int r = threadIdx.x; r < m; r += 256) tw.p[int64_t(k) * mb + r] = make_double2(0.0, 0.0);
+  if (threadIdx.x == 0) tw.cnt[k] = 0u;
+  double2 a[kTrdRows];
+#pragma unroll
+  for (int q = 0; q < kTrdRows; ++q) {
+    const int r = threadIdx.x + q * 256;
+    a[q] = keep(A[int64_t(min(r, m - 1)) * mb], r < m);
+  }
+  trd_reflector(0, m, mb, A, a, tw.v + int64_t(k) * 2 * mb, dd + int64_t(k) * mb,
+                ee + int64_t(k) * mb, tau + int64_t(k) * mb, red);
+}
+
+// Step j (0 <= j <= m - 2).  Grid (tiles of the largest job, jobs); 256 threads.
+__global__ void __launch_bounds__(256) k_trd_step(DJobs jobs, int j, double2* __restrict__ Aw,
+                                                  double* __restrict__ dd, double* __restrict__ ee,
+                                                  double2* __restrict__ tau, TrdWork tw) {
+  constexpr int T = kTrdTile;
+  __shared__ double2 s_col[4][T];
+  __shared__ double2 s_row[T];
+  __shared__ double2 s_vec[6][T];
+  __shared__ double red[32];
+  __shared__ unsigned s_last;
+  __shared__ double2 s_wj1, s_vj1;
+  const DJob& J = jobs.j[blockIdx.y];
+  const int mb = jobs.mb, m = J.m, k = J.k;
+  if (j >= m - 1) return;
+  const int j1 = j + 1;
+  const int b0 = j1 / T, nt = (m - 1) / T - b0 + 1, ntiles = nt * (nt + 1) / 2;
+  const int t = blockIdx.x;
+  if (t >= ntiles) return;
+  int ti = int((sqrt(8.0 * double(t) + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  while (ti * (ti + 1) / 2 > t) --ti;
+  const int tj = t - ti * (ti + 1) / 2;
+  const int R0 = (b0 + ti) * T, C0 = (b0 + tj) * T;
+  double2* A = Aw + int64_t(k) * mb * mb;
+  const double2* vj = tw.v + (int64_t(k) * 2 + (j & 1)) * mb;        // this step's reflector
+  const double2* vp = tw.v + (int64_t(k) * 2 + ((j + 1) & 1)) * mb;  // pending: v_{j-1}
+  double2* W = tw.w + int64_t(k) * mb;                                // pending: w_{j-1}
+  double2* P = tw.p + int64_t(k) * mb;
+  const bool pend = j > 0;
+  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15, lane = tid & 63, wave = tid >> 6;
+  const double2 z = make_double2(0.0, 0.0);
+  // Every load reads an in-bounds address (indices clamped to m - 1) and masked values are
+  // replaced afterwards: a conditional load would be compiled into a load through a
+  // selected pointer (flat addressing, split, serialised waits).
+  // The tile's slices of v_j, v_{j-1}, w_{j-1} (rows and columns) go through LDS, one load
+  // per entry; the tile itself is loaded at the same time.  Every load reads an in-bounds
+  // address (indices clamped to m - 1) and masked values are replaced afterwards: a
+  // conditional load would be compiled into a load through a selected pointer.
+  double2 a[4][4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int rc = min(R0 + 4 * tr + q, m - 1);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[q][u] = A[int64_t(rc) * mb + min(C0 + 4 * tc + u, rc)];
+  }
+  {
+    const int wv = __builtin_amdgcn_readfirstlane(wave), i = lane;
+    const int r = R0 + i, c = C0 + i, rr = min(r, m - 1), cc = min(c, m - 1);
+    const bool okr = r >= j1 && r < m, okc = c >= j1 && c < m;
+    if (wv == 0) {          // wave 0: v_j rows, v_{j-1} columns
+      const double2 x = vj[rr], y = vp[cc];
+      s_vec[0][i] = keep(x, okr);
+      s_vec[4][i] = keep(y, okc && pend);
+    } else if (wv == 1) {   // wave 1: v_{j-1} rows, w_{j-1} columns
+      const double2 x = vp[rr], y = W[cc];
+      s_vec[1][i] = keep(x, okr && pend);
+      s_vec[5][i] = keep(y, okc && pend);
+    } else if (wv == 2) {   // wave 2: w_{j-1} rows
+      const double2 x = W[rr];
+      s_vec[2][i] = keep(x, okr && pend);
+    } else {                // wave 3: v_j columns
+      const double2 x = vj[cc];
+      s_vec[3][i] = keep(x, okc);
+    }
+  }
+  __syncthreads();
+  double2 vr[4], vpr[4], wpr[4], vc[4], vpc[4], wpc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    vr[q] = s_vec[0][4 * tr + q];
+    vpr[q] = s_vec[1][4 * tr + q];
+    wpr[q] = s_vec[2][4 * tr + q];
+    vc[q] = s_vec[3][4 * tc + q];
+    vpc[q] = s_vec[4][4 * tc + q];
+    wpc[q] = s_vec[5][4 * tc + q];
+  }
+  double2 racc[4], cacc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) racc[q] = cacc[q] = z;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int r = R0 + 4 * tr + q;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int c = C0 + 4 * tc + u;
+      if (!(r < m && c >= j1 && c <= r)) continue;
+      double2 x = a[q][u];
+      if (pend) {
+        x = csub2(x, cmul2(vpr[q], cconj(wpc[u])));
+        x = csub2(x, cmul2(wpr[q], cconj(vpc[u])));
+        if (c != j1) A[int64_t(r) * mb + c] = x;
+      }
+      racc[q] = cadd2(racc[q], cmul2(x, vc[u]));
+      if (c < r) cacc[u] = cadd2(cacc[u], cmul2(cconj(x), vr[q]));
+    }
+  }
+  // row parts summed over the 16 column groups (lane bits 0-3), column parts over the 16 row
+  // groups (lane bits 4-5, then the four waves); then one round of additions into p, 64 row
+  // and 64 column entries.  chk collects the values the additions return, so a thread
+  // cannot pass the barrier below before its additions are done.
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    for (int o = 1; o < 16; o <<= 1) {
+      racc[q].x += __shfl_xor(racc[q].x, o, 64);
+      racc[q].y += __shfl_xor(racc[q].y, o, 64);
+    }
+    for (int o = 16; o < 64; o <<= 1) {
+      cacc[q].x += __shfl_xor(cacc[q].x, o, 64);
+      cacc[q].y += __shfl_xor(cacc[q].y, o, 64);
+    }
+    if (tc == 0) s_row[4 * tr + q] = racc[q];
+    if (lane < 16) s_col[wave][4 * tc + q] = cacc[q];
+  }
+  __syncthreads();
+  double chk = 0.0;
+  if (tid < T) {
+    const int r = R0 + tid;
+    if (r >= j1 && r < m) {
+      chk += atomicAdd(&P[r].x, s_row[tid].x);
+      chk += atomicAdd(&P[r].y, s_row[tid].y);
+    }
+  } else if (tid < 2 * T) {
+    const int i = tid - T, c = C0 + i;
+    if (c >= j1 && c < m && c < R0 + T - 1) {
+      const double2 s = cadd2(cadd2(s_col[0][i], s_col[1][i]), cadd2(s_col[2][i], s_col[3][i]));
+      chk += atomicAdd(&P[c].x, s.x);
+      chk += atomicAdd(&P[c].y, s.y);
+    }
+  }
+  // the last workgroup of this job to finish carries on
+  if (chk == 1.0e300) s_last = 2u;   // never true; makes the thread wait for its additions
+  __syncthreads();
+  if (tid == 0) s_last = atomicAdd(&tw.cnt[k], 1u) == unsigned(ntiles - 1) ? 1u : 0u;
+  __syncthreads();
+  if (s_last != 1u) return;
+  double* d = dd + int64_t(k) * mb;
+  double* e = ee + int64_t(k) * mb;
+  double2* tk = tau + int64_t(k) * mb;
+  const double2 tj_ = tk[j];
+  // column j+1 as the previous launch left it, with the update of step j-1 applied; every
+  // independent load is issued before the swaps that read p
+  const double2 wpj1c = keep(cconj(W[j1]), pend), vpj1c = keep(cconj(vp[j1]), pend);
+  double2 pq[kTrdRows], vq[kTrdRows], col[kTrdRows], vpq[kTrdRows], wpq[kTrdRows];
+#pragma unroll
+  for (int q = 0; q < kTrdRows; ++q) {
+    const int rc = min(j1 + tid + q * 256, m - 1);
+    col[q] = A[int64_t(rc) * mb + j1];
+    vq[q] = vj[rc];
+    vpq[q] = vp[rc];
+    wpq[q] = W[rc];
+  }
+#pragma unroll
+  for (int q = 0; q < kTrdRows; ++q) {
+    const int r = j1 + tid + q * 256;
+    pq[q] = z;
+    if (r < m) {
+      unsigned long long* pr = reinterpret_cast<unsigned long long*>(&P[r]);
+      pq[q].x = __longlong_as_double(static_cast<long long>(atomicExch(pr, 0ull)));
+      pq[q].y = __longlong_as_double(static_cast<long long>(atomicExch(pr + 1, 0ull)));
+    }
+  }
+  double sr = 0.0, si = 0.0;
+#pragma unroll
+  for (int q = 0; q < kTrdRows; ++q) {
+    const bool ok = j1 + tid + q * 256 < m;
+    col[q] = keep(col[q], ok);
+    vq[q] = keep(vq[q], ok);
+    vpq[q] = keep(vpq[q], ok && pend);
+    wpq[q] = keep(wpq[q], ok && pend);
+    col[q] = csub2(col[q], cmul2(vpq[q], wpj1c));
+    col[q] = csub2(col[q], cmul2(wpq[q], vpj1c));
+    pq[q] = cmul2(tj_, pq[q]);
+    sr += pq[q].x * vq[q].x + pq[q].y * vq[q].y;
+    si += pq[q].x * vq[q].y - pq[q].y * vq[q].x;
+  }
+  block_sum2(sr, si, red);   // its barriers also separate the reads of W above from the writes below
+  const double2 aw = cmul2(make_double2(-0.5 * tj_.x, -0.5 * tj_.y), make_double2(sr, si));
+#pragma unroll
+  for (int q = 0; q < kTrdRows; ++q) {
+    const int r = j1 + tid + q * 256;
+    if (r < m) {
+      pq[q] = cadd2(pq[q], cmul2(aw, vq[q]));   // w_j
+      W[r] = pq[q];
+      if (r == j1) {
+        s_wj1 = pq[q];
+        s_vj1 = vq[q];
+      }
+    }
+  }
+  __syncthreads();
+  if (tid == 0) tw.cnt[k] = 0u;
+  if (j == m - 2) {   // only the last diagonal element is left: apply the update of step j
+    if (tid == 0) {
+      d[m - 1] = col[0].x - 2.0 * (s_vj1.x * s_wj1.x + s_vj1.y * s_wj1.y);
+      e[m - 1] = 0.0;
+      tk[m - 1] = z;
+    }
+    return;
+  }
+  // column j+1, rows [j+1, m), with the update of step j applied
+  const double2 wj1c = cconj(s_wj1), vj1c = cconj(s_vj1);
+#pragma unroll
+  for (int q = 0; q < kTrdRows; ++q) {
+    const int r = j1 + tid + q * 256;
+    if (r < m) {
+      col[q] = csub2(col[q], cmul2(vq[q], wj1c));
+      col[q] = csub2(col[q], cmul2(pq[q], vj1c));
+    }
+  }
+  trd_reflector(j1, m, mb, A, col, tw.v + (int64_t(k) * 2 + (j1 & 1)) * mb, d, e, tk, red);
+}
+
 // ---------------------------------------------------------------- tridiagonal eigenpairs
 // Number of eigenvalues of the tridiagonal (diagonal d, squared off-diagonal e2) below x.
 __device__ int sturm_count(const double* d, const double* e2, int m, double x, double pivmin) {

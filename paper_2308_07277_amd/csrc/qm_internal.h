@@ -137,6 +137,9 @@ struct qm_hpsi_plan {
   // autotuner.  xy_forced (environment QM_XY_MODE = 1 or 2) overrides both.
   int32_t xy_variant[2] = {0, 0};
   int32_t xy_forced = 0;
+  // Davidson tridiagonalisation: 1 one workgroup per k-point, 2 many workgroups per k-point
+  // (one launch per step), 0 chosen by basis size (environment QM_TRIDIAG_MODE).
+  int32_t trd_forced = 0;
 };
 
 namespace qm {

@@ -188,3 +188,26 @@ def test_lanes_with_precision_ladder():
     assert st1 == 0 and st4 == 0 and r4.max() <= 1e-8
     assert s4["n_hpsi_bands_lowp"] > 0
     assert np.abs(e1 - e4).max() <= 1e-10
+
+
+@pytest.mark.parametrize("mode", ["1", "2"])
+def test_tridiagonalisation_paths(mode, monkeypatch):
+    """QM_TRIDIAG_MODE=1 reduces the projected matrix in one workgroup per k-point; 2 uses one
+    launch per Householder step over 64 x 64 tiles of the trailing block, the last workgroup
+    of each step building the next reflector (the default from a basis of 192 columns).  Both
+    must reach the dense-matrix eigenvalues within 1e-8 Ha on the 8-atom cells (bases of 8-32
+    and 32-128 columns: one to two tile rows with ragged edges, four k-points in one launch)."""
+    monkeypatch.setenv("QM_TRIDIAG_MODE", mode)
+    for name in ("c1", "c2"):
+        w = workload.make_workload(name)
+        plan, a = make_plan(w, w.nbnd)
+        eig, res, stats, st, x = _solve(plan, w, w.nbnd, _start(w, w.nbnd), tol=1e-9,
+                                        max_basis=4 * w.nbnd)
+        print(name, "mode", mode, stats)
+        assert st == 0 and stats["converged"] == 1
+        for ik in range(w.nk):
+            h, beta = _oracle_h(w, a, ik)
+            dense = ham.dense_h(w.cell, w.grid, w.k_cryst[ik], w.miller[ik], a["vloc"], beta,
+                                a["dmat"])
+            lam = np.linalg.eigvalsh(dense)[:w.nbnd]
+            assert np.abs(eig[ik] - lam).max() <= 1e-8
