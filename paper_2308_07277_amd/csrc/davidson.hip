@@ -38,6 +38,7 @@ struct DavState {
   int32_t *unconv = nullptr, *info = nullptr;
   int64_t* goff = nullptr;
   TrdWork trd{};
+  EigWork ew{};
   void* work = nullptr;
   int64_t work_bytes = 0;
   double *h_resn = nullptr, *h_theta = nullptr;
@@ -54,7 +55,7 @@ struct DavState {
 static void dav_release(DavState* d) {
   void* dev[] = {d->V, d->HV, d->X, d->HX, d->R, d->TS, d->Hs, d->Aw, d->Z, d->tau, d->Cw, d->G,
                  d->W, d->theta, d->d, d->e, d->resn, d->tkin, d->yw, d->fw, d->unconv, d->info,
-                 d->goff, d->work, d->estar, d->ps.part, d->trd.v, d->trd.w, d->trd.p, d->trd.cnt};
+                 d->goff, d->work, d->estar, d->ps.part, d->trd.v, d->trd.w, d->trd.p, d->trd.cnt, d->ew.sc, d->ew.nrm};
   for (void* q : dev)
     if (q) (void)hipFree(q);
   void* host[] = {d->h_resn, d->h_theta, d->h_unconv, d->h_info};
@@ -126,6 +127,8 @@ static DavState* dav_create(qm_hpsi_plan* p, int k0, int k1, int nb, int mb, boo
     d->trd.w = dalloc<double2>(nk * mb);
     d->trd.p = dalloc<double2>(nk * mb);
     d->trd.cnt = dalloc<uint32_t>(nk);
+    d->ew.sc = dalloc<double>(nk * nb);
+    d->ew.nrm = dalloc<double>(nk);
     std::vector<int64_t> go(nk);
     for (size_t k = 0; k < nk; ++k) go[k] = p->kinfo[k].g_off;
     QM_HIP(hipMemcpy(d->goff, go.data(), nk * sizeof(int64_t), hipMemcpyHostToDevice));
@@ -136,7 +139,7 @@ static DavState* dav_create(qm_hpsi_plan* p, int k0, int k1, int nb, int mb, boo
     QM_HIP(hipHostMalloc(reinterpret_cast<void**>(&d->h_unconv), nk * nb * sizeof(int32_t)));
     QM_HIP(hipHostMalloc(reinterpret_cast<void**>(&d->h_info), nk * sizeof(int32_t)));
     for (hipEvent_t& e : d->ev) QM_HIP(hipEventCreate(&e));
-    const void* big[] = {reinterpret_cast<const void*>(&k_tridiag), reinterpret_cast<const void*>(&k_tridiag_eig),
+    const void* big[] = {reinterpret_cast<const void*>(&k_tridiag), reinterpret_cast<const void*>(&k_eig_vals),
                          reinterpret_cast<const void*>(&k_backtransform)};
     for (const void* f : big) QM_HIP(allow_full_lds(f));
     d->m.assign(nk, 0);
@@ -258,15 +261,24 @@ static void rayleigh_ritz(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipSt
   QM_HIP(hipGetLastError());
   QM_HIP(hipEventRecord(d->ev[2], s));
   tridiagonalise(p, d, jobs, s);
-  hipLaunchKernelGGL(k_tridiag_eig, dim3(jobs.n), dim3(1024),
-                     (size_t(3) * d->mb + size_t(2) * d->nb) * sizeof(double), s,
-                     jobs, d->d, d->e, d->theta, d->yw, d->fw);
+  int mmax = 0;
+  for (int i = 0; i < jobs.n; ++i) mmax = std::max(mmax, jobs.j[i].m);
+  const int nw = std::min(d->nb, mmax);
+  hipLaunchKernelGGL(k_eig_vals, dim3((nw + 3) / 4, jobs.n), dim3(256), size_t(3) * d->mb * sizeof(double),
+                     s, jobs, d->d, d->e, d->theta, d->ew);
+  QM_HIP(hipGetLastError());
+  for (int step = 0; step < 3; ++step) {   // inverse iteration, clusters re-orthogonalised
+    hipLaunchKernelGGL(k_eig_inviter, dim3((nw + 63) / 64, jobs.n), dim3(64),
+                       size_t(2) * d->mb * sizeof(double), s, jobs, d->d, d->e, d->theta, d->yw,
+                       d->fw, d->ew, step);
+    hipLaunchKernelGGL(k_eig_orth, dim3(nw, jobs.n), dim3(256), 0, s, jobs, d->theta, d->yw, d->ew);
+  }
   QM_HIP(hipGetLastError());
   // Z slice + one reflector must fit in the 160 KiB of LDS
   const int cols = std::max(1, std::min(8, int((160 * 1024 - 1024) / (16 * int64_t(d->mb))) - 1));
   hipLaunchKernelGGL(k_backtransform, dim3((d->nb + cols - 1) / cols, jobs.n), dim3(256),
-                     size_t(d->mb) * (cols + 1) * sizeof(double2), s, jobs, d->Aw, d->tau, d->yw, d->Z,
-                     cols);
+                     size_t(d->mb) * (cols + 1) * sizeof(double2), s, jobs, d->Aw, d->tau, d->yw,
+                     d->ew.sc, d->Z, cols);
   QM_HIP(hipGetLastError());
   QM_HIP(hipEventRecord(d->ev[3], s));
   std::vector<GemmEX> ex;

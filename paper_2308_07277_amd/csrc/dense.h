@@ -29,6 +29,12 @@ struct TrdWork {
   uint32_t* cnt;   // [k]        workgroups of the current step that have finished
 };
 
+// Scratch of the tridiagonal eigensolver, per k.
+struct EigWork {
+  double* sc;    // [k][nb] scale of each stored eigenvector (true vector = Y[.][n] * sc[n])
+  double* nrm;   // [k]     norm estimate of the tridiagonal
+};
+
 }  // namespace qm
 
 namespace qm {
@@ -38,10 +44,12 @@ __global__ void k_tridiag(DJobs jobs, double2* Aw, double* dd, double* ee, doubl
 __global__ void k_trd_start(DJobs jobs, double2* Aw, double* dd, double* ee, double2* tau, TrdWork tw);
 __global__ void k_trd_step(DJobs jobs, int j, double2* Aw, double* dd, double* ee, double2* tau,
                            TrdWork tw);
-__global__ void k_tridiag_eig(DJobs jobs, const double* dd, const double* ee, double* theta,
-                              double* yw, double* fw);
+__global__ void k_eig_vals(DJobs jobs, const double* dd, const double* ee, double* theta, EigWork ew);
+__global__ void k_eig_inviter(DJobs jobs, const double* dd, const double* ee, const double* theta,
+                              double* yw, double* fw, EigWork ew, int step);
+__global__ void k_eig_orth(DJobs jobs, const double* theta, double* yw, EigWork ew);
 __global__ void k_backtransform(DJobs jobs, const double2* Aw, const double2* tau, const double* yw,
-                                double2* Zout, int cols);
+                                const double* scw, double2* Zout, int cols);
 __global__ void k_chol_inv(DJobs jobs, double2* Gm, double2* Wm, int32_t* info);
 __global__ void k_residual(DJobs jobs, const double2* X, const double2* HX, double2* Rr,
                            const double* theta, const double* kin_all, const int64_t* goff,

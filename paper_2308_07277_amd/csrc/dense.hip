@@ -4,10 +4,13 @@
 //   k_tridiag     Householder reduction of the complex Hermitian projected matrix
 //                 to a real symmetric tridiagonal one (H = I - tau v v^H, with the
 //                 reflector chosen so the off-diagonal comes out real)
-//   k_tridiag_eig lowest nb eigenvalues by Sturm-count bisection, eigenvectors by
-//                 inverse iteration (re-orthogonalised inside clusters of close
-//                 eigenvalues, so degenerate levels get orthonormal vectors), then
-//                 back-transformed through the reflectors
+//   k_trd_start/k_trd_step  the same reduction spread over many workgroups, one
+//                 launch per step (used from a basis of a few hundred columns)
+//   k_eig_vals, k_eig_inviter, k_eig_orth  lowest nb eigenvalues by Sturm-count
+//                 multisection, eigenvectors by inverse iteration (re-orthogonalised
+//                 inside clusters of close eigenvalues, so degenerate levels get
+//                 orthonormal vectors)
+//   k_backtransform  eigenvectors back through the reflectors
 //   k_chol_inv    Cholesky G = L L^H of a Gram matrix and W = conj(L^-1)^T for the
 //                 CholQR update T <- L^-1 T
 //   k_residual    r = HX - theta X, ||r||, band kinetic energy <x|T|x>
@@ -577,6 +580,30 @@ __global__ void __launch_bounds__(256) k_trd_step(DJobs jobs, int j, double2* __
 }
 
 // ---------------------------------------------------------------- tridiagonal eigenpairs
+// Lowest nwant = min(nb, m) eigenpairs of the real symmetric tridiagonal (d, e), spread over
+// the GPU in three kernels:
+//   k_eig_vals     eigenvalues: one wave per eigenvalue, 64-section on Sturm counts (the 64
+//                  lanes cut the bracket into 65 parts per round)
+//   k_eig_inviter  one step of inverse iteration, one lane per eigenvector (64 per
+//                  workgroup); vectors are stored unnormalised with their scale 1/||y||
+//   k_eig_orth     one workgroup per cluster of close eigenvalues (gap <= ortol): block
+//                  classical Gram-Schmidt, twice, then unit norm, so that degenerate levels
+//                  get orthonormal vectors
+// The host runs k_eig_vals once and (k_eig_inviter, k_eig_orth) three times.
+// Y[k][i][n] (n fastest: the lanes of an inverse-iteration wave touch consecutive addresses),
+// true vector n = Y[.][n] * sc[k][n].
+
+// 1/q from the hardware reciprocal refined by two Newton steps (relative error of a few
+// ulps): a Sturm count tolerates that as a relative perturbation of e^2 of the same size,
+// and it is half the dependent chain of a correctly rounded division.
+__device__ __forceinline__ double rcp_nr(double q) {
+  double r = __builtin_amdgcn_rcp(q);
+  double t = fma(-q, r, 1.0);
+  r = fma(r, t, r);
+  t = fma(-q, r, 1.0);
+  return fma(r, t, r);
+}
+
 // Number of eigenvalues of the tridiagonal (diagonal d, squared off-diagonal e2) below x.
 __device__ int sturm_count(const double* d, const double* e2, int m, double x, double pivmin) {
   int c = 0;
@@ -584,7 +611,7 @@ __device__ int sturm_count(const double* d, const double* e2, int m, double x, d
   if (fabs(q) < pivmin) q = -pivmin;
   c += q < 0.0;
   for (int i = 1; i < m; ++i) {
-    q = (d[i] - x) - e2[i - 1] / q;
+    q = (d[i] - x) - e2[i - 1] * rcp_nr(q);
     if (fabs(q) < pivmin) q = -pivmin;
     c += q < 0.0;
   }
@@ -607,248 +634,316 @@ __device__ __forceinline__ double wave_sum_all(double v) {
   return v;
 }
 
-// theta[k][0..nb) ascending and real eigenvectors Y[k][i][n] of the tridiagonal (i < m,
-// n < nb; n fastest, so lanes working on consecutive eigenvectors touch consecutive
-// addresses).  fw: [k][3][mb][nb] upper factor (diagonal, two superdiagonals) of the
-// pivoted LU of T - lambda_n I, same interleaving.
-//   1. Eigenvalues: multisection on Sturm counts.  S lanes of a wave share one
-//      eigenvalue; each round their S points cut the bracket into S + 1 parts.
-//   2. Eigenvectors: three steps of inverse iteration, one lane per eigenvalue.  The
-//      sweep that eliminates the right-hand side also recomputes the LU factors (from
-//      d and e in LDS), so it never reads what it has written; the back substitution
-//      prefetches a block of rows ahead.  Eigenvalues closer than ortol form clusters
-//      whose vectors are re-orthogonalised (modified Gram-Schmidt, one wave per cluster)
-//      after every step, which gives degenerate levels orthonormal vectors.
-constexpr int kInvBlk = 8;  // rows prefetched ahead in the forward sweep
-constexpr int kBwdBlk = 4;  // and in the back substitution (four streams)
-__global__ void __launch_bounds__(1024) k_tridiag_eig(DJobs jobs, const double* __restrict__ dd,
-                                                      const double* __restrict__ ee,
-                                                      double* __restrict__ theta,
-                                                      double* __restrict__ yw,
-                                                      double* __restrict__ fw) {
-  extern __shared__ double sde[];  // d [mb], e [mb], e^2 [mb], eigenvalues [nb], shifts [nb]
-  const DJob& J = jobs.j[blockIdx.x];
-  const int mb = jobs.mb, nb = jobs.nb, m = J.m;
+constexpr double kEps = 2.220446049250313e-16;
+
+// Gershgorin interval and the norm estimate max_i |d_i| + |e_{i-1}| + |e_i| of (d, e) in LDS,
+// identical on every thread of the block.
+__device__ void gershgorin(const double* sd, const double* se, int m, double* red, double& lo,
+                           double& hi, double& nrm) {
+  double l = 1e300, h = -1e300, nr = 0.0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const double r = (i > 0 ? fabs(se[i - 1]) : 0.0) + (i < m - 1 ? fabs(se[i]) : 0.0);
+    l = fmin(l, sd[i] - r);
+    h = fmax(h, sd[i] + r);
+    nr = fmax(nr, fabs(sd[i]) + r);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    l = fmin(l, __shfl_xor(l, o, 64));
+    h = fmax(h, __shfl_xor(h, o, 64));
+    nr = fmax(nr, __shfl_xor(nr, o, 64));
+  }
+  const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[w] = l;
+    red[nw + w] = h;
+    red[2 * nw + w] = nr;
+  }
+  __syncthreads();
+  lo = red[0];
+  hi = red[nw];
+  nrm = red[2 * nw];
+  for (int i = 1; i < nw; ++i) {
+    lo = fmin(lo, red[i]);
+    hi = fmax(hi, red[nw + i]);
+    nrm = fmax(nrm, red[2 * nw + i]);
+  }
+  nrm = fmax(nrm, 1e-300);
+  __syncthreads();
+}
+
+// Grid (ceil(nwant / 4), jobs), 256 threads: wave w finds eigenvalue 4 blockIdx.x + w.
+__global__ void __launch_bounds__(256) k_eig_vals(DJobs jobs, const double* __restrict__ dd,
+                                                  const double* __restrict__ ee,
+                                                  double* __restrict__ theta, EigWork ew) {
+  extern __shared__ double sde[];  // d [mb], e [mb], e^2 [mb]
+  __shared__ double red[12];
+  const DJob& J = jobs.j[blockIdx.y];
+  const int mb = jobs.mb, m = J.m, k = J.k, nwant = min(jobs.nb, m);
+  if (blockIdx.x * 4 >= nwant) return;
   double* sd = sde;
   double* se = sd + mb;
   double* se2 = se + mb;
-  double* sth = se2 + mb;
-  double* slam = sth + nb;
-  double* th = theta + int64_t(J.k) * mb;
-  double* Y = yw + int64_t(J.k) * nb * mb;
-  double* FD = fw + int64_t(J.k) * nb * 3 * mb;
-  double* FU1 = FD + int64_t(mb) * nb;
-  double* FU2 = FU1 + int64_t(mb) * nb;
-  __shared__ double s_lo, s_hi, s_norm;
-  __shared__ int s_cl[1025];
-  __shared__ int s_ncl;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nwaves = blockDim.x >> 6;
-  for (int i = tid; i < m; i += blockDim.x) {
-    const double ev = ee[int64_t(J.k) * mb + i];
-    sd[i] = dd[int64_t(J.k) * mb + i];
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const double ev = ee[int64_t(k) * mb + i];
+    sd[i] = dd[int64_t(k) * mb + i];
     se[i] = ev;
     se2[i] = ev * ev;
   }
   __syncthreads();
-  const int nwant = min(nb, m);
-  if (wave == 0) {  // Gershgorin bounds and a norm estimate
-    double lo = 1e300, hi = -1e300, nr = 0.0;
-    for (int i = lane; i < m; i += 64) {
-      const double r = (i > 0 ? fabs(se[i - 1]) : 0.0) + (i < m - 1 ? fabs(se[i]) : 0.0);
-      lo = fmin(lo, sd[i] - r);
-      hi = fmax(hi, sd[i] + r);
-      nr = fmax(nr, fabs(sd[i]) + r);
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      lo = fmin(lo, __shfl_xor(lo, o, 64));
-      hi = fmax(hi, __shfl_xor(hi, o, 64));
-      nr = fmax(nr, __shfl_xor(nr, o, 64));
-    }
-    if (lane == 0) {
-      s_lo = lo;
-      s_hi = hi;
-      s_norm = fmax(nr, 1e-300);
-    }
+  double glo, ghi, nrm;
+  gershgorin(sd, se, m, red, glo, ghi, nrm);
+  if (blockIdx.x == 0 && threadIdx.x == 0) ew.nrm[k] = nrm;
+  const int lane = threadIdx.x & 63, n = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (n >= nwant) return;
+  const double pivmin = fmax(1e-290, kEps * kEps * nrm * nrm * 1e-6);
+  const double atol = 1e-3 * kEps * nrm;
+  double lo = glo - 4 * kEps * nrm, hi = ghi + 4 * kEps * nrm;
+  for (int it = 0; it < 64; ++it) {
+    if (hi - lo <= fmax(2.0 * kEps * fmax(fabs(lo), fabs(hi)), atol)) break;
+    const double w = (hi - lo) / 65.0;
+    const bool below = sturm_count(sd, se2, m, lo + w * double(lane + 1), pivmin) <= n;
+    // the lanes whose point lies at or below lambda_n form a prefix
+    const int j = __popcll(__ballot(below));
+    const double nlo = j == 0 ? lo : lo + w * double(j);
+    const double nhi = j == 64 ? hi : lo + w * double(j + 1);
+    if (nlo == lo && nhi == hi) break;
+    lo = nlo;
+    hi = nhi;
+  }
+  if (lane == 0) theta[int64_t(k) * mb + n] = 0.5 * (lo + hi);
+}
+
+// Inverse-iteration shift of eigenvalue n: inside a cluster (gaps <= ortol) the shifts are
+// nudged apart by 10 eps ||T|| so that no two coincide.
+__device__ double inviter_shift(const double* th, int n, double ortol, double tiny) {
+  int n0 = n;
+  while (n0 > 0 && th[n0] - th[n0 - 1] <= ortol) --n0;
+  double prev = th[n0];
+  for (int t = n0 + 1; t <= n; ++t) {
+    const double x = th[t];
+    prev = x - prev < 10.0 * tiny ? prev + 10.0 * tiny : x;
+  }
+  return prev;
+}
+
+constexpr int kInvBlk = 8;   // rows whose right-hand side is loaded ahead in the forward sweep
+constexpr int kBwdBlk = 8;   // and whose factors are loaded ahead in the back substitution
+
+// One inverse-iteration step (T - lambda_n I) y_new = y for 64 eigenvectors per workgroup
+// (one lane each; grid (ceil(nwant / 64), jobs)).  The sweep that eliminates the right-hand
+// side (partial pivoting) also produces the factors, so it never reads what it writes; it
+// stores 1/pivot so the back substitution only multiplies.  fw: [k][3][mb][nb] (1/pivot and
+// the two superdiagonals of U), same interleaving as Y.
+__global__ void __launch_bounds__(64) k_eig_inviter(DJobs jobs, const double* __restrict__ dd,
+                                                    const double* __restrict__ ee,
+                                                    const double* __restrict__ theta,
+                                                    double* __restrict__ yw, double* __restrict__ fw,
+                                                    EigWork ew, int step) {
+  extern __shared__ double sde[];  // d [mb], e [mb]
+  const DJob& J = jobs.j[blockIdx.y];
+  const int mb = jobs.mb, nb = jobs.nb, m = J.m, k = J.k, nwant = min(nb, m);
+  if (blockIdx.x * 64 >= nwant) return;
+  double* sd = sde;
+  double* se = sd + mb;
+  for (int i = threadIdx.x; i < m; i += 64) {
+    sd[i] = dd[int64_t(k) * mb + i];
+    se[i] = ee[int64_t(k) * mb + i];
   }
   __syncthreads();
-  const double eps = 2.220446049250313e-16;
-  const double nrm = s_norm;
-  const double pivmin = fmax(1e-290, eps * eps * nrm * nrm * 1e-6);
-  const double atol = 1e-3 * eps * nrm;
-  // 1. multisection: S in {1, 2, 4, 8, 16} lanes per eigenvalue, groups never straddle waves
-  int S = 1;
-  while (S < 16 && nwant * S * 2 <= int(blockDim.x)) S *= 2;
-  const int ngroups = int(blockDim.x) / S, sl = tid % S;
-  const uint64_t gmask = (S == 64 ? ~0ull : ((1ull << S) - 1)) << ((lane / S) * S);
-  for (int n = tid / S; n < nwant; n += ngroups) {
-    double lo = s_lo - 4 * eps * nrm, hi = s_hi + 4 * eps * nrm;
-    for (int it = 0; it < 256; ++it) {
-      if (hi - lo <= fmax(2.0 * eps * fmax(fabs(lo), fabs(hi)), atol)) break;
-      const double w = (hi - lo) / double(S + 1);
-      const bool below = sturm_count(sd, se2, m, lo + w * double(sl + 1), pivmin) <= n;
-      // the lanes of this group whose point lies at or below lambda_n form a prefix
-      const int j = __popcll(__ballot(below) & gmask);
-      const double nlo = j == 0 ? lo : lo + w * double(j);
-      const double nhi = j == S ? hi : lo + w * double(j + 1);
-      if (nlo == lo && nhi == hi) break;
-      lo = nlo;
-      hi = nhi;
-    }
-    if (sl == 0) {
-      const double t = 0.5 * (lo + hi);
-      th[n] = t;
-      sth[n] = t;
-    }
-  }
-  __syncthreads();
-  // clusters (gap > ortol starts a new one) and shifts nudged apart inside a cluster
-  const double ortol = 1e-5 * nrm;  // inter-cluster orthogonality ~ eps / 1e-5
-  const double tiny = eps * nrm;
-  if (tid == 0) {
-    int nc = 0;
-    s_cl[nc++] = 0;
-    double prev = sth[0];
-    slam[0] = prev;
-    for (int n = 1; n < nwant; ++n) {
-      const double t = sth[n];
-      if (t - sth[n - 1] > ortol && nc < 1024) {
-        s_cl[nc++] = n;
-        prev = t;
-      } else {
-        prev = t - prev < 10.0 * tiny ? prev + 10.0 * tiny : t;
-      }
-      slam[n] = prev;
-    }
-    s_cl[nc] = nwant;
-    s_ncl = nc;
-  }
-  __syncthreads();
+  const int n = blockIdx.x * 64 + threadIdx.x;
+  if (n >= nwant) return;
+  const double nrm = ew.nrm[k];
+  const double tiny = kEps * nrm, ortol = 1e-5 * nrm;
+  const double* th = theta + int64_t(k) * mb;
+  const double lam = inviter_shift(th, n, ortol, tiny);
   const int64_t st = nb;  // stride between consecutive elements of one vector
-  for (int step = 0; step < 3; ++step) {
-    for (int n = tid; n < nwant; n += blockDim.x) {
-      const double lam = slam[n];
-      double* y = Y + n;
-      double* D = FD + n;
-      double* U1 = FU1 + n;
-      double* U2 = FU2 + n;
-      // forward sweep: row i of the LU (partial pivoting) of T - lam I and of the
-      // eliminated right-hand side; b is the previous iterate (start vector at step 0)
-      double dcur = sd[0] - lam, u1 = m > 1 ? se[0] : 0.0;
-      double bcur = step == 0 ? inviter_start(0, n) : y[0];
-      double bq[kInvBlk];
+  double* y = yw + int64_t(k) * nb * mb + n;
+  double* RD = fw + int64_t(k) * nb * 3 * mb + n;
+  double* U1 = RD + int64_t(mb) * nb;
+  double* U2 = U1 + int64_t(mb) * nb;
+  double* scp = ew.sc + int64_t(k) * nb + n;
+  const double s_in = step == 0 ? 1.0 : *scp;
+  auto rhs = [&](int r) {
+    if (r >= m) return 0.0;
+    return step == 0 ? inviter_start(r, n) : y[r * st] * s_in;
+  };
+  auto safe = [&](double p) { return fabs(p) < tiny ? (p < 0.0 ? -tiny : tiny) : p; };
+  double dcur = sd[0] - lam, u1 = m > 1 ? se[0] : 0.0;
+  double bcur = rhs(0);
+  double bq[kInvBlk];
 #pragma unroll
-      for (int q = 0; q < kInvBlk; ++q) {
-        const int r = q + 1;
-        bq[q] = r < m ? (step == 0 ? inviter_start(r, n) : y[r * st]) : 0.0;
+  for (int q = 0; q < kInvBlk; ++q) bq[q] = rhs(q + 1);
+  for (int ib = 0; ib < m - 1; ib += kInvBlk) {
+    double bn[kInvBlk];
+#pragma unroll
+    for (int q = 0; q < kInvBlk; ++q) bn[q] = rhs(ib + kInvBlk + q + 1);   // ahead of the stores
+#pragma unroll
+    for (int q = 0; q < kInvBlk; ++q) {
+      const int i = ib + q;
+      if (i >= m - 1) break;
+      const double sub = se[i];
+      const double anext = sd[i + 1] - lam;
+      const double enext = i + 1 < m - 1 ? se[i + 1] : 0.0;
+      const double bnext = bq[q];
+      if (fabs(dcur) >= fabs(sub)) {
+        const double piv = safe(dcur), rp = rcp_nr(piv);
+        const double f = sub * rp;
+        RD[i * st] = rp;
+        U1[i * st] = u1;
+        U2[i * st] = 0.0;
+        y[i * st] = bcur;
+        bcur = bnext - f * bcur;
+        dcur = anext - f * u1;
+        u1 = enext;
+      } else {
+        const double piv = safe(sub), rp = rcp_nr(piv);
+        const double f = dcur * rp;
+        RD[i * st] = rp;
+        U1[i * st] = anext;
+        U2[i * st] = enext;
+        y[i * st] = bnext;
+        bcur = bcur - f * bnext;
+        dcur = u1 - f * anext;
+        u1 = -f * enext;
       }
-      for (int ib = 0; ib < m - 1; ib += kInvBlk) {
-        double bn[kInvBlk];
+    }
 #pragma unroll
-        for (int q = 0; q < kInvBlk; ++q) {  // next block's right-hand side, ahead of the stores
-          const int r = ib + kInvBlk + q + 1;
-          bn[q] = r < m ? (step == 0 ? inviter_start(r, n) : y[r * st]) : 0.0;
+    for (int q = 0; q < kInvBlk; ++q) bq[q] = bn[q];
+  }
+  // back substitution with U (rows m-1 .. 0), a block of rows loaded ahead; the norm of the
+  // solution accumulates on the way
+  double y1 = bcur * rcp_nr(safe(dcur)), y2 = 0.0;
+  double ss = y1 * y1;
+  y[(m - 1) * st] = y1;
+  double pz[kBwdBlk], pu1[kBwdBlk], pu2[kBwdBlk], pd[kBwdBlk];
+#pragma unroll
+  for (int q = 0; q < kBwdBlk; ++q) {
+    const int i = max(m - 2 - q, 0);
+    pz[q] = y[i * st];
+    pu1[q] = U1[i * st];
+    pu2[q] = U2[i * st];
+    pd[q] = RD[i * st];
+  }
+  for (int ib = m - 2; ib >= 0; ib -= kBwdBlk) {
+    double nz[kBwdBlk], nu1[kBwdBlk], nu2[kBwdBlk], nd[kBwdBlk];
+#pragma unroll
+    for (int q = 0; q < kBwdBlk; ++q) {
+      const int i = max(ib - kBwdBlk - q, 0);
+      nz[q] = y[i * st];
+      nu1[q] = U1[i * st];
+      nu2[q] = U2[i * st];
+      nd[q] = RD[i * st];
+    }
+#pragma unroll
+    for (int q = 0; q < kBwdBlk; ++q) {
+      const int i = ib - q;
+      if (i < 0) break;
+      const double yi = (pz[q] - pu1[q] * y1 - pu2[q] * y2) * pd[q];
+      y[i * st] = yi;
+      ss += yi * yi;
+      y2 = y1;
+      y1 = yi;
+    }
+#pragma unroll
+    for (int q = 0; q < kBwdBlk; ++q) {
+      pz[q] = nz[q];
+      pu1[q] = nu1[q];
+      pu2[q] = nu2[q];
+      pd[q] = nd[q];
+    }
+  }
+  *scp = 1.0 / sqrt(ss);
+}
+
+// Grid (nwant, jobs), 256 threads: workgroup n0 orthonormalises the cluster that starts at
+// eigenvalue n0 if it has two or more members (others return at once).  Vectors in order:
+// two passes of block classical Gram-Schmidt against the finished ones (16 at a time, one
+// batched reduction per block), then unit norm; rows i = tid + 256 r.
+constexpr int kOrthBlk = 16;
+__global__ void __launch_bounds__(256) k_eig_orth(DJobs jobs, const double* __restrict__ theta,
+                                                  double* __restrict__ yw, EigWork ew) {
+  __shared__ double red[4][kOrthBlk];
+  const DJob& J = jobs.j[blockIdx.y];
+  const int mb = jobs.mb, nb = jobs.nb, m = J.m, k = J.k, nwant = min(nb, m);
+  const int n0 = blockIdx.x;
+  if (n0 >= nwant) return;
+  const double* th = theta + int64_t(k) * mb;
+  const double ortol = 1e-5 * ew.nrm[k];
+  if (n0 > 0 && th[n0] - th[n0 - 1] <= ortol) return;   // not the first of its cluster
+  int n1 = n0 + 1;
+  while (n1 < nwant && th[n1] - th[n1 - 1] <= ortol) ++n1;
+  if (n1 - n0 < 2) return;
+  double* Y = yw + int64_t(k) * nb * mb;
+  double* sc = ew.sc + int64_t(k) * nb;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int R = kTrdMaxBasis / 256;   // rows per thread
+  for (int n = n0; n < n1; ++n) {
+    double yn[R];
+    const double s0 = sc[n];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + 256 * r;
+      yn[r] = i < m ? Y[int64_t(i) * nb + n] * s0 : 0.0;
+    }
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int qb = n0; qb < n; qb += kOrthBlk) {
+        const int nq = min(kOrthBlk, n - qb);
+        double part[kOrthBlk];
+#pragma unroll
+        for (int q = 0; q < kOrthBlk; ++q) part[q] = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int i = tid + 256 * r;
+          if (i >= m) break;
+#pragma unroll
+          for (int q = 0; q < kOrthBlk; ++q)
+            if (q < nq) part[q] += Y[int64_t(i) * nb + qb + q] * yn[r];
         }
 #pragma unroll
-        for (int q = 0; q < kInvBlk; ++q) {
-          const int i = ib + q;
-          if (i >= m - 1) break;
-          const double sub = se[i];
-          const double anext = sd[i + 1] - lam;
-          const double enext = i + 1 < m - 1 ? se[i + 1] : 0.0;
-          const double bnext = bq[q];
-          if (fabs(dcur) >= fabs(sub)) {
-            const double f = dcur != 0.0 ? sub / dcur : 0.0;
-            D[i * st] = fabs(dcur) < tiny ? (dcur < 0.0 ? -tiny : tiny) : dcur;
-            U1[i * st] = u1;
-            U2[i * st] = 0.0;
-            y[i * st] = bcur;
-            bcur = bnext - f * bcur;
-            dcur = anext - f * u1;
-            u1 = enext;
-          } else {
-            const double f = dcur / sub;
-            D[i * st] = fabs(sub) < tiny ? (sub < 0.0 ? -tiny : tiny) : sub;
-            U1[i * st] = anext;
-            U2[i * st] = enext;
-            y[i * st] = bnext;
-            bcur = bcur - f * bnext;
-            dcur = u1 - f * anext;
-            u1 = -f * enext;
-          }
+        for (int q = 0; q < kOrthBlk; ++q) {
+          for (int o = 32; o > 0; o >>= 1) part[q] += __shfl_xor(part[q], o, 64);
+          if (lane == 0) red[wave][q] = part[q];
         }
+        __syncthreads();
 #pragma unroll
-        for (int q = 0; q < kInvBlk; ++q) bq[q] = bn[q];
-      }
-      // back substitution with U (rows m-1 .. 0), a block of rows prefetched ahead
-      const double dl = fabs(dcur) < tiny ? (dcur < 0.0 ? -tiny : tiny) : dcur;
-      double y1 = bcur / dl, y2 = 0.0;
-      y[(m - 1) * st] = y1;
-      double pz[kBwdBlk], pu1[kBwdBlk], pu2[kBwdBlk], pd[kBwdBlk];
+        for (int q = 0; q < kOrthBlk; ++q) part[q] = red[0][q] + red[1][q] + red[2][q] + red[3][q];
+        __syncthreads();
 #pragma unroll
-      for (int q = 0; q < kBwdBlk; ++q) {
-        const int i = m - 2 - q;
-        const bool ok = i >= 0;
-        pz[q] = ok ? y[i * st] : 0.0;
-        pu1[q] = ok ? U1[i * st] : 0.0;
-        pu2[q] = ok ? U2[i * st] : 0.0;
-        pd[q] = ok ? D[i * st] : 1.0;
-      }
-      for (int ib = m - 2; ib >= 0; ib -= kBwdBlk) {
-        double nz[kBwdBlk], nu1[kBwdBlk], nu2[kBwdBlk], nd[kBwdBlk];
+        for (int r = 0; r < R; ++r) {
+          const int i = tid + 256 * r;
+          if (i >= m) break;
 #pragma unroll
-        for (int q = 0; q < kBwdBlk; ++q) {
-          const int i = ib - kBwdBlk - q;
-          const bool ok = i >= 0;
-          nz[q] = ok ? y[i * st] : 0.0;
-          nu1[q] = ok ? U1[i * st] : 0.0;
-          nu2[q] = ok ? U2[i * st] : 0.0;
-          nd[q] = ok ? D[i * st] : 1.0;
-        }
-#pragma unroll
-        for (int q = 0; q < kBwdBlk; ++q) {
-          const int i = ib - q;
-          if (i < 0) break;
-          const double yi = (pz[q] - pu1[q] * y1 - pu2[q] * y2) / pd[q];
-          y[i * st] = yi;
-          y2 = y1;
-          y1 = yi;
-        }
-#pragma unroll
-        for (int q = 0; q < kBwdBlk; ++q) {
-          pz[q] = nz[q];
-          pu1[q] = nu1[q];
-          pu2[q] = nu2[q];
-          pd[q] = nd[q];
+          for (int q = 0; q < kOrthBlk; ++q)
+            if (q < nq) yn[r] -= part[q] * Y[int64_t(i) * nb + qb + q];
         }
       }
     }
+    double ss = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) ss += yn[r] * yn[r];
+    ss = wave_sum_all(ss);
+    if (lane == 0) red[wave][0] = ss;
     __syncthreads();
-    // modified Gram-Schmidt inside each cluster, then unit norm; one wave per cluster
-    for (int c = wave; c < s_ncl; c += nwaves) {
-      const int n0 = s_cl[c], n1 = s_cl[c + 1];
-      for (int n = n0; n < n1; ++n) {
-        for (int q = n0; q < n; ++q) {
-          double s = 0.0;
-          for (int i = lane; i < m; i += 64) s += Y[i * st + n] * Y[i * st + q];
-          s = wave_sum_all(s);
-          for (int i = lane; i < m; i += 64) Y[i * st + n] -= s * Y[i * st + q];
-        }
-        double s = 0.0;
-        for (int i = lane; i < m; i += 64) s += Y[i * st + n] * Y[i * st + n];
-        s = 1.0 / sqrt(wave_sum_all(s));
-        for (int i = lane; i < m; i += 64) Y[i * st + n] *= s;
-      }
+    const double s = 1.0 / sqrt(red[0][0] + red[1][0] + red[2][0] + red[3][0]);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int i = tid + 256 * r;
+      if (i < m) Y[int64_t(i) * nb + n] = yn[r] * s;
     }
-    __syncthreads();
+    if (tid == 0) sc[n] = 1.0;
   }
 }
 
 // Z = Q y with Q = H_0 H_1 ... H_{m-2}: one workgroup per (slice of cols columns, k); the
-// slice of Z lives in LDS while every reflector streams through.  Z[k][i][n] complex.
+// slice of Z lives in LDS while every reflector streams through.  Z[k][i][n] complex; y
+// column n is Y[k][.][n] * sc[k][n].
 constexpr int BT_COLS = 8;   // upper bound of cols
 __global__ void __launch_bounds__(256) k_backtransform(DJobs jobs, const double2* __restrict__ Aw,
                                                        const double2* __restrict__ tau,
                                                        const double* __restrict__ yw,
+                                                       const double* __restrict__ scw,
                                                        double2* __restrict__ Zout, int cols) {
   extern __shared__ double2 shz[];   // [mb][BT_COLS] slice, then [mb] reflector
   const DJob& J = jobs.j[blockIdx.y];
@@ -866,7 +961,9 @@ __global__ void __launch_bounds__(256) k_backtransform(DJobs jobs, const double2
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   for (int t = tid; t < m * cols; t += blockDim.x) {
     const int i = t / cols, c = t % cols;
-    zs[t] = c < nc ? make_double2(Y[int64_t(i) * nb + c0 + c], 0.0) : make_double2(0.0, 0.0);
+    const int cl = min(c, nc - 1);
+    const double yv = Y[int64_t(i) * nb + c0 + cl] * scw[int64_t(J.k) * nb + c0 + cl];
+    zs[t] = make_double2(c < nc ? yv : 0.0, 0.0);
   }
   __syncthreads();
   for (int j = m - 2; j >= 0; --j) {
