@@ -39,6 +39,8 @@ struct DavState {
   int64_t* goff = nullptr;
   TrdWork trd{};
   EigWork ew{};
+  double* chol_dmax = nullptr;   // [k] largest Gram diagonal (Cholesky pivot test)
+  double2* chol_ld = nullptr;    // [k][nb / 16 rounded up][16][16] diagonal blocks of L
   void* work = nullptr;
   int64_t work_bytes = 0;
   double *h_resn = nullptr, *h_theta = nullptr;
@@ -55,7 +57,8 @@ struct DavState {
 static void dav_release(DavState* d) {
   void* dev[] = {d->V, d->HV, d->X, d->HX, d->R, d->TS, d->Hs, d->Aw, d->Z, d->tau, d->Cw, d->G,
                  d->W, d->theta, d->d, d->e, d->resn, d->tkin, d->yw, d->fw, d->unconv, d->info,
-                 d->goff, d->work, d->estar, d->ps.part, d->trd.v, d->trd.w, d->trd.p, d->trd.cnt, d->ew.sc, d->ew.nrm};
+                 d->goff, d->work, d->estar, d->ps.part, d->trd.v, d->trd.w, d->trd.p, d->trd.cnt,
+                 d->ew.sc, d->ew.nrm, d->chol_dmax, d->chol_ld};
   for (void* q : dev)
     if (q) (void)hipFree(q);
   void* host[] = {d->h_resn, d->h_theta, d->h_unconv, d->h_info};
@@ -129,6 +132,8 @@ static DavState* dav_create(qm_hpsi_plan* p, int k0, int k1, int nb, int mb, boo
     d->trd.cnt = dalloc<uint32_t>(nk);
     d->ew.sc = dalloc<double>(nk * nb);
     d->ew.nrm = dalloc<double>(nk);
+    d->chol_dmax = dalloc<double>(nk);
+    d->chol_ld = dalloc<double2>(nk * size_t((nb + kCholBlk - 1) / kCholBlk) * kCholBlk * kCholBlk);
     std::vector<int64_t> go(nk);
     for (size_t k = 0; k < nk; ++k) go[k] = p->kinfo[k].g_off;
     QM_HIP(hipMemcpy(d->goff, go.data(), nk * sizeof(int64_t), hipMemcpyHostToDevice));
@@ -140,6 +145,7 @@ static DavState* dav_create(qm_hpsi_plan* p, int k0, int k1, int nb, int mb, boo
     QM_HIP(hipHostMalloc(reinterpret_cast<void**>(&d->h_info), nk * sizeof(int32_t)));
     for (hipEvent_t& e : d->ev) QM_HIP(hipEventCreate(&e));
     const void* big[] = {reinterpret_cast<const void*>(&k_tridiag), reinterpret_cast<const void*>(&k_eig_vals),
+                         reinterpret_cast<const void*>(&k_chol_inv_cols),
                          reinterpret_cast<const void*>(&k_backtransform)};
     for (const void* f : big) QM_HIP(allow_full_lds(f));
     d->m.assign(nk, 0);
@@ -169,6 +175,27 @@ static void timed_apply(qm_hpsi_plan* p, DavState* d, const std::vector<KSlice>&
   for (const KSlice& x : sl) nb += x.nb;
   d->n_hpsi += nb;
   if (lowp && p->prec != QM_PREC_FP64) d->n_hpsi_lowp += nb;
+}
+
+// Cholesky G = L L^H of every job's Gram matrix and W = conj(Linv)^T: blocked on many
+// workgroups when the inverse's column block fits in LDS, else one workgroup per job.
+static void cholesky_inverse(DavState* d, const DJobs& jobs, hipStream_t s) {
+  if (d->nb > kCholMaxBlocked) {
+    hipLaunchKernelGGL(k_chol_inv, dim3(jobs.n), dim3(1024), 0, s, jobs, d->G, d->W, d->info);
+    QM_HIP(hipGetLastError());
+    return;
+  }
+  int numax = 0;
+  for (int i = 0; i < jobs.n; ++i) numax = std::max(numax, jobs.j[i].nu);
+  const int nblk = (numax + kCholBlk - 1) / kCholBlk;
+  hipLaunchKernelGGL(k_chol_prep, dim3(jobs.n), dim3(256), 0, s, jobs, d->G, d->chol_dmax, d->info);
+  for (int jb = 0; jb < nblk; ++jb)
+    hipLaunchKernelGGL(k_chol_col, dim3(nblk - jb, jobs.n), dim3(256), 0, s, jobs, jb, d->G,
+                       d->chol_ld, d->chol_dmax, d->info);
+  hipLaunchKernelGGL(k_chol_inv_cols, dim3(nblk, jobs.n), dim3(256),
+                     size_t(nblk) * kCholBlk * kCholBlk * sizeof(double2), s, jobs, d->G, d->chol_ld,
+                     d->W, d->info);
+  QM_HIP(hipGetLastError());
 }
 
 // T = rows [m - nu, m) of V; orthogonalise against rows [0, m - nu) (two CGS passes) and
@@ -204,8 +231,7 @@ static bool orthonormalise(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipS
       ex.push_back(GemmEX{Wk, T, O, j.nu, j.npw, j.nu, d->nb, j.npw, j.npw});
     }
     zgemm_cn_batched(cn, 1.0, 0.0, d->work, d->work_bytes, s);
-    hipLaunchKernelGGL(k_chol_inv, dim3(jobs.n), dim3(1024), 0, s, jobs, d->G, d->W, d->info);
-    QM_HIP(hipGetLastError());
+    cholesky_inverse(d, jobs, s);
     zgemm_ex_batched(ex, 1.0, 0.0, s);
   }
   QM_HIP(hipMemcpyAsync(d->h_info, d->info, sizeof(int32_t) * d->nk, hipMemcpyDeviceToHost, s));

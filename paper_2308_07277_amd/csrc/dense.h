@@ -51,6 +51,13 @@ __global__ void k_eig_orth(DJobs jobs, const double* theta, double* yw, EigWork 
 __global__ void k_backtransform(DJobs jobs, const double2* Aw, const double2* tau, const double* yw,
                                 const double* scw, double2* Zout, int cols);
 __global__ void k_chol_inv(DJobs jobs, double2* Gm, double2* Wm, int32_t* info);
+constexpr int kCholBlk = 16;        // block size of the many-workgroup Cholesky
+constexpr int kCholMaxBlocked = 544; // largest band count whose Linv column block fits in LDS
+__global__ void k_chol_prep(DJobs jobs, const double2* Gm, double* dmax, int32_t* info);
+__global__ void k_chol_col(DJobs jobs, int jb, double2* Gm, double2* Ldw, const double* dmaxw,
+                           int32_t* info);
+__global__ void k_chol_inv_cols(DJobs jobs, const double2* Gm, const double2* Ldw, double2* Wm,
+                                const int32_t* info);
 __global__ void k_residual(DJobs jobs, const double2* X, const double2* HX, double2* Rr,
                            const double* theta, const double* kin_all, const int64_t* goff,
                            double* resn, double* tkin);

@@ -1066,6 +1066,194 @@ __global__ void __launch_bounds__(1024) k_chol_inv(DJobs jobs, double2* __restri
   }
 }
 
+// ---------------------------------------------------------------- blocked Cholesky + inverse
+// The same factorisation and inverse on many workgroups, in blocks of kCholB = 16:
+//   k_chol_prep      largest diagonal entry (pivot test) and info = 0
+//   k_chol_col       block column jb of L (Crout order, one launch per block column): the
+//                    workgroup of row block ib forms [S_jj; S_ib,j] = G - (finished columns)
+//                    through LDS tiles, factors S_jj itself (every workgroup of the launch
+//                    does, identically, so none waits for another) and solves its own block.
+//                    The diagonal blocks of L go to Ld: the other workgroups of the launch
+//                    still read that block of G, and no later block column needs them
+//   k_chol_inv_cols  one workgroup per column block of Linv, walking down the block rows
+//                    with the finished part of its column block kept in LDS
+// Output: the off-diagonal blocks of L in the lower triangle of G, its diagonal blocks in
+// Ld [k][block][16][16], W[i][n] = conj(Linv[n][i]) as from k_chol_inv.
+constexpr int kCholB = kCholBlk;
+
+__global__ void __launch_bounds__(256) k_chol_prep(DJobs jobs, const double2* __restrict__ Gm,
+                                                   double* __restrict__ dmax, int32_t* __restrict__ info) {
+  __shared__ double red[4];
+  const DJob& J = jobs.j[blockIdx.x];
+  const int nb = jobs.nb, n = J.nu;
+  const double2* G = Gm + int64_t(J.k) * nb * nb;
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) mx = fmax(mx, G[int64_t(i) * nb + i].x);
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    dmax[J.k] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    info[J.k] = 0;
+  }
+}
+
+// Grid (row blocks from jb on, jobs), 256 threads: thread (r = tid / 16, c = tid % 16).
+__global__ void __launch_bounds__(256) k_chol_col(DJobs jobs, int jb, double2* __restrict__ Gm,
+                                                  double2* __restrict__ Ldw,
+                                                  const double* __restrict__ dmaxw,
+                                                  int32_t* __restrict__ info) {
+  constexpr int B = kCholB;
+  __shared__ double2 sL[2 * B][B + 1];
+  __shared__ double2 sS[2 * B][B + 1];
+  __shared__ double s_piv;
+  __shared__ int s_fail;
+  const DJob& J = jobs.j[blockIdx.y];
+  const int nb = jobs.nb, n = J.nu, k = J.k;
+  const int ib = jb + blockIdx.x;
+  if (jb * B >= n || ib * B >= n) return;
+  if (info[k] != 0) return;   // an earlier block column failed
+  double2* G = Gm + int64_t(k) * nb * nb;
+  const int tid = threadIdx.x, r = tid >> 4, c = tid & 15;
+  const int rj = jb * B + r, ri = ib * B + r, cj = jb * B + c;
+  const double2 z = make_double2(0.0, 0.0);
+  // S = G - sum over the finished columns q < jb B of L[row][q] conj(L[cj][q])
+  double2 acc0 = z, acc1 = z;
+  for (int k0 = 0; k0 < jb * B; k0 += B) {
+    for (int e = tid; e < 2 * B * B; e += 256) {
+      const int rr = e / B, qq = e % B;
+      const int row = rr < B ? jb * B + rr : ib * B + rr - B;
+      sL[rr][qq] = keep(G[int64_t(min(row, n - 1)) * nb + k0 + qq], row < n);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < B; ++q) {
+      const double2 lc = cconj(sL[c][q]);
+      acc0 = cadd2(acc0, cmul2(sL[r][q], lc));
+      acc1 = cadd2(acc1, cmul2(sL[B + r][q], lc));
+    }
+    __syncthreads();
+  }
+  {
+    const bool ok0 = rj < n && cj < n && c <= r;
+    const double2 g0 = G[int64_t(min(rj, n - 1)) * nb + min(cj, n - 1)];
+    sS[r][c] = keep(csub2(g0, acc0), ok0);
+    if (ib != jb) {
+      const bool ok1 = ri < n && cj < n;
+      const double2 g1 = G[int64_t(min(ri, n - 1)) * nb + min(cj, n - 1)];
+      sS[B + r][c] = keep(csub2(g1, acc1), ok1);
+    }
+  }
+  if (tid == 0) s_fail = 0;
+  __syncthreads();
+  // Cholesky of S_jj in LDS (rows past n: identity)
+  const double dmax = dmaxw[k];
+  for (int q = 0; q < B; ++q) {
+    if (tid == 0) {
+      double piv = 1.0;
+      if (jb * B + q < n) {
+        const double djj = sS[q][q].x;
+        if (!(djj > 1e-14 * dmax) || !(djj < 1e300)) s_fail = jb * B + q + 1;
+        else piv = sqrt(djj);
+      }
+      s_piv = piv;
+      sS[q][q] = make_double2(piv, 0.0);
+    }
+    __syncthreads();
+    if (s_fail) break;
+    if (tid > q && tid < B) {
+      const double inv = 1.0 / s_piv;
+      sS[tid][q] = make_double2(sS[tid][q].x * inv, sS[tid][q].y * inv);
+    }
+    __syncthreads();
+    if (r > q && c > q && c <= r) sS[r][c] = csub2(sS[r][c], cmul2(sS[r][q], cconj(sS[c][q])));
+    __syncthreads();
+  }
+  if (s_fail) {
+    if (ib == jb && tid == 0) info[k] = s_fail;
+    return;
+  }
+  if (ib == jb) {
+    const int nblk_all = (nb + B - 1) / B;
+    Ldw[((int64_t(k) * nblk_all + jb) * B + r) * B + c] = keep(sS[r][c], c <= r);
+    return;
+  }
+  // L_ib,j = S_ib,j L_jj^-H: row r solves x L_jj^H = s column by column
+  for (int cc = 0; cc < B; ++cc) {
+    if (tid < B) {
+      double2 s = sS[B + tid][cc];
+      for (int q = 0; q < cc; ++q) s = csub2(s, cmul2(sS[B + tid][q], cconj(sS[cc][q])));
+      const double inv = 1.0 / sS[cc][cc].x;
+      sS[B + tid][cc] = make_double2(s.x * inv, s.y * inv);
+    }
+    __syncthreads();
+  }
+  if (ri < n && cj < n) G[int64_t(ri) * nb + cj] = sS[B + r][c];
+}
+
+// Grid (column blocks, jobs), 256 threads, dynamic LDS [n rounded up to B][B] complex.
+__global__ void __launch_bounds__(256) k_chol_inv_cols(DJobs jobs, const double2* __restrict__ Gm,
+                                                       const double2* __restrict__ Ldw,
+                                                       double2* __restrict__ Wm,
+                                                       const int32_t* __restrict__ info) {
+  constexpr int B = kCholB;
+  extern __shared__ double2 sX[];          // rows [jb B, n) of column block jb of Linv, [.][B]
+  __shared__ double2 sLc[B][B + 1];
+  __shared__ double2 sD[B][B + 1];
+  __shared__ double2 sY[B][B + 1];
+  const DJob& J = jobs.j[blockIdx.y];
+  const int nb = jobs.nb, n = J.nu, k = J.k;
+  const int jb = blockIdx.x;
+  if (jb * B >= n || info[k] != 0) return;
+  const double2* G = Gm + int64_t(k) * nb * nb;
+  double2* W = Wm + int64_t(k) * nb * nb;
+  const int tid = threadIdx.x, r = tid >> 4, c = tid & 15;
+  const int cj = jb * B + c;
+  const double2 z = make_double2(0.0, 0.0);
+  const int nblk = (n + B - 1) / B;
+  // the other triangle of W's rows for this column block
+  for (int e = tid; e < B * jb * B; e += 256) {
+    const int cc = e / (jb * B), rr = e % (jb * B);
+    if (jb * B + cc < n) W[int64_t(jb * B + cc) * nb + rr] = z;
+  }
+  for (int ib = jb; ib < nblk; ++ib) {
+    // acc = sum over q in [jb B, ib B) of L[ib B + r][q] X[q][c]
+    double2 acc = z;
+    for (int q0 = jb * B; q0 < ib * B; q0 += B) {
+      const int row = ib * B + r;
+      sLc[r][c] = keep(G[int64_t(min(row, n - 1)) * nb + q0 + c], row < n);
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < B; ++q) acc = cadd2(acc, cmul2(sLc[r][q], sX[(q0 - jb * B + q) * B + c]));
+      __syncthreads();
+    }
+    // diagonal block of L and the right-hand side (identity on the diagonal block)
+    {
+      const int row = ib * B + r, col = ib * B + c;
+      const bool ok = row < n && col < n && c <= r;
+      sD[r][c] = keep(Ldw[((int64_t(k) * ((nb + B - 1) / B) + ib) * B + r) * B + c], ok);
+      if (row >= n && r == c) sD[r][c] = make_double2(1.0, 0.0);
+      const double2 id = make_double2(ib == jb && r == c ? 1.0 : 0.0, 0.0);
+      sY[r][c] = csub2(id, acc);
+    }
+    __syncthreads();
+    // forward substitution L_ii Y = rhs, one row at a time (16 columns in parallel)
+    for (int rr = 0; rr < B; ++rr) {
+      if (tid < B) {
+        double2 s = sY[rr][tid];
+        for (int q = 0; q < rr; ++q) s = csub2(s, cmul2(sD[rr][q], sY[q][tid]));
+        const double inv = 1.0 / sD[rr][rr].x;
+        sY[rr][tid] = make_double2(s.x * inv, s.y * inv);
+      }
+      __syncthreads();
+    }
+    const int row = ib * B + r;
+    sX[(ib * B - jb * B + r) * B + c] = sY[r][c];
+    if (row < n && cj < n) W[int64_t(cj) * nb + row] = cconj(sY[r][c]);
+    __syncthreads();
+  }
+}
+
 // ---------------------------------------------------------------- residuals
 // One workgroup per (job, band): r = HX - theta X into R, ||r||, <x|T|x>/<x|x>.
 __global__ void __launch_bounds__(256) k_residual(DJobs jobs, const double2* __restrict__ X,
