@@ -134,7 +134,12 @@ typedef struct {
  * workspace, so inputs may be freed after the call returns.  Environment:
  * QM_XY_MODE=1 forces the two-pass xy-plane kernel, QM_XY_MODE=2 the lane-group kernel
  * (grids of 20, 40 and 72 points along x; same transform, for comparisons); otherwise
- * qm_hpsi_plan_autotune picks one per precision. */
+ * qm_hpsi_plan_autotune picks one per precision.  For the Davidson calls on the plan
+ * (same results up to the order of float64 additions, for comparisons):
+ * QM_TRIDIAG_MODE=1 reduces the projected matrix in one workgroup per k-point, =2 with one
+ * launch per Householder step on many workgroups (default: from a basis of 192 columns);
+ * QM_CHOL_MODE=1 factors the CholQR Gram matrices in one workgroup per k-point, =2 blocked
+ * on many workgroups (default: blocked up to 544 bands, the largest it supports). */
 qm_status qm_hpsi_plan_create(const double cell[9], const int32_t grid[3], const qm_kset *ks,
                               int32_t nbnd_max, int32_t nproj, const double *vloc_r,
                               const void *beta, const double *dmat, qm_prec prec, void *stream,

@@ -179,8 +179,8 @@ static void timed_apply(qm_hpsi_plan* p, DavState* d, const std::vector<KSlice>&
 
 // Cholesky G = L L^H of every job's Gram matrix and W = conj(Linv)^T: blocked on many
 // workgroups when the inverse's column block fits in LDS, else one workgroup per job.
-static void cholesky_inverse(DavState* d, const DJobs& jobs, hipStream_t s) {
-  if (d->nb > kCholMaxBlocked) {
+static void cholesky_inverse(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipStream_t s) {
+  if (d->nb > kCholMaxBlocked || p->chol_forced == 1) {
     hipLaunchKernelGGL(k_chol_inv, dim3(jobs.n), dim3(1024), 0, s, jobs, d->G, d->W, d->info);
     QM_HIP(hipGetLastError());
     return;
@@ -231,7 +231,7 @@ static bool orthonormalise(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipS
       ex.push_back(GemmEX{Wk, T, O, j.nu, j.npw, j.nu, d->nb, j.npw, j.npw});
     }
     zgemm_cn_batched(cn, 1.0, 0.0, d->work, d->work_bytes, s);
-    cholesky_inverse(d, jobs, s);
+    cholesky_inverse(p, d, jobs, s);
     zgemm_ex_batched(ex, 1.0, 0.0, s);
   }
   QM_HIP(hipMemcpyAsync(d->h_info, d->info, sizeof(int32_t) * d->nk, hipMemcpyDeviceToHost, s));

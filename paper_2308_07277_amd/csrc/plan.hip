@@ -70,6 +70,7 @@ static void build_plan(qm_hpsi_plan* p, const double cell[9], const int32_t grid
   p->zts = kTileSticks;
   if (const char* xm = std::getenv("QM_XY_MODE")) p->xy_forced = std::atoi(xm);
   if (const char* tm = std::getenv("QM_TRIDIAG_MODE")) p->trd_forced = std::atoi(tm);
+  if (const char* cm = std::getenv("QM_CHOL_MODE")) p->chol_forced = std::atoi(cm);
   std::memcpy(p->cell, cell, sizeof(p->cell));
   // reciprocal rows b_i = 2 pi (A^-1)^T
   const double* a = cell;

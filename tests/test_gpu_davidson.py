@@ -211,3 +211,27 @@ def test_tridiagonalisation_paths(mode, monkeypatch):
                                 a["dmat"])
             lam = np.linalg.eigvalsh(dense)[:w.nbnd]
             assert np.abs(eig[ik] - lam).max() <= 1e-8
+
+
+@pytest.mark.parametrize("mode", ["1", "2"])
+def test_cholesky_paths(mode, monkeypatch):
+    """QM_CHOL_MODE=1 factors the CholQR Gram matrices (and inverts the factor) in one
+    workgroup per k-point; 2 uses the blocked kernels (16-wide Crout block columns, one
+    workgroup per column block of the inverse), the default up to 544 bands.  Both must
+    reach the dense eigenvalues within 1e-8 Ha with orthonormal vectors on the 8-atom cells
+    (8 bands: one ragged block; 32 bands: two blocks; four k-points per launch)."""
+    monkeypatch.setenv("QM_CHOL_MODE", mode)
+    for name in ("c1", "c2"):
+        w = workload.make_workload(name)
+        plan, a = make_plan(w, w.nbnd)
+        eig, res, stats, st, x = _solve(plan, w, w.nbnd, _start(w, w.nbnd), tol=1e-9)
+        print(name, "mode", mode, stats)
+        assert st == 0 and stats["converged"] == 1
+        xs = split_k(x, w, w.nbnd)
+        for ik in range(w.nk):
+            h, beta = _oracle_h(w, a, ik)
+            dense = ham.dense_h(w.cell, w.grid, w.k_cryst[ik], w.miller[ik], a["vloc"], beta,
+                                a["dmat"])
+            lam = np.linalg.eigvalsh(dense)[:w.nbnd]
+            assert np.abs(eig[ik] - lam).max() <= 1e-8
+            np.testing.assert_allclose(xs[ik].conj() @ xs[ik].T, np.eye(w.nbnd), atol=1e-10)
