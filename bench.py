@@ -143,11 +143,11 @@ def cpu_baseline(w, nb_sample, nk_sample=8):
                       f"applications in {dt:.1f} s"}
 
 
-def _plan_for(w, prec=0):
+def _plan_for(w, prec=0, nbnd_max=None):
     import paper_2308_07277_amd as qm
     miller, beta, vloc, _ = build_inputs(w)
-    plan = qm.qm_hpsi_plan_create(w.cell, w.grid, w.k_cart, w.npw, miller, w.nbnd, w.nproj,
-                                  vloc, beta, w.dmat(), prec)
+    plan = qm.qm_hpsi_plan_create(w.cell, w.grid, w.k_cart, w.npw, miller,
+                                  nbnd_max or w.nbnd, w.nproj, vloc, beta, w.dmat(), prec)
     return plan
 
 
@@ -251,37 +251,50 @@ def davidson_cpu_baseline(name="c2", tol=1e-8):
             "max_abs_eig_diff": float(np.abs(np.array(eig_cpu) - eig).max())}
 
 
-def davidson_run(name, weights=None, tol=1e-8, max_basis_factor=4, switch_resid=1e-3, lanes=3,
-                 only=None):
+# Davidson arms: (name, ladder precision of H or None for float64 throughout, switch
+# residual, preconditioner, buffer bands: None = the run's default, lanes: None = default)
+DAVIDSON_ARMS = [
+    ("fp64+teter", None, 0.0, "teter", None, None),
+    ("fp64+teter, one lane", None, 0.0, "teter", None, 1),
+    ("fp64+teter, no buffer bands", None, 0.0, "teter", 0, None),
+    ("fp64+mlp", None, 0.0, "mlp", None, None),
+    ("fp32-ladder+teter", 1, 1e-5, "teter", None, None),
+    ("fp32-ladder+mlp", 1, 1e-5, "mlp", None, None),
+    ("bf16-ladder+teter", 2, 1e-3, "teter", None, None),
+    ("bf16-ladder+mlp", 2, 1e-3, "mlp", None, None),
+]
+
+
+def davidson_run(name, weights=None, tol=1e-8, max_basis_factor=4, lanes=3, only=None,
+                 extra_bands=32):
     """Block Davidson from a seeded random start to max residual <= tol over every k-point
-    and band: arm A float64 H + Teter; arm B float32-FFT/bf16-GEMM H while the residual is
-    above switch_resid (float64 H below) + the learned preconditioner."""
+    and wanted band, one solve per arm of DAVIDSON_ARMS: float64 H, or a precision ladder
+    (float32 FFT with float32 or bf16 projector GEMMs while the max residual is above the
+    switch residual, float64 H below), with the Teter or the learned preconditioner, and
+    extra_bands buffer bands (corrected but not required to converge)."""
     import torch
     import workload
     import paper_2308_07277_amd as qm
     w = workload.make_workload(name)
-    plan = _plan_for(w, prec=2)
+    plan = _plan_for(w, prec=2, nbnd_max=w.nbnd + extra_bands)
     start = torch.cat([torch.from_numpy(w.psi(ik, purpose=2).reshape(-1)) for ik in range(w.nk)]).cuda()
     arms = {}
     eigs = {}
-    cfgs = [("fp64+teter", dict(precond=qm.QM_PRECOND_TETER, switch_resid=0.0)),
-            ("fp64+teter, one lane", dict(precond=qm.QM_PRECOND_TETER, switch_resid=0.0, lanes=1)),
-            ("mixed+teter", dict(precond=qm.QM_PRECOND_TETER, switch_resid=switch_resid))]
-    if weights is not None:
-        cfgs.append(("fp64+mlp", dict(precond=qm.QM_PRECOND_MLP, mlp_weights=weights,
-                                      switch_resid=0.0)))
-        cfgs.append(("mixed+mlp", dict(precond=qm.QM_PRECOND_MLP, mlp_weights=weights,
-                                       switch_resid=switch_resid)))
-    if only is not None:
-        cfgs = [c for c in cfgs if c[0] in only]
-    for arm, kw in cfgs:
+    for arm, lprec, sw, pre, eb, ln in DAVIDSON_ARMS:
+        if (only is not None and arm not in only) or (pre == "mlp" and weights is None):
+            continue
+        eb = extra_bands if eb is None else eb
+        kw = dict(precond=qm.QM_PRECOND_MLP if pre == "mlp" else qm.QM_PRECOND_TETER,
+                  switch_resid=sw, lanes=lanes if ln is None else ln, extra_bands=eb,
+                  max_basis=max_basis_factor * (w.nbnd + eb))
+        if pre == "mlp":
+            kw["mlp_weights"] = weights
+        if lprec is not None:
+            qm.qm_hpsi_plan_set_precision(plan, lprec)
         psi = start.clone()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        kw = dict(kw)
-        kw.setdefault("lanes", lanes)
-        eig, res, stats, st = qm.qm_davidson_solve(plan, -1, psi, w.nbnd, tol=tol, max_iter=400,
-                                                   max_basis=max_basis_factor * w.nbnd, **kw)
+        eig, res, stats, st = qm.qm_davidson_solve(plan, -1, psi, w.nbnd, tol=tol, max_iter=400, **kw)
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         eigs[arm] = eig
@@ -289,15 +302,18 @@ def davidson_run(name, weights=None, tol=1e-8, max_basis_factor=4, switch_resid=
                      "n_hpsi_bands": stats["n_hpsi_bands"],
                      "n_hpsi_bands_lowp": stats["n_hpsi_bands_lowp"],
                      "max_resnorm": stats["max_resnorm"], "t_hpsi_ms": stats["t_hpsi_ms"],
-                     "t_eig_ms": stats["t_eig_ms"], "t_subspace_ms": stats["t_subspace_ms"]}
+                     "t_eig_ms": stats["t_eig_ms"], "t_subspace_ms": stats["t_subspace_ms"],
+                     "extra_bands": eb}
+    ref = "fp64+teter" if "fp64+teter" in eigs else next(iter(eigs))
     for arm in arms:
-        if arm != "fp64+teter":
-            arms[arm]["max_abs_eig_diff_vs_fp64_teter"] = float(np.abs(eigs[arm] - eigs["fp64+teter"]).max())
+        if arm != ref:
+            arms[arm]["max_abs_eig_diff_vs_" + ref] = float(np.abs(eigs[arm] - eigs[ref]).max())
     plan.close()
     return {"workload": f"{name}: {len(w.atoms)}-atom cell, {w.nk} k-points, "
-                        f"{w.nbnd} bands, tol {tol:g} Ha, max_basis {max_basis_factor} nbnd, "
-                        f"k-points in {lanes} concurrent lanes unless the arm says otherwise",
-            "arms": arms, "lowest_eig_gamma": float(eigs["fp64+teter"][0][0]),
+                        f"{w.nbnd} bands, tol {tol:g} Ha, {extra_bands} buffer bands, max_basis "
+                        f"{max_basis_factor} (nbnd + buffer bands), k-points in {lanes} concurrent "
+                        f"lanes, unless the arm says otherwise",
+            "arms": arms, "lowest_eig_gamma": float(eigs[ref][0][0]),
             "eig_error_bound_note": "every eigenvalue of every arm is within its residual norm "
                                     "(<= tol) of an exact eigenvalue (Krylov-Weinstein)"}
 
@@ -436,7 +452,7 @@ def main():
         progress("Davidson on the 64-atom cell done")
         if args.davidson_c5:
             out["davidson_c5"] = davidson_run("c5", weights=weights, max_basis_factor=3,
-                                              only=("fp64+teter", "mixed+mlp"))
+                                              only=("fp64+teter", "fp64+mlp", "fp32-ladder+mlp"))
             progress("Davidson on the 216-atom cell done")
         if args.cpu_baseline:
             out["davidson_cpu_baseline"] = davidson_cpu_baseline("c2")

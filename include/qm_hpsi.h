@@ -99,6 +99,12 @@ typedef struct {
                              problems, so results equal the one-group solve up to
                              rounding; the precision ladder switches per group).  0 or 1:
                              one group [0] */
+  int32_t extra_bands;    /* buffer bands: the block holds nbnd + extra_bands Ritz vectors
+                             (the extra ones start from a fixed pseudo-random block), all
+                             of them corrected while unconverged, but only the nbnd lowest
+                             decide convergence and are returned.  Keeps a degenerate level
+                             cut by the band count from stalling the highest wanted bands.
+                             Needs nbnd + extra_bands <= the plan's nbnd_max [0] */
 } qm_dav_opts;
 
 /* Davidson statistics (host), filled by qm_davidson_solve. */
@@ -139,7 +145,7 @@ typedef struct {
  * QM_TRIDIAG_MODE=1 reduces the projected matrix in one workgroup per k-point, =2 with one
  * launch per Householder step on many workgroups (default: from a basis of 192 columns);
  * QM_CHOL_MODE=1 factors the CholQR Gram matrices in one workgroup per k-point, =2 blocked
- * on many workgroups (default: blocked up to 544 bands, the largest it supports). */
+ * on many workgroups (default: blocked up to 576 bands, the largest it supports). */
 qm_status qm_hpsi_plan_create(const double cell[9], const int32_t grid[3], const qm_kset *ks,
                               int32_t nbnd_max, int32_t nproj, const double *vloc_r,
                               const void *beta, const double *dmat, qm_prec prec, void *stream,

@@ -26,6 +26,7 @@ void mlp_precondition(qm_hpsi_plan* p, const DJobs& jobs, const void* weights, h
 
 struct DavState {
   int nb = 0, mb = 0, k0 = 0, k1 = 0, nk = 0;
+  int nwant = 0;             // bands returned and tested for convergence (nb minus buffer bands)
   int64_t g0 = 0, npl = 0;   // G offset of k0 and plane waves of k0..k1-1 (band block base)
   ProjScratch ps;            // own projector scratch (lanes only; else the plan's)
   bool ready = false;
@@ -353,19 +354,24 @@ struct StepResult {
   bool nan = false;
 };
 
+// Every unconverged band (buffer bands too) is listed for correction; only the wanted ones
+// count towards convergence and the reported maximum.
 static void collect(qm_hpsi_plan* p, DavState* d, double tol, StepResult& r) {
   (void)p;
   for (int k = d->k0; k < d->k1; ++k) {
     if (d->done[k]) continue;
-    int nu = 0;
+    int nu = 0, nuw = 0;
     for (int n = 0; n < d->nb; ++n) {
       const double x = d->h_resn[int64_t(k) * d->nb + n];
       if (!std::isfinite(x)) r.nan = true;
-      r.max_res = std::max(r.max_res, x);
-      if (!(x <= tol)) d->h_unconv[int64_t(k) * d->nb + nu++] = n;
+      if (n < d->nwant) r.max_res = std::max(r.max_res, x);
+      if (!(x <= tol)) {
+        d->h_unconv[int64_t(k) * d->nb + nu++] = n;
+        if (n < d->nwant) ++nuw;
+      }
     }
-    r.n_unconv += nu;
-    if (nu == 0) d->done[k] = 1;
+    r.n_unconv += nuw;
+    if (nuw == 0) d->done[k] = 1;
   }
 }
 
@@ -375,12 +381,12 @@ static void write_outputs(qm_hpsi_plan* p, DavState* d, void* psi, double* eig, 
   for (int k = d->k0; k < d->k1; ++k) {
     const KInfo& ki = p->kinfo[k];
     if (psi)
-      QM_HIP(hipMemcpyAsync(reinterpret_cast<double2*>(psi) + int64_t(d->nb) * (ki.g_off - g0),
-                            d->X + int64_t(d->nb) * (ki.g_off - g0), sizeof(double2) * d->nb * ki.npw,
+      QM_HIP(hipMemcpyAsync(reinterpret_cast<double2*>(psi) + int64_t(d->nwant) * (ki.g_off - g0),
+                            d->X + int64_t(d->nb) * (ki.g_off - g0), sizeof(double2) * d->nwant * ki.npw,
                             hipMemcpyDeviceToDevice, s));
-    for (int n = 0; n < d->nb; ++n) {
-      if (eig) eig[int64_t(k - d->k0) * d->nb + n] = d->h_theta[int64_t(k) * d->mb + n];
-      if (resnorm) resnorm[int64_t(k - d->k0) * d->nb + n] = d->h_resn[int64_t(k) * d->nb + n];
+    for (int n = 0; n < d->nwant; ++n) {
+      if (eig) eig[int64_t(k - d->k0) * d->nwant + n] = d->h_theta[int64_t(k) * d->mb + n];
+      if (resnorm) resnorm[int64_t(k - d->k0) * d->nwant + n] = d->h_resn[int64_t(k) * d->nb + n];
     }
   }
   QM_HIP(hipStreamSynchronize(s));
@@ -389,9 +395,12 @@ static void write_outputs(qm_hpsi_plan* p, DavState* d, void* psi, double* eig, 
 // One Davidson iteration on k-points k0..k1-1 with the state in *slot (created or rebuilt as
 // needed).  psi points at k0's first band, eig and resnorm at k0's first entry.
 static qm_status dav_step_range(qm_hpsi_plan* p, DavState** slot, bool own_scratch, int k0, int k1,
-                                void* psi, double* eig, double* resnorm, int nb,
+                                void* psi, double* eig, double* resnorm, int nwant,
                                 const qm_dav_opts* o, int32_t* n_unconv, hipStream_t s) {
-  QM_REQUIRE(nb >= 1 && nb <= p->nbnd_max, QM_E_ARG, "need 1 <= nbnd <= nbnd_max");
+  QM_REQUIRE(nwant >= 1, QM_E_ARG, "need nbnd >= 1");
+  QM_REQUIRE(!o || o->extra_bands >= 0, QM_E_ARG, "extra_bands must be >= 0");
+  const int nb = nwant + (o ? o->extra_bands : 0);   // block size: wanted + buffer bands
+  QM_REQUIRE(nb <= p->nbnd_max, QM_E_ARG, "need nbnd + extra_bands <= nbnd_max");
   QM_REQUIRE(k0 >= 0 && k0 < k1 && k1 <= p->nk, QM_E_ARG, "k out of range");
   QM_REQUIRE(psi, QM_E_ARG, "psi must be non-NULL");
   const double tol = (o && o->tol > 0) ? o->tol : 1e-8;
@@ -404,7 +413,7 @@ static qm_status dav_step_range(qm_hpsi_plan* p, DavState** slot, bool own_scrat
   QM_REQUIRE(k1 - k0 <= kMaxSlices, QM_E_ARG, "at most 32 k-points per Davidson call");
   DavState* d = *slot;
   const bool fresh = !d || !d->ready || (o && o->restart) || d->k0 != k0 || d->k1 != k1 ||
-                     d->nb != nb || d->mb != mb;
+                     d->nb != nb || d->mb != mb || d->nwant != nwant;
   if (fresh) {
     if (!d || d->k0 != k0 || d->k1 != k1 || d->nb != nb || d->mb != mb) {
       if (d) dav_release(d);
@@ -412,6 +421,7 @@ static qm_status dav_step_range(qm_hpsi_plan* p, DavState** slot, bool own_scrat
       *slot = d = dav_create(p, k0, k1, nb, mb, own_scratch);
     }
     d->ready = false;
+    d->nwant = nwant;
     std::fill(d->m.begin(), d->m.end(), 0);
     std::fill(d->it.begin(), d->it.end(), 0);
     std::fill(d->done.begin(), d->done.end(), 0);
@@ -428,13 +438,17 @@ static qm_status dav_step_range(qm_hpsi_plan* p, DavState** slot, bool own_scrat
     for (int kk = k0; kk < k1; ++kk) {
       DJob j = make_job(p, d, kk);
       QM_HIP(hipMemcpyAsync(vrow(d, d->V, j, 0),
-                            reinterpret_cast<const double2*>(psi) + int64_t(nb) * (p->kinfo[kk].g_off - g0),
-                            sizeof(double2) * nb * j.npw, hipMemcpyDeviceToDevice, s));
+                            reinterpret_cast<const double2*>(psi) + int64_t(nwant) * (p->kinfo[kk].g_off - g0),
+                            sizeof(double2) * nwant * j.npw, hipMemcpyDeviceToDevice, s));
       j.m = nb;
       j.m_old = 0;
       j.nu = nb;
       jobs.j[jobs.n++] = j;
       sl.push_back(KSlice{kk, nb, j.voff, j.voff});
+    }
+    if (nb > nwant) {   // buffer bands: a fixed pseudo-random start
+      hipLaunchKernelGGL(k_start_block, dim3(nb - nwant, jobs.n), dim3(256), 0, s, jobs, d->V, nwant);
+      QM_HIP(hipGetLastError());
     }
     if (!orthonormalise(p, d, jobs, s)) throw Error(QM_E_NOT_SPD, "start block is linearly dependent");
     timed_apply(p, d, sl, d->V, d->HV, s, d->lowp);
@@ -446,7 +460,7 @@ static qm_status dav_step_range(qm_hpsi_plan* p, DavState** slot, bool own_scrat
     // rebuilding the basis from the Ritz vectors with float64 H
     double maxres = 0.0;
     for (int kk = k0; kk < k1; ++kk)
-      for (int n = 0; n < nb; ++n) maxres = std::max(maxres, d->h_resn[int64_t(kk) * nb + n]);
+      for (int n = 0; n < nwant; ++n) maxres = std::max(maxres, d->h_resn[int64_t(kk) * nb + n]);
     // switch when below switch_resid, or when the reduced-precision H stops making progress
     // (max residual not down by 20% over the last four iterations)
     bool stagnant = false;
@@ -785,7 +799,7 @@ qm_status qm_davidson_solve(qm_hpsi_plan* plan, int32_t k, void* psi, double* ei
       if (!d) continue;
       for (int kk = d->k0; kk < d->k1; ++kk) {
         itmax = std::max(itmax, d->it[kk]);
-        for (int n = 0; n < d->nb; ++n) mr = std::max(mr, d->h_resn[int64_t(kk) * d->nb + n]);
+        for (int n = 0; n < d->nwant; ++n) mr = std::max(mr, d->h_resn[int64_t(kk) * d->nb + n]);
       }
       stats->n_hpsi_bands += d->n_hpsi;
       stats->n_hpsi_bands_lowp += d->n_hpsi_lowp;

@@ -52,7 +52,9 @@ __global__ void k_backtransform(DJobs jobs, const double2* Aw, const double2* ta
                                 const double* scw, double2* Zout, int cols);
 __global__ void k_chol_inv(DJobs jobs, double2* Gm, double2* Wm, int32_t* info);
 constexpr int kCholBlk = 16;        // block size of the many-workgroup Cholesky
-constexpr int kCholMaxBlocked = 544; // largest band count whose Linv column block fits in LDS
+// largest band count whose Linv column block fits in LDS next to the kernel's static
+// 13 KiB: 36 blocks of 16 x 16 complex (147 KiB)
+constexpr int kCholMaxBlocked = 576;
 __global__ void k_chol_prep(DJobs jobs, const double2* Gm, double* dmax, int32_t* info);
 __global__ void k_chol_col(DJobs jobs, int jb, double2* Gm, double2* Ldw, const double* dmaxw,
                            int32_t* info);
@@ -61,6 +63,7 @@ __global__ void k_chol_inv_cols(DJobs jobs, const double2* Gm, const double2* Ld
 __global__ void k_residual(DJobs jobs, const double2* X, const double2* HX, double2* Rr,
                            const double* theta, const double* kin_all, const int64_t* goff,
                            double* resn, double* tkin);
+__global__ void k_start_block(DJobs jobs, double2* V, int first);
 __global__ void k_teter(DJobs jobs, const double2* Rr, double2* V, const int32_t* unconv,
                         const double* tkin, const double* kin_all, const int64_t* goff);
 }  // namespace qm

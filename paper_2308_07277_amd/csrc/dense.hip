@@ -1254,6 +1254,29 @@ __global__ void __launch_bounds__(256) k_chol_inv_cols(DJobs jobs, const double2
   }
 }
 
+// ---------------------------------------------------------------- buffer-band start
+// Basis rows [first, first + gridDim.x) of every job (V row-major [row][npw_k] at J.voff)
+// filled with a fixed pseudo-random complex block, entries in [-0.5, 0.5)^2: the start
+// vectors of buffer bands, orthonormalised against the caller's block afterwards.
+__device__ __forceinline__ uint32_t mix32(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x7FEB352Du;
+  h ^= h >> 15;
+  h *= 0x846CA68Bu;
+  h ^= h >> 16;
+  return h;
+}
+__global__ void __launch_bounds__(256) k_start_block(DJobs jobs, double2* __restrict__ V, int first) {
+  const DJob& J = jobs.j[blockIdx.y];
+  const int row = first + blockIdx.x;
+  double2* v = V + J.voff + int64_t(row) * J.npw;
+  const uint32_t base = mix32(uint32_t(J.k) * 0x9E3779B1u + uint32_t(row) * 0x85EBCA77u + 0x165667B1u);
+  for (int g = threadIdx.x; g < J.npw; g += 256) {
+    const uint32_t h1 = mix32(base ^ uint32_t(2 * g + 1)), h2 = mix32(base ^ uint32_t(2 * g + 2) * 0xC2B2AE3Du);
+    v[g] = make_double2(double(h1) * 2.3283064365386963e-10 - 0.5, double(h2) * 2.3283064365386963e-10 - 0.5);
+  }
+}
+
 // ---------------------------------------------------------------- residuals
 // One workgroup per (job, band): r = HX - theta X into R, ||r||, <x|T|x>/<x|x>.
 __global__ void __launch_bounds__(256) k_residual(DJobs jobs, const double2* __restrict__ X,

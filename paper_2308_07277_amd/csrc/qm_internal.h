@@ -141,7 +141,7 @@ struct qm_hpsi_plan {
   // (one launch per step), 0 chosen by basis size (environment QM_TRIDIAG_MODE).
   int32_t trd_forced = 0;
   // CholQR Cholesky + inverse: 1 one workgroup per k-point, 2 blocked on many workgroups,
-  // 0 blocked up to 544 bands (environment QM_CHOL_MODE).
+  // 0 blocked up to 576 bands (environment QM_CHOL_MODE).
   int32_t chol_forced = 0;
 };
 

@@ -217,7 +217,7 @@ def test_tridiagonalisation_paths(mode, monkeypatch):
 def test_cholesky_paths(mode, monkeypatch):
     """QM_CHOL_MODE=1 factors the CholQR Gram matrices (and inverts the factor) in one
     workgroup per k-point; 2 uses the blocked kernels (16-wide Crout block columns, one
-    workgroup per column block of the inverse), the default up to 544 bands.  Both must
+    workgroup per column block of the inverse), the default up to 576 bands.  Both must
     reach the dense eigenvalues within 1e-8 Ha with orthonormal vectors on the 8-atom cells
     (8 bands: one ragged block; 32 bands: two blocks; four k-points per launch)."""
     monkeypatch.setenv("QM_CHOL_MODE", mode)
@@ -235,3 +235,44 @@ def test_cholesky_paths(mode, monkeypatch):
             lam = np.linalg.eigvalsh(dense)[:w.nbnd]
             assert np.abs(eig[ik] - lam).max() <= 1e-8
             np.testing.assert_allclose(xs[ik].conj() @ xs[ik].T, np.eye(w.nbnd), atol=1e-10)
+
+
+def test_buffer_bands():
+    """extra_bands: the block carries nbnd + extra Ritz vectors, only the nbnd lowest decide
+    convergence and are returned.  On the 2-atom cell the 8 requested bands cut a triply
+    degenerate level (8th/9th/10th), which stalls the highest wanted band; four buffer
+    bands must give the same dense eigenvalues (1e-8 Ha) with orthonormal vectors in fewer
+    iterations.  The 8-atom cell (4 k) with four buffer bands must match too."""
+    import torch
+    import paper_2308_07277_amd as qm
+    w = workload.make_workload("c1")
+    plan, a = make_plan(w, w.nbnd + 4)
+    h, beta = _oracle_h(w, a, 0)
+    dense = ham.dense_h(w.cell, w.grid, w.k_cryst[0], w.miller[0], a["vloc"], beta, a["dmat"])
+    lam = np.linalg.eigvalsh(dense)[:w.nbnd]
+    its = {}
+    for extra in (0, 4):
+        eig, res, stats, st, x = _solve(plan, w, w.nbnd, _start(w, w.nbnd), tol=1e-9, extra_bands=extra)
+        print("c1 extra", extra, stats)
+        assert st == 0 and eig.shape == (1, w.nbnd) and res.max() <= 1e-9
+        assert np.abs(eig[0] - lam).max() <= 1e-8
+        xs = x.reshape(w.nbnd, -1)
+        np.testing.assert_allclose(xs.conj() @ xs.T, np.eye(w.nbnd), atol=1e-10)
+        its[extra] = stats["iterations"]
+    assert its[4] < its[0]
+    with pytest.raises(qm.QmError) as e:
+        _solve(plan, w, w.nbnd, _start(w, w.nbnd), extra_bands=5)   # 8 + 5 > nbnd_max = 12
+    assert e.value.code == qm.QM_E_ARG
+    with pytest.raises(qm.QmError) as e:
+        _solve(plan, w, w.nbnd, _start(w, w.nbnd), extra_bands=-1)
+    assert e.value.code == qm.QM_E_ARG
+    w = workload.make_workload("c2")
+    plan, a = make_plan(w, w.nbnd + 4)
+    eig, res, stats, st, x = _solve(plan, w, w.nbnd, _start(w, w.nbnd), tol=1e-8, extra_bands=4)
+    assert st == 0
+    xs = split_k(x, w, w.nbnd)
+    for ik in range(w.nk):
+        h, beta = _oracle_h(w, a, ik)
+        dense = ham.dense_h(w.cell, w.grid, w.k_cryst[ik], w.miller[ik], a["vloc"], beta, a["dmat"])
+        assert np.abs(eig[ik] - np.linalg.eigvalsh(dense)[:w.nbnd]).max() <= 1e-8
+        np.testing.assert_allclose(xs[ik].conj() @ xs[ik].T, np.eye(w.nbnd), atol=1e-10)
