@@ -89,25 +89,30 @@ __device__ __forceinline__ int find_prob(const B& b, int bid) {
 }
 
 // ------------------------------------------------------------------ CN, split-K partials
-template <typename T, typename SA, typename SB>
+// Output tile TM x TN: 64 x 64, or 128 x 32 when the column count is a multiple of 32 but
+// not of 64 (e.g. 160 bands: no padded columns); four waves of 32 x 32 each.
+template <typename T, typename SA, typename SB, int TM, int TN>
 __global__ void __launch_bounds__(256) k_cgemm_cn(const CNBatch batch, int nsplit,
                                                   cplx<T>* __restrict__ work) {
   typedef typename Acc<T>::type AV;
-  __shared__ cplx<T> As[BT][KC + 1];
-  __shared__ cplx<T> Bs[BT][KC + 1];
+  constexpr int NAE = TM * KC / 256, NBE = TN * KC / 256;   // K values per thread and chunk
+  constexpr int WM = TM / 32;                               // waves along the rows
+  __shared__ cplx<T> As[TM][KC + 1];
+  __shared__ cplx<T> Bs[TN][KC + 1];
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const int pi = find_prob(batch, lb);
   const CNDev& P = batch.p[pi];
   // row tiles fastest: the row tiles of one (column tile, K split) share the B slab
   const int bid = lb - P.blk0, rest = bid / P.tm;
   const int split = rest % nsplit;
-  const int i0 = (bid % P.tm) * BT, j0 = (rest / nsplit) * BT;
+  const int i0 = (bid % P.tm) * TM, j0 = (rest / nsplit) * TN;
   const int nch = (P.K + KC - 1) / KC;
   const int per = (nch + nsplit - 1) / nsplit;
   const int c0 = split * per, c1 = min(nch, c0 + per);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wi = (wave & 1) * 32, wj = (wave >> 1) * 32;
-  const int lrow = tid >> 2, lseg = (tid & 3) * 4;
+  const int wi = (wave % WM) * 32, wj = (wave / WM) * 32;
+  const int larow = tid / (KC / NAE), laseg = (tid % (KC / NAE)) * NAE;
+  const int lbrow = tid / (KC / NBE), lbseg = (tid % (KC / NBE)) * NBE;
   const SA* A = reinterpret_cast<const SA*>(P.A);
   const SB* B = reinterpret_cast<const SB*>(P.B);
   AV cr[2][2], ci[2][2];
@@ -118,26 +123,37 @@ __global__ void __launch_bounds__(256) k_cgemm_cn(const CNBatch batch, int nspli
       cr[a][b] = AV{0, 0, 0, 0};
       ci[a][b] = AV{0, 0, 0, 0};
     }
-  const bool arow = (i0 + lrow) < P.M, brow = (j0 + lrow) < P.N;
+  const bool arow = (i0 + larow) < P.M, brow = (j0 + lbrow) < P.N;
   // rows past the matrix read row i0 / j0 (which exists) and are zeroed after the load
-  const SA* Ar = A + int64_t(arow ? i0 + lrow : i0) * P.lda;
-  const SB* Br = B + int64_t(brow ? j0 + lrow : j0) * P.ldb;
+  const SA* Ar = A + int64_t(arow ? i0 + larow : i0) * P.lda;
+  const SB* Br = B + int64_t(brow ? j0 + lbrow : j0) * P.ldb;
   // the next chunk's operands are loaded into registers while this chunk's MFMAs run
-  cplx<T> pa[4], pb[4];
+  cplx<T> pa[NAE], pb[NBE];
   auto fetch = [&](int c) {
-    const int kb = c * KC + lseg;
-    if (kb + 4 <= P.K) {   // whole run inside K: one bounds test per row
+    const int ka = c * KC + laseg, kb = c * KC + lbseg;
+    if (ka + NAE <= P.K) {   // whole run inside K: one bounds test per row
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const cplx<T> av = ld<T>(Ar + kb + q), bv = ld<T>(Br + kb + q);
+      for (int q = 0; q < NAE; ++q) {
+        const cplx<T> av = ld<T>(Ar + ka + q);
         pa[q] = arow ? av : cplx<T>{T(0), T(0)};
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NAE; ++q) {
+        const int g = ka + q;
+        pa[q] = (arow && g < P.K) ? ld<T>(Ar + g) : cplx<T>{T(0), T(0)};
+      }
+    }
+    if (kb + NBE <= P.K) {
+#pragma unroll
+      for (int q = 0; q < NBE; ++q) {
+        const cplx<T> bv = ld<T>(Br + kb + q);
         pb[q] = brow ? bv : cplx<T>{T(0), T(0)};
       }
     } else {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < NBE; ++q) {
         const int g = kb + q;
-        pa[q] = (arow && g < P.K) ? ld<T>(Ar + g) : cplx<T>{T(0), T(0)};
         pb[q] = (brow && g < P.K) ? ld<T>(Br + g) : cplx<T>{T(0), T(0)};
       }
     }
@@ -145,10 +161,9 @@ __global__ void __launch_bounds__(256) k_cgemm_cn(const CNBatch batch, int nspli
   if (c0 < c1) fetch(c0);
   for (int c = c0; c < c1; ++c) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      As[lrow][lseg + q] = pa[q];
-      Bs[lrow][lseg + q] = pb[q];
-    }
+    for (int q = 0; q < NAE; ++q) As[larow][laseg + q] = pa[q];
+#pragma unroll
+    for (int q = 0; q < NBE; ++q) Bs[lbrow][lbseg + q] = pb[q];
     __syncthreads();
     if (c + 1 < c1) fetch(c + 1);
 #pragma unroll
@@ -213,20 +228,25 @@ __global__ void k_cn_reduce(const CNOutBatch outs, int nsplit,
 }
 
 // ------------------------------------------------------------------ EX
-template <typename T, typename SW, typename SA>
+// Output tile TM x TN (64 x 64, or 32 x 128 when the row count is a multiple of 32 but not
+// of 64, e.g. 160 bands: no padded rows); four waves of 32 x 32 each.
+template <typename T, typename SW, typename SA, int TM, int TN>
 __global__ void __launch_bounds__(256) k_cgemm_ex(const EXBatch batch, double alpha, double beta) {
   typedef typename Acc<T>::type AV;
-  __shared__ cplx<T> Ws[KC][BT + 1];
-  __shared__ cplx<T> As[KC][BT + 1];
+  constexpr int NWE = KC * TM / 256, NAE = KC * TN / 256;   // elements per thread and chunk
+  constexpr int WM = TM / 32;                               // waves along the rows
+  __shared__ cplx<T> Ws[KC][TM + 1];
+  __shared__ cplx<T> As[KC][TN + 1];
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const int pi = find_prob(batch, lb);
   const EXDev& P = batch.p[pi];
   // row tiles fastest: the row tiles of one column tile share the A slab
   const int tile = lb - P.blk0;
-  const int m0 = (tile % P.tm) * BT, n0 = (tile / P.tm) * BT;
+  const int m0 = (tile % P.tm) * TM, n0 = (tile / P.tm) * TN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wi = (wave & 1) * 32, wj = (wave >> 1) * 32;
-  const int lr = tid >> 4, lc = (tid & 15) * 4;
+  const int wi = (wave % WM) * 32, wj = (wave / WM) * 32;
+  const int lrw = tid / (TM / NWE), lcw = (tid % (TM / NWE)) * NWE;
+  const int lra = tid / (TN / NAE), lca = (tid % (TN / NAE)) * NAE;
   const SW* Wp = reinterpret_cast<const SW*>(P.W);
   const SA* Ap = reinterpret_cast<const SA*>(P.A);
   AV cr[2][2], ci[2][2];
@@ -239,32 +259,36 @@ __global__ void __launch_bounds__(256) k_cgemm_ex(const EXBatch batch, double al
     }
   const int nch = (P.K + KC - 1) / KC;
   // the next chunk's operands are loaded into registers while this chunk's MFMAs run
-  cplx<T> pw[4], pa[4];
+  cplx<T> pw[NWE], pa[NAE];
   auto fetch = [&](int c) {
-    const int i = c * KC + lr;
-    const bool irow = i < P.K;
-    if (irow && m0 + lc + 4 <= P.M && n0 + lc + 4 <= P.N) {   // interior: no element tests
+    const int iw = c * KC + lrw, ia = c * KC + lra;
+    if (iw < P.K && m0 + lcw + NWE <= P.M) {   // interior: no element tests
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        pw[q] = ld<T>(Wp + int64_t(i) * P.ldw + m0 + lc + q);
-        pa[q] = ld<T>(Ap + int64_t(i) * P.lda + n0 + lc + q);
-      }
+      for (int q = 0; q < NWE; ++q) pw[q] = ld<T>(Wp + int64_t(iw) * P.ldw + m0 + lcw + q);
     } else {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int m = m0 + lc + q, n = n0 + lc + q;
-        pw[q] = (irow && m < P.M) ? ld<T>(Wp + int64_t(i) * P.ldw + m) : cplx<T>{T(0), T(0)};
-        pa[q] = (irow && n < P.N) ? ld<T>(Ap + int64_t(i) * P.lda + n) : cplx<T>{T(0), T(0)};
+      for (int q = 0; q < NWE; ++q) {
+        const int m = m0 + lcw + q;
+        pw[q] = (iw < P.K && m < P.M) ? ld<T>(Wp + int64_t(iw) * P.ldw + m) : cplx<T>{T(0), T(0)};
+      }
+    }
+    if (ia < P.K && n0 + lca + NAE <= P.N) {
+#pragma unroll
+      for (int q = 0; q < NAE; ++q) pa[q] = ld<T>(Ap + int64_t(ia) * P.lda + n0 + lca + q);
+    } else {
+#pragma unroll
+      for (int q = 0; q < NAE; ++q) {
+        const int n = n0 + lca + q;
+        pa[q] = (ia < P.K && n < P.N) ? ld<T>(Ap + int64_t(ia) * P.lda + n) : cplx<T>{T(0), T(0)};
       }
     }
   };
   if (nch > 0) fetch(0);
   for (int c = 0; c < nch; ++c) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      Ws[lr][lc + q] = pw[q];
-      As[lr][lc + q] = pa[q];
-    }
+    for (int q = 0; q < NWE; ++q) Ws[lrw][lcw + q] = pw[q];
+#pragma unroll
+    for (int q = 0; q < NAE; ++q) As[lra][lca + q] = pa[q];
     __syncthreads();
     if (c + 1 < nch) fetch(c + 1);
 #pragma unroll
@@ -630,9 +654,17 @@ void zgemm_cn_batched(const std::vector<GemmCN>& probs, double alpha, double bet
     CNBatch d{};
     CNOutBatch o{};
     d.n = o.n = int32_t(n);
+    // tile shape: 128 x 32 where it pads fewer output elements than 64 x 64 (bf16: 64 x 64)
+    int64_t pad64 = 0, padw = 0;
+    for (const GemmCN& g : sub) {
+      pad64 += int64_t((g.M + 63) / 64 * 64) * ((g.N + 63) / 64 * 64);
+      padw += int64_t((g.M + 127) / 128 * 128) * ((g.N + 31) / 32 * 32);
+    }
+    const bool wide = lp != 2 && padw * 20 < pad64 * 19;   // at least 5% less padded work
+    const int tm_ = wide ? 128 : 64, tn_ = wide ? 32 : 64;
     int64_t tiles = 0, maxK = 0;
     for (const GemmCN& g : sub) {
-      tiles += int64_t((g.M + BT - 1) / BT) * ((g.N + BT - 1) / BT);
+      tiles += int64_t((g.M + tm_ - 1) / tm_) * ((g.N + tn_ - 1) / tn_);
       maxK = std::max<int64_t>(maxK, g.K);
     }
     int64_t mn = 0;
@@ -645,7 +677,7 @@ void zgemm_cn_batched(const std::vector<GemmCN>& probs, double alpha, double bet
       CNDev& x = d.p[i];
       x.A = g.A; x.B = g.B;
       x.M = g.M; x.N = g.N; x.K = g.K;
-      x.tm = (g.M + BT - 1) / BT; x.tn = (g.N + BT - 1) / BT;
+      x.tm = (g.M + tm_ - 1) / tm_; x.tn = (g.N + tn_ - 1) / tn_;
       x.blk0 = int32_t(blk);
       x.lda = g.lda; x.ldb = g.ldb;
       x.work_off = woff;
@@ -659,16 +691,24 @@ void zgemm_cn_batched(const std::vector<GemmCN>& probs, double alpha, double bet
                "GEMM split-K workspace too small");
     const int rb = int(std::min<int64_t>((e0 + 255) / 256, 8192));
     if (lp == 0) {
-      hipLaunchKernelGGL((k_cgemm_cn<double, double2, double2>), dim3(unsigned(blk)), dim3(256), 0, s,
-                         d, nsplit, reinterpret_cast<cplx<double>*>(work));
+      if (wide)
+        hipLaunchKernelGGL((k_cgemm_cn<double, double2, double2, 128, 32>), dim3(unsigned(blk)), dim3(256),
+                           0, s, d, nsplit, reinterpret_cast<cplx<double>*>(work));
+      else
+        hipLaunchKernelGGL((k_cgemm_cn<double, double2, double2, 64, 64>), dim3(unsigned(blk)), dim3(256),
+                           0, s, d, nsplit, reinterpret_cast<cplx<double>*>(work));
       QM_HIP(hipGetLastError());
       if (ev) ev->mark(stage0);
       hipLaunchKernelGGL(k_cn_reduce<double>, dim3(rb), dim3(256), 0, s, o, nsplit,
                          reinterpret_cast<const cplx<double>*>(work), alpha, beta_c, e0);
     } else {
       if (lp == 1)
-        hipLaunchKernelGGL((k_cgemm_cn<float, float2, double2>), dim3(unsigned(blk)), dim3(256), 0, s,
-                           d, nsplit, reinterpret_cast<cplx<float>*>(work));
+        if (wide)
+          hipLaunchKernelGGL((k_cgemm_cn<float, float2, double2, 128, 32>), dim3(unsigned(blk)), dim3(256),
+                             0, s, d, nsplit, reinterpret_cast<cplx<float>*>(work));
+        else
+          hipLaunchKernelGGL((k_cgemm_cn<float, float2, double2, 64, 64>), dim3(unsigned(blk)), dim3(256),
+                             0, s, d, nsplit, reinterpret_cast<cplx<float>*>(work));
       else
         hipLaunchKernelGGL(k_cgemm_cn_bf16, dim3(unsigned(blk)), dim3(256), 0, s, d, nsplit,
                            reinterpret_cast<cplx<float>*>(work));
@@ -686,6 +726,15 @@ void zgemm_ex_batched(const std::vector<GemmEX>& probs, double alpha, double bet
                       int lp) {
   for (size_t base = 0; base < probs.size(); base += MAXP) {
     const size_t n = std::min<size_t>(MAXP, probs.size() - base);
+    // tile shape: 32 x 128 where it pads fewer output elements than 64 x 64 (bf16: 64 x 64)
+    int64_t pad64 = 0, pad32 = 0;
+    for (size_t i = 0; i < n; ++i) {
+      const GemmEX& g = probs[base + i];
+      pad64 += int64_t((g.M + 63) / 64 * 64) * ((g.N + 63) / 64 * 64);
+      pad32 += int64_t((g.M + 31) / 32 * 32) * ((g.N + 127) / 128 * 128);
+    }
+    const bool narrow = lp != 2 && pad32 * 20 < pad64 * 19;   // at least 5% less padded work
+    const int tm_ = narrow ? 32 : 64, tn_ = narrow ? 128 : 64;
     EXBatch d{};
     d.n = int32_t(n);
     int64_t blk = 0;
@@ -694,18 +743,24 @@ void zgemm_ex_batched(const std::vector<GemmEX>& probs, double alpha, double bet
       EXDev& x = d.p[i];
       x.W = g.W; x.A = g.A; x.Y = g.Y;
       x.M = g.M; x.N = g.N; x.K = g.K;
-      x.tm = (g.M + BT - 1) / BT; x.tn = (g.N + BT - 1) / BT;
+      x.tm = (g.M + tm_ - 1) / tm_; x.tn = (g.N + tn_ - 1) / tn_;
       x.blk0 = int32_t(blk);
       x.ldw = g.ldw; x.lda = g.lda; x.ldy = g.ldy;
       blk += int64_t(x.tm) * x.tn;
     }
     if (blk == 0) continue;
-    if (lp == 0)
-      hipLaunchKernelGGL((k_cgemm_ex<double, double2, double2>), dim3(unsigned(blk)), dim3(256), 0, s,
-                         d, alpha, beta_y);
+    if (lp == 0 && narrow)
+      hipLaunchKernelGGL((k_cgemm_ex<double, double2, double2, 32, 128>), dim3(unsigned(blk)), dim3(256), 0,
+                         s, d, alpha, beta_y);
+    else if (lp == 0)
+      hipLaunchKernelGGL((k_cgemm_ex<double, double2, double2, 64, 64>), dim3(unsigned(blk)), dim3(256), 0,
+                         s, d, alpha, beta_y);
+    else if (lp == 1 && narrow)
+      hipLaunchKernelGGL((k_cgemm_ex<float, double2, float2, 32, 128>), dim3(unsigned(blk)), dim3(256), 0,
+                         s, d, alpha, beta_y);
     else if (lp == 1)
-      hipLaunchKernelGGL((k_cgemm_ex<float, double2, float2>), dim3(unsigned(blk)), dim3(256), 0, s,
-                         d, alpha, beta_y);
+      hipLaunchKernelGGL((k_cgemm_ex<float, double2, float2, 64, 64>), dim3(unsigned(blk)), dim3(256), 0,
+                         s, d, alpha, beta_y);
     else
       hipLaunchKernelGGL(k_cgemm_ex_bf16, dim3(unsigned(blk)), dim3(256), 0, s, d, alpha, beta_y);
     QM_HIP(hipGetLastError());
