@@ -343,8 +343,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(k-point and G-sphere sharding are described in the design notes).", file=sys.stderr)
+        print("bench.py measures one GPU only: the library runs on a single GPU "
+              "(splitting the k-points over several GPUs is not implemented).", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -42,6 +42,7 @@ struct DavState {
   EigWork ew{};
   double* chol_dmax = nullptr;   // [k] largest Gram diagonal (Cholesky pivot test)
   double2* chol_ld = nullptr;    // [k][nb / 16 rounded up][16][16] diagonal blocks of L
+  double2* bt_t = nullptr;       // [k][mb / 32 rounded up][32][32] T factors of the back-transform
   void* work = nullptr;
   int64_t work_bytes = 0;
   double *h_resn = nullptr, *h_theta = nullptr;
@@ -59,7 +60,7 @@ static void dav_release(DavState* d) {
   void* dev[] = {d->V, d->HV, d->X, d->HX, d->R, d->TS, d->Hs, d->Aw, d->Z, d->tau, d->Cw, d->G,
                  d->W, d->theta, d->d, d->e, d->resn, d->tkin, d->yw, d->fw, d->unconv, d->info,
                  d->goff, d->work, d->estar, d->ps.part, d->trd.v, d->trd.w, d->trd.p, d->trd.cnt,
-                 d->ew.sc, d->ew.nrm, d->chol_dmax, d->chol_ld};
+                 d->ew.sc, d->ew.nrm, d->chol_dmax, d->chol_ld, d->bt_t};
   for (void* q : dev)
     if (q) (void)hipFree(q);
   void* host[] = {d->h_resn, d->h_theta, d->h_unconv, d->h_info};
@@ -135,6 +136,7 @@ static DavState* dav_create(qm_hpsi_plan* p, int k0, int k1, int nb, int mb, boo
     d->ew.nrm = dalloc<double>(nk);
     d->chol_dmax = dalloc<double>(nk);
     d->chol_ld = dalloc<double2>(nk * size_t((nb + kCholBlk - 1) / kCholBlk) * kCholBlk * kCholBlk);
+    d->bt_t = dalloc<double2>(nk * size_t((mb + kBtBlk - 1) / kBtBlk) * kBtBlk * kBtBlk);
     std::vector<int64_t> go(nk);
     for (size_t k = 0; k < nk; ++k) go[k] = p->kinfo[k].g_off;
     QM_HIP(hipMemcpy(d->goff, go.data(), nk * sizeof(int64_t), hipMemcpyHostToDevice));
@@ -147,7 +149,7 @@ static DavState* dav_create(qm_hpsi_plan* p, int k0, int k1, int nb, int mb, boo
     for (hipEvent_t& e : d->ev) QM_HIP(hipEventCreate(&e));
     const void* big[] = {reinterpret_cast<const void*>(&k_tridiag), reinterpret_cast<const void*>(&k_eig_vals),
                          reinterpret_cast<const void*>(&k_chol_inv_cols),
-                         reinterpret_cast<const void*>(&k_backtransform)};
+                         reinterpret_cast<const void*>(&k_bt_apply)};
     for (const void* f : big) QM_HIP(allow_full_lds(f));
     d->m.assign(nk, 0);
     d->it.assign(nk, 0);
@@ -301,11 +303,15 @@ static void rayleigh_ritz(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipSt
     hipLaunchKernelGGL(k_eig_orth, dim3(nw, jobs.n), dim3(256), 0, s, jobs, d->theta, d->yw, d->ew);
   }
   QM_HIP(hipGetLastError());
-  // Z slice + one reflector must fit in the 160 KiB of LDS
-  const int cols = std::max(1, std::min(8, int((160 * 1024 - 1024) / (16 * int64_t(d->mb))) - 1));
-  hipLaunchKernelGGL(k_backtransform, dim3((d->nb + cols - 1) / cols, jobs.n), dim3(256),
-                     size_t(d->mb) * (cols + 1) * sizeof(double2), s, jobs, d->Aw, d->tau, d->yw,
-                     d->ew.sc, d->Z, cols);
+  // blocked back-transform: T factors of every 32-reflector block, then the eigenvector
+  // slices (Z slice, partial sums and W must fit in the 160 KiB of LDS next to the 17 KiB T)
+  const int nblk_bt = (mmax - 1 + kBtBlk - 1) / kBtBlk;
+  if (nblk_bt > 0)
+    hipLaunchKernelGGL(k_bt_tfactor, dim3(nblk_bt, jobs.n), dim3(256), 0, s, jobs, d->Aw, d->tau, d->bt_t);
+  const int64_t per_col = (int64_t(d->mb) + 9 * kBtBlk) * int64_t(sizeof(double2));
+  const int cols = std::max(1, std::min<int>(8, int((160 * 1024 - 18 * 1024) / per_col)));
+  hipLaunchKernelGGL(k_bt_apply, dim3((d->nb + cols - 1) / cols, jobs.n), dim3(256),
+                     size_t(per_col) * cols, s, jobs, d->Aw, d->bt_t, d->yw, d->ew.sc, d->Z, cols);
   QM_HIP(hipGetLastError());
   QM_HIP(hipEventRecord(d->ev[3], s));
   std::vector<GemmEX> ex;

@@ -48,8 +48,10 @@ __global__ void k_eig_vals(DJobs jobs, const double* dd, const double* ee, doubl
 __global__ void k_eig_inviter(DJobs jobs, const double* dd, const double* ee, const double* theta,
                               double* yw, double* fw, EigWork ew, int step);
 __global__ void k_eig_orth(DJobs jobs, const double* theta, double* yw, EigWork ew);
-__global__ void k_backtransform(DJobs jobs, const double2* Aw, const double2* tau, const double* yw,
-                                const double* scw, double2* Zout, int cols);
+__global__ void k_bt_tfactor(DJobs jobs, const double2* Aw, const double2* tau, double2* Tw);
+__global__ void k_bt_apply(DJobs jobs, const double2* Aw, const double2* Tw, const double* yw,
+                           const double* scw, double2* Zout, int cols);
+constexpr int kBtBlk = 32;   // reflectors per block of the blocked back-transform
 __global__ void k_chol_inv(DJobs jobs, double2* Gm, double2* Wm, int32_t* info);
 constexpr int kCholBlk = 16;        // block size of the many-workgroup Cholesky
 // largest band count whose Linv column block fits in LDS next to the kernel's static

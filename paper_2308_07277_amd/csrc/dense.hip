@@ -10,7 +10,8 @@
 //                 multisection, eigenvectors by inverse iteration (re-orthogonalised
 //                 inside clusters of close eigenvalues, so degenerate levels get
 //                 orthonormal vectors)
-//   k_backtransform  eigenvectors back through the reflectors
+//   k_bt_tfactor, k_bt_apply  eigenvectors back through the reflectors, 32 at a time
+//                 (compact WY form)
 //   k_chol_inv    Cholesky G = L L^H of a Gram matrix and W = conj(L^-1)^T for the
 //                 CholQR update T <- L^-1 T
 //   k_residual    r = HX - theta X, ||r||, band kinetic energy <x|T|x>
@@ -936,64 +937,167 @@ __global__ void __launch_bounds__(256) k_eig_orth(DJobs jobs, const double* __re
   }
 }
 
-// Z = Q y with Q = H_0 H_1 ... H_{m-2}: one workgroup per (slice of cols columns, k); the
-// slice of Z lives in LDS while every reflector streams through.  Z[k][i][n] complex; y
-// column n is Y[k][.][n] * sc[k][n].
-constexpr int BT_COLS = 8;   // upper bound of cols
-__global__ void __launch_bounds__(256) k_backtransform(DJobs jobs, const double2* __restrict__ Aw,
-                                                       const double2* __restrict__ tau,
-                                                       const double* __restrict__ yw,
-                                                       const double* __restrict__ scw,
-                                                       double2* __restrict__ Zout, int cols) {
-  extern __shared__ double2 shz[];   // [mb][BT_COLS] slice, then [mb] reflector
+// Blocked back-transform (compact WY form of 32 reflectors at a time):
+//   H_j0 ... H_j0+b-1 = I - V T V^H  (V: the b reflectors as columns, T upper triangular,
+//   T_ii = tau_i, T[0:i, i] = -tau_i T[0:i, 0:i] (V[:, 0:i]^H v_i)),
+// applied to the eigenvector block from the last block to the first: Z -= V (T (V^H Z)).
+// Reflector q of a block (global j = j0 + q) is v[j+1] = 1, v[r] = A[r][j] below, 0 above.
+constexpr int kBtB = kBtBlk;
+
+__device__ __forceinline__ double2 bt_v(const double2* A, int mb, int r, int j) {
+  const double2 x = A[int64_t(max(r, j + 1)) * mb + j];   // clamped: r >= j + 1 always exists
+  return make_double2(r > j + 1 ? x.x : (r == j + 1 ? 1.0 : 0.0), r > j + 1 ? x.y : 0.0);
+}
+
+// T of every block: grid (blocks, jobs), 256 threads.
+__global__ void __launch_bounds__(256) k_bt_tfactor(DJobs jobs, const double2* __restrict__ Aw,
+                                                    const double2* __restrict__ tau,
+                                                    double2* __restrict__ Tw) {
+  constexpr int B = kBtB;
+  __shared__ double2 sV[B][B + 1];   // a chunk of 32 rows of the block's reflectors
+  __shared__ double2 sG[B][B + 1];   // Gram V^H V
+  __shared__ double2 sT[B][B + 1];
   const DJob& J = jobs.j[blockIdx.y];
-  const int mb = jobs.mb, nb = jobs.nb, m = J.m;
+  const int mb = jobs.mb, m = J.m, k = J.k, nref = m - 1;
+  const int j0 = blockIdx.x * B;
+  if (j0 >= nref) return;
+  const int bb = min(B, nref - j0);
+  const double2* A = Aw + int64_t(k) * mb * mb;
+  const int tid = threadIdx.x;
+  // thread (p, q) pairs: p = tid / 8 .. in steps; 4 entries of G each
+  double2 g[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) g[e] = make_double2(0.0, 0.0);
+  for (int r0 = j0 + 1; r0 < m; r0 += B) {
+    for (int e = tid; e < B * B; e += 256) {
+      const int rr = e / B, q = e % B, r = min(r0 + rr, m - 1);
+      sV[rr][q] = keep(bt_v(A, mb, r, j0 + min(q, bb - 1)), r0 + rr < m && q < bb);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int idx = tid + 256 * e, p = idx / B, q = idx % B;
+#pragma unroll 8
+      for (int rr = 0; rr < B; ++rr) g[e] = cadd2(g[e], cmul2(cconj(sV[rr][p]), sV[rr][q]));
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int idx = tid + 256 * e;
+    sG[idx / B][idx % B] = g[e];
+  }
+  for (int e = tid; e < B * B; e += 256) sT[e / B][e % B] = make_double2(0.0, 0.0);
+  __syncthreads();
+  const double2* tk = tau + int64_t(k) * mb;
+  if (tid == 0) sT[0][0] = tk[j0];
+  __syncthreads();
+  for (int i = 1; i < bb; ++i) {
+    const double2 ti = tk[j0 + i];
+    double2 s = make_double2(0.0, 0.0);
+    if (tid < i) {
+      for (int q = tid; q < i; ++q) s = cadd2(s, cmul2(sT[tid][q], sG[q][i]));
+    }
+    __syncthreads();
+    if (tid < i) sT[tid][i] = cmul2(make_double2(-ti.x, -ti.y), s);
+    if (tid == i) sT[i][i] = ti;
+    __syncthreads();
+  }
+  const int nblk_all = (jobs.mb + B - 1) / B;
+  double2* T = Tw + (int64_t(k) * nblk_all + blockIdx.x) * B * B;
+  for (int e = tid; e < B * B; e += 256) T[e] = sT[e / B][e % B];
+}
+
+// Z = Q y for a slice of cols columns per workgroup: grid (column slices, jobs), 256 threads,
+// dynamic LDS [mb][cols] slice + [8][32][cols] partial sums + [32][cols] W.
+__global__ void __launch_bounds__(256) k_bt_apply(DJobs jobs, const double2* __restrict__ Aw,
+                                                  const double2* __restrict__ Tw,
+                                                  const double* __restrict__ yw,
+                                                  const double* __restrict__ scw,
+                                                  double2* __restrict__ Zout, int cols) {
+  constexpr int B = kBtB;
+  extern __shared__ double2 shz[];
+  __shared__ double2 sT[B][B + 1];
+  const DJob& J = jobs.j[blockIdx.y];
+  const int mb = jobs.mb, nb = jobs.nb, m = J.m, k = J.k, nref = m - 1;
   const int c0 = blockIdx.x * cols;
   if (c0 >= min(nb, m)) return;
   const int nc = min(cols, min(nb, m) - c0);
-  const double2* A = Aw + int64_t(J.k) * mb * mb;
-  const double2* tk = tau + int64_t(J.k) * mb;
-  const double* Y = yw + int64_t(J.k) * nb * mb;
-  double2* Z = Zout + int64_t(J.k) * mb * nb;
-  double2* zs = shz;
-  double2* vj = shz + int64_t(mb) * cols;
-  __shared__ double2 s[BT_COLS];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  for (int t = tid; t < m * cols; t += blockDim.x) {
-    const int i = t / cols, c = t % cols;
-    const int cl = min(c, nc - 1);
-    const double yv = Y[int64_t(i) * nb + c0 + cl] * scw[int64_t(J.k) * nb + c0 + cl];
+  const double2* A = Aw + int64_t(k) * mb * mb;
+  const double* Y = yw + int64_t(k) * nb * mb;
+  double2* Z = Zout + int64_t(k) * mb * nb;
+  double2* zs = shz;                                   // [m][cols]
+  double2* part = zs + int64_t(mb) * cols;             // [8][B][cols]
+  double2* sW = part + 8 * B * cols;                   // [B][cols]
+  const int tid = threadIdx.x;
+  for (int t = tid; t < m * cols; t += 256) {
+    const int i = t / cols, c = t % cols, cl = min(c, nc - 1);
+    const double yv = Y[int64_t(i) * nb + c0 + cl] * scw[int64_t(k) * nb + c0 + cl];
     zs[t] = make_double2(c < nc ? yv : 0.0, 0.0);
   }
-  __syncthreads();
-  for (int j = m - 2; j >= 0; --j) {
-    const double2 t = tk[j];
-    if (t.x == 0.0 && t.y == 0.0) continue;  // uniform
-    for (int r = j + 1 + tid; r < m; r += blockDim.x)
-      vj[r] = r == j + 1 ? make_double2(1.0, 0.0) : A[int64_t(r) * mb + j];
+  const int nblk = (nref + B - 1) / B, nblk_all = (mb + B - 1) / B;
+  const int q = tid & (B - 1), grp = tid >> 5;
+  for (int blk = nblk - 1; blk >= 0; --blk) {
+    const int j0 = blk * B, bb = min(B, nref - j0);
+    const double2* T = Tw + (int64_t(k) * nblk_all + blk) * B * B;
+    for (int e = tid; e < B * B; e += 256) sT[e / B][e % B] = T[e];
+    __syncthreads();   // also orders the previous block's Z update before the reads below
+    // W = V^H Z: thread (q, group) sums rows r = j0 + 1 + group + 8 t
+    double2 acc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = make_double2(0.0, 0.0);
+    const int qc = j0 + min(q, bb - 1);
+    int r = j0 + 1 + grp;
+    for (; r + 24 < m; r += 32) {   // four rows per trip: their loads are in flight together
+      double2 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) v[u] = cconj(keep(bt_v(A, mb, r + 8 * u, qc), q < bb));
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          if (c < cols) acc[c] = cadd2(acc[c], cmul2(v[u], zs[(r + 8 * u) * cols + c]));
+    }
+    for (; r < m; r += 8) {
+      const double2 v = cconj(keep(bt_v(A, mb, r, qc), q < bb));
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c < cols) acc[c] = cadd2(acc[c], cmul2(v, zs[r * cols + c]));
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+      if (c < cols) part[(grp * B + q) * cols + c] = acc[c];
     __syncthreads();
-    // s_c = sum_r conj(v_r) z_rc : wave w reduces column w (and w + 4)
-    for (int c = wave; c < cols; c += 4) {
-      double sr = 0.0, si = 0.0;
-      for (int r = j + 1 + lane; r < m; r += 64) {
-        const double2 v = vj[r], z = zs[r * cols + c];
-        sr += v.x * z.x + v.y * z.y;
-        si += v.x * z.y - v.y * z.x;
+    // W' = T W (T upper triangular)
+    for (int e = tid; e < B * cols; e += 256) {
+      const int p = e / cols, c = e % cols;
+      double2 w = make_double2(0.0, 0.0);
+      for (int qq = p; qq < bb; ++qq) {
+        double2 s = part[qq * cols + c];
+        for (int g2 = 1; g2 < 8; ++g2) s = cadd2(s, part[(g2 * B + qq) * cols + c]);
+        w = cadd2(w, cmul2(sT[p][qq], s));
       }
-      for (int o = 32; o > 0; o >>= 1) {
-        sr += __shfl_down(sr, o, 64);
-        si += __shfl_down(si, o, 64);
-      }
-      if (lane == 0) s[c] = cmul2(t, make_double2(sr, si));
+      sW[p * cols + c] = w;
     }
     __syncthreads();
-    for (int q = tid; q < (m - j - 1) * cols; q += blockDim.x) {
-      const int r = j + 1 + q / cols, c = q % cols;
-      zs[r * cols + c] = csub2(zs[r * cols + c], cmul2(vj[r], s[c]));
+    // Z -= V W', one row per thread (its 32 reflector entries loaded once for all columns)
+    for (int r = j0 + 1 + tid; r < m; r += 256) {
+      double2 sacc[8];
+#pragma unroll
+      for (int c = 0; c < 8; ++c) sacc[c] = make_double2(0.0, 0.0);
+      for (int qq = 0; qq < bb; ++qq) {
+        const double2 v = bt_v(A, mb, r, j0 + qq);
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          if (c < cols) sacc[c] = cadd2(sacc[c], cmul2(v, sW[qq * cols + c]));
+      }
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        if (c < cols) zs[r * cols + c] = csub2(zs[r * cols + c], sacc[c]);
     }
     __syncthreads();
   }
-  for (int t = tid; t < m * cols; t += blockDim.x) {
+  for (int t = tid; t < m * cols; t += 256) {
     const int i = t / cols, c = t % cols;
     if (c < nc) Z[int64_t(i) * nb + c0 + c] = zs[t];
   }
