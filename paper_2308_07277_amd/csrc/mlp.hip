@@ -22,7 +22,8 @@ namespace qm {
 constexpr int NIN = QM_MLP_NIN, NH = QM_MLP_NHID, NPAR = QM_MLP_NPARAM;
 constexpr int OW1 = 0, OB1 = NH * NIN, OW2 = OB1 + NH, OB2 = OW2 + 2 * NH;
 
-__device__ __forceinline__ float silu_f(float z) { return z / (1.0f + __expf(-z)); }
+// z sigmoid(z) with the hardware reciprocal (about 1 ulp): exp(-z) -> inf gives -0, -> 0 gives z
+__device__ __forceinline__ float silu_f(float z) { return z * __builtin_amdgcn_rcpf(1.0f + __expf(-z)); }
 
 __device__ __forceinline__ float teter_k(float x) {
   const float num = 27.0f + x * (18.0f + x * (12.0f + 8.0f * x));
@@ -87,13 +88,13 @@ __global__ void __launch_bounds__(256) k_mlp_precond(DJobs jobs, const double2* 
                                                      const double* __restrict__ kin_all,
                                                      const int64_t* __restrict__ goff,
                                                      const float* __restrict__ weights) {
-  __shared__ float w[NPAR];
+  // the weights are read at wave-uniform addresses straight from the read-only argument
+  // (scalar loads), so the hidden-layer loop issues no LDS traffic
+  const float* __restrict__ w = weights;
   __shared__ double red[16];
   const DJob& J = jobs.j[blockIdx.y];
   const int nb = jobs.nb, j = blockIdx.x;
   if (j >= J.nu) return;
-  for (int i = threadIdx.x; i < NPAR; i += blockDim.x) w[i] = weights[i];
-  __syncthreads();
   const int n = unconv[int64_t(J.k) * nb + j];
   const double tn = tkin[int64_t(J.k) * nb + n];
   const double th = theta[int64_t(J.k) * jobs.mb + n];
