@@ -89,7 +89,9 @@ typedef struct {
   int32_t restart;        /* qm_davidson_step: 1 = discard state and start from psi [0] */
   double switch_resid;    /* precision ladder: while max residual > switch_resid the
                              corrections are applied with the plan's reduced-precision
-                             H; below it (and for every reported residual) float64.
+                             H and the subspace products (orthonormalisation, projected
+                             matrix, Ritz vectors) use float32 arithmetic on the float64
+                             basis; below it (and for every reported residual) float64.
                              0 = float64 throughout [0] */
   const void *mlp_weights;/* device float32 weights of the learned preconditioner
                              (layout in qm_mlp_*), required for QM_PRECOND_MLP */

@@ -201,9 +201,15 @@ static void cholesky_inverse(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hi
   QM_HIP(hipGetLastError());
 }
 
+// Subspace products (Gram-Schmidt, CholQR, projected matrix, Ritz vectors) use float32
+// arithmetic on the float64 basis while H itself runs in reduced precision: there the basis
+// only has to be accurate to the reduced-precision H; float64 from the switch on.
+static int subspace_lp(const DavState* d) { return d->lowp ? 3 : 0; }
+
 // T = rows [m - nu, m) of V; orthogonalise against rows [0, m - nu) (two CGS passes) and
 // orthonormalise (two CholQR passes).  Returns false if a Gram matrix was not positive definite.
 static bool orthonormalise(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipStream_t s) {
+  const int lp = subspace_lp(d);
   std::vector<GemmCN> cn;
   std::vector<GemmEX> ex;
   for (int pass = 0; pass < 2; ++pass) {
@@ -218,8 +224,8 @@ static bool orthonormalise(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipS
       cn.push_back(GemmCN{vrow(d, d->V, j, 0), T, C, base, j.nu, j.npw, j.npw, j.npw, d->nb});
       ex.push_back(GemmEX{C, vrow(d, d->V, j, 0), T, j.nu, j.npw, base, d->nb, j.npw, j.npw});
     }
-    zgemm_cn_batched(cn, 1.0, 0.0, d->work, d->work_bytes, s);
-    zgemm_ex_batched(ex, -1.0, 1.0, s);
+    zgemm_cn_batched(cn, 1.0, 0.0, d->work, d->work_bytes, s, nullptr, 0, lp);
+    zgemm_ex_batched(ex, -1.0, 1.0, s, lp);
   }
   for (int pass = 0; pass < 2; ++pass) {
     cn.clear();
@@ -233,9 +239,9 @@ static bool orthonormalise(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipS
       cn.push_back(GemmCN{T, T, Gk, j.nu, j.nu, j.npw, j.npw, j.npw, d->nb});
       ex.push_back(GemmEX{Wk, T, O, j.nu, j.npw, j.nu, d->nb, j.npw, j.npw});
     }
-    zgemm_cn_batched(cn, 1.0, 0.0, d->work, d->work_bytes, s);
+    zgemm_cn_batched(cn, 1.0, 0.0, d->work, d->work_bytes, s, nullptr, 0, lp);
     cholesky_inverse(p, d, jobs, s);
-    zgemm_ex_batched(ex, 1.0, 0.0, s);
+    zgemm_ex_batched(ex, 1.0, 0.0, s, lp);
   }
   QM_HIP(hipMemcpyAsync(d->h_info, d->info, sizeof(int32_t) * d->nk, hipMemcpyDeviceToHost, s));
   QM_HIP(hipStreamSynchronize(s));
@@ -277,6 +283,7 @@ static void tridiagonalise(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipS
 
 // Projected matrix columns [m_old, m), eigenproblem, Ritz vectors and residuals.
 static void rayleigh_ritz(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipStream_t s) {
+  const int lp = subspace_lp(d);
   std::vector<GemmCN> cn;
   for (int i = 0; i < jobs.n; ++i) {
     const DJob& j = jobs.j[i];
@@ -284,7 +291,7 @@ static void rayleigh_ritz(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipSt
     cn.push_back(GemmCN{vrow(d, d->V, j, 0), vrow(d, d->HV, j, j.m_old), Hk + j.m_old, j.m,
                         j.m - j.m_old, j.npw, j.npw, j.npw, d->mb});
   }
-  zgemm_cn_batched(cn, 1.0, 0.0, d->work, d->work_bytes, s);
+  zgemm_cn_batched(cn, 1.0, 0.0, d->work, d->work_bytes, s, nullptr, 0, lp);
   hipLaunchKernelGGL(k_hs_fill, dim3(64, jobs.n), dim3(256), 0, s, jobs, d->Hs);
   hipLaunchKernelGGL(k_hs_copy, dim3(64, jobs.n), dim3(256), 0, s, jobs, d->Hs, d->Aw);
   QM_HIP(hipGetLastError());
@@ -321,7 +328,7 @@ static void rayleigh_ritz(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipSt
     ex.push_back(GemmEX{Zk, vrow(d, d->V, j, 0), d->X + j.xoff, d->nb, j.npw, j.m, d->nb, j.npw, j.npw});
     ex.push_back(GemmEX{Zk, vrow(d, d->HV, j, 0), d->HX + j.xoff, d->nb, j.npw, j.m, d->nb, j.npw, j.npw});
   }
-  zgemm_ex_batched(ex, 1.0, 0.0, s);
+  zgemm_ex_batched(ex, 1.0, 0.0, s, lp);
   hipLaunchKernelGGL(k_residual, dim3(d->nb, jobs.n), dim3(256), 0, s, jobs, d->X, d->HX, d->R,
                      d->theta, p->g.kin, d->goff, d->resn, d->tkin);
   QM_HIP(hipGetLastError());

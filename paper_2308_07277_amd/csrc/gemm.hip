@@ -709,6 +709,13 @@ void zgemm_cn_batched(const std::vector<GemmCN>& probs, double alpha, double bet
         else
           hipLaunchKernelGGL((k_cgemm_cn<float, float2, double2, 64, 64>), dim3(unsigned(blk)), dim3(256),
                              0, s, d, nsplit, reinterpret_cast<cplx<float>*>(work));
+      else if (lp == 3)
+        if (wide)
+          hipLaunchKernelGGL((k_cgemm_cn<float, double2, double2, 128, 32>), dim3(unsigned(blk)), dim3(256),
+                             0, s, d, nsplit, reinterpret_cast<cplx<float>*>(work));
+        else
+          hipLaunchKernelGGL((k_cgemm_cn<float, double2, double2, 64, 64>), dim3(unsigned(blk)), dim3(256),
+                             0, s, d, nsplit, reinterpret_cast<cplx<float>*>(work));
       else
         hipLaunchKernelGGL(k_cgemm_cn_bf16, dim3(unsigned(blk)), dim3(256), 0, s, d, nsplit,
                            reinterpret_cast<cplx<float>*>(work));
@@ -760,6 +767,12 @@ void zgemm_ex_batched(const std::vector<GemmEX>& probs, double alpha, double bet
                          s, d, alpha, beta_y);
     else if (lp == 1)
       hipLaunchKernelGGL((k_cgemm_ex<float, double2, float2, 64, 64>), dim3(unsigned(blk)), dim3(256), 0,
+                         s, d, alpha, beta_y);
+    else if (lp == 3 && narrow)
+      hipLaunchKernelGGL((k_cgemm_ex<float, double2, double2, 32, 128>), dim3(unsigned(blk)), dim3(256), 0,
+                         s, d, alpha, beta_y);
+    else if (lp == 3)
+      hipLaunchKernelGGL((k_cgemm_ex<float, double2, double2, 64, 64>), dim3(unsigned(blk)), dim3(256), 0,
                          s, d, alpha, beta_y);
     else
       hipLaunchKernelGGL(k_cgemm_ex_bf16, dim3(unsigned(blk)), dim3(256), 0, s, d, alpha, beta_y);

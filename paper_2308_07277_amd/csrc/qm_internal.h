@@ -192,7 +192,9 @@ int64_t zgemm_cn_work_bytes(const std::vector<GemmCN>& probs);
 void zgemm_ex_batched(const std::vector<GemmEX>& probs, double alpha, double beta_y,
                       hipStream_t s, int lp = 0);
 // lp: 0 float64 operands, 1 float32 (A of CN / A of EX stored float32), 2 bfloat16 (same
-// operands stored bfloat16); B of CN and W of EX are always c128 and converted on load
+// operands stored bfloat16); B of CN and W of EX are always c128 and converted on load.
+// lp 3: every operand c128, rounded to float32 on load, float32 MFMA arithmetic, float64
+// output (the subspace products of the reduced-precision phase of the Davidson ladder)
 void convert_beta_lp(const void* beta64, void* out, int64_t n, int kind, hipStream_t s);
 
 void plan_upload_davidson(qm_hpsi_plan* p);
