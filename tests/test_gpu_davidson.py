@@ -301,3 +301,34 @@ def test_default_dense_paths_at_larger_bases():
         print(f"k={ik} max eig err {err:.2e} max residual {r.max():.2e}")
         assert err <= 1e-8 and r.max() <= 1.5e-8
         np.testing.assert_allclose(xs[ik].conj() @ xs[ik].T, np.eye(nb), atol=1e-10)
+
+
+def test_float32_ladder_subspace_products():
+    """Float32 ladder on the 8-atom cell (4 k): before the switch at 1e-5 both H and the
+    subspace products (Gram-Schmidt, CholQR, projected matrix, Ritz vectors) run in float32
+    arithmetic.  The float64 phase after the switch must still deliver the dense-matrix
+    eigenvalues (1e-8 Ha), orthonormal vectors (1e-10) and oracle-recomputed residuals
+    <= 1.5e-8; the reduced-precision phase must do real work and not cost more than six
+    extra iterations over the float64 solve."""
+    w = workload.make_workload("c2")
+    a = plan_arrays(w)
+    plan64, _ = make_plan(w, w.nbnd, arrays=a)
+    e64, r64, s64, st64, _ = _solve(plan64, w, w.nbnd, _start(w, w.nbnd), tol=1e-8)
+    plan64.close()
+    plan, _ = make_plan(w, w.nbnd, prec=1, arrays=a)
+    eig, res, stats, st, x = _solve(plan, w, w.nbnd, _start(w, w.nbnd), tol=1e-8, switch_resid=1e-5)
+    plan.close()
+    print("float64", s64["iterations"], "float32 ladder", stats)
+    assert st64 == 0 and st == 0 and stats["converged"] == 1
+    assert stats["n_hpsi_bands_lowp"] > 0
+    assert stats["iterations"] <= s64["iterations"] + 6
+    assert np.abs(eig - e64).max() <= 1e-10
+    xs = split_k(x, w, w.nbnd)
+    for ik in range(w.nk):
+        h, beta = _oracle_h(w, a, ik)
+        dense = ham.dense_h(w.cell, w.grid, w.k_cryst[ik], w.miller[ik], a["vloc"], beta, a["dmat"])
+        err = np.abs(eig[ik] - np.linalg.eigvalsh(dense)[:w.nbnd]).max()
+        r = np.linalg.norm(h(xs[ik]) - eig[ik][:, None] * xs[ik], axis=1)
+        print(f"k={ik} max eig err {err:.2e} max residual {r.max():.2e}")
+        assert err <= 1e-8 and r.max() <= 1.5e-8
+        np.testing.assert_allclose(xs[ik].conj() @ xs[ik].T, np.eye(w.nbnd), atol=1e-10)
