@@ -258,8 +258,8 @@ DAVIDSON_ARMS = [
     ("fp64+teter, one lane", None, 0.0, "teter", None, 1),
     ("fp64+teter, no buffer bands", None, 0.0, "teter", 0, None),
     ("fp64+mlp", None, 0.0, "mlp", None, None),
-    ("fp32-ladder+teter", 1, 1e-5, "teter", None, None),
-    ("fp32-ladder+mlp", 1, 1e-5, "mlp", None, None),
+    ("fp32-ladder+teter", 1, 3e-4, "teter", None, None),
+    ("fp32-ladder+mlp", 1, 3e-4, "mlp", None, None),
     ("bf16-ladder+teter", 2, 1e-3, "teter", None, None),
     ("bf16-ladder+mlp", 2, 1e-3, "mlp", None, None),
 ]
@@ -452,7 +452,8 @@ def main():
         progress("Davidson on the 64-atom cell done")
         if args.davidson_c5:
             out["davidson_c5"] = davidson_run("c5", weights=weights, max_basis_factor=3,
-                                              only=("fp64+teter", "fp64+mlp", "fp32-ladder+mlp"))
+                                              only=("fp64+teter", "fp64+mlp", "fp32-ladder+teter",
+                                                    "fp32-ladder+mlp"))
             progress("Davidson on the 216-atom cell done")
         if args.cpu_baseline:
             out["davidson_cpu_baseline"] = davidson_cpu_baseline("c2")
