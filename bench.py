@@ -303,11 +303,12 @@ def davidson_run(name, weights=None, tol=1e-8, max_basis_factor=4, lanes=3, only
                      "n_hpsi_bands_lowp": stats["n_hpsi_bands_lowp"],
                      "max_resnorm": stats["max_resnorm"], "t_hpsi_ms": stats["t_hpsi_ms"],
                      "t_eig_ms": stats["t_eig_ms"], "t_subspace_ms": stats["t_subspace_ms"],
-                     "extra_bands": eb}
+                     "extra_bands": eb, "switch_resid": sw}
     ref = "fp64+teter" if "fp64+teter" in eigs else next(iter(eigs))
     for arm in arms:
         if arm != ref:
             arms[arm]["max_abs_eig_diff_vs_" + ref] = float(np.abs(eigs[arm] - eigs[ref]).max())
+            arms[arm]["speedup_vs_" + ref] = arms[ref]["time_s"] / arms[arm]["time_s"]
     plan.close()
     return {"workload": f"{name}: {len(w.atoms)}-atom cell, {w.nk} k-points, "
                         f"{w.nbnd} bands, tol {tol:g} Ha, {extra_bands} buffer bands, max_basis "
