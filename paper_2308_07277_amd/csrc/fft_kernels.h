@@ -66,6 +66,57 @@ __device__ __forceinline__ int locate_tile_block(const LocalArgs& a, int& bid) {
   return s;
 }
 
+// Loops over table entries keep kUnroll of them in flight per thread: the loads of a group
+// are all issued before any is used, so a workgroup waits for one round trip to memory per
+// group instead of one per entry.  Indices past the end are clamped to the last valid entry.
+// Where the loop only moves a value to the place its entry names, the clamped copies store
+// the same value at the same place again, which needs no guard; a guard would let the
+// compiler sink each load into its guarded store and serialise the group again.
+constexpr int kUnroll = 4;
+
+// Makes a loaded value live in registers at this point, so that its load is not moved into
+// a later conditional block.
+__device__ __forceinline__ void pin(int x) { asm volatile("" ::"v"(x)); }
+__device__ __forceinline__ void pin(double x) { asm volatile("" ::"v"(x)); }
+__device__ __forceinline__ void pin(double2 x) {
+  pin(x.x);
+  pin(x.y);
+}
+
+// plane[s] -> L at the stick's (row, active column) position, s < nstick
+template <typename R, int NT>
+__device__ __forceinline__ void sticks_to_lds(const cplx<R>* plane, const int32_t* spos, int nstick,
+                                              cplx<R>* L, int ns, int tid) {
+  for (int s0 = tid; s0 < nstick; s0 += kUnroll * NT) {
+    int ps[kUnroll];
+    cplx<R> v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int s = min(s0 + u * NT, nstick - 1);
+      ps[u] = spos[s];
+      v[u] = plane[s];
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) L[(ps[u] & 0xffff) * ns + (ps[u] >> 16)] = v[u];
+  }
+}
+
+// L at the stick's position -> plane[s], s < nstick
+template <typename R, int NT>
+__device__ __forceinline__ void lds_to_sticks(cplx<R>* plane, const int32_t* spos, int nstick,
+                                              const cplx<R>* L, int ns, int tid) {
+  for (int s0 = tid; s0 < nstick; s0 += kUnroll * NT) {
+    int s[kUnroll], ps[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      s[u] = min(s0 + u * NT, nstick - 1);
+      ps[u] = spos[s[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) plane[s[u]] = L[(ps[u] & 0xffff) * ns + (ps[u] >> 16)];
+  }
+}
+
 // ------------------------------------------------------------------ z inverse + scatter
 template <typename R, int N3, int TS>
 __global__ void __launch_bounds__(TS * Split<N3>::R2) k_zinv(LocalArgs a) {
@@ -91,11 +142,20 @@ __global__ void __launch_bounds__(TS * Split<N3>::R2) k_zinv(LocalArgs a) {
   const double2* psi_b = a.psi + ks.psi_off + int64_t(band) * ki.npw;
   const int32_t* eg = a.ent_g + ki.g_off;
   const int32_t* esz = a.ent_sz + ki.g_off;
-  for (int e = e0 + tid; e < e1; e += NT) {
-    const int sz = esz[e];
-    const int s = sz / N3, z = sz - s * N3;
-    const double2 v = psi_b[eg[e]];
-    tile[z * TS + (s - s0)] = {R(v.x), R(v.y)};
+  for (int eb = e0 + tid; eb < e1; eb += kUnroll * NT) {
+    int sz[kUnroll];
+    double2 v[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int e = min(eb + u * NT, e1 - 1);
+      sz[u] = esz[e];
+      v[u] = psi_b[eg[e]];
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int s = sz[u] / N3, z = sz[u] - s * N3;
+      tile[z * TS + (s - s0)] = {R(v[u].x), R(v[u].y)};
+    }
   }
   __syncthreads();
   const int sl = tid % TS, j = tid / TS;
@@ -168,10 +228,7 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
   cplx<R>* plane = stick_base<R>(a.sbuf, ki) +
                    (int64_t(band) * N3 + p) * ki.nstick;
   const int32_t* spos = a.stick_pos + ki.stick_off;
-  for (int s = tid; s < ki.nstick; s += 256) {
-    const int ps = spos[s];
-    L[(ps & 0xffff) * ns + (ps >> 16)] = plane[s];
-  }
+  sticks_to_lds<R, 256>(plane, spos, ki.nstick, L, ns, tid);
   __syncthreads();
   // ---- inverse y on active columns: pass 1 (R2-point, stride R1)
   for (int w = tid; w < nax * R1; w += 256) {
@@ -287,10 +344,7 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
     for (int k1 = 0; k1 < R2; ++k1) L[(k2 + R1 * k1) * ns + ia] = z[k1];
   }
   __syncthreads();
-  for (int s = tid; s < ki.nstick; s += 256) {
-    const int ps = spos[s];
-    plane[s] = L[(ps & 0xffff) * ns + (ps >> 16)];
-  }
+  lds_to_sticks<R, 256>(plane, spos, ki.nstick, L, ns, tid);
 }
 
 // ------------------------------------------------------------------ xy plane, lane-group lines
@@ -429,10 +483,7 @@ __global__ void __launch_bounds__(L * NX) k_xy_group(LocalArgs a) {
   cplx<R>* plane = stick_base<R>(a.sbuf, ki) +
                    (int64_t(band) * N3 + p) * ki.nstick;
   const int32_t* spos = a.stick_pos + ki.stick_off;
-  for (int s = tid; s < ki.nstick; s += NT) {
-    const int ps = spos[s];
-    Lp[(ps & 0xffff) * ns + (ps >> 16)] = plane[s];
-  }
+  sticks_to_lds<R, NT>(plane, spos, ki.nstick, Lp, ns, tid);
   __syncthreads();
   // whole waves take part in the cross-lane steps (lines rounded up to a wave)
   const int nax_w = ((nax + LPW - 1) / LPW) * LPW;
@@ -482,10 +533,7 @@ __global__ void __launch_bounds__(L * NX) k_xy_group(LocalArgs a) {
     }
   }
   __syncthreads();
-  for (int s = tid; s < ki.nstick; s += NT) {
-    const int ps = spos[s];
-    plane[s] = Lp[(ps & 0xffff) * ns + (ps >> 16)];
-  }
+  lds_to_sticks<R, NT>(plane, spos, ki.nstick, Lp, ns, tid);
 }
 
 // ------------------------------------------------------------------ z forward + gather + kinetic
@@ -541,14 +589,33 @@ __global__ void __launch_bounds__(TS * Split<N3>::R2) k_zfwd(LocalArgs a) {
   const int32_t* eg = a.ent_g + ki.g_off;
   const int32_t* esz = a.ent_sz + ki.g_off;
   const double* kin = a.kin + ki.g_off;
-  for (int e = e0 + tid; e < e1; e += NT) {
-    const int sz = esz[e];
-    const int s = sz / N3, z = sz - s * N3;
-    const int g = eg[e];
-    const cplx<R> v = tile[z * TS + (s - s0)];
-    const double2 ps = psi_b[g];
-    const double kv = kin[g];
-    out_b[g] = make_double2(kv * ps.x + double(v.re), kv * ps.y + double(v.im));
+  for (int eb = e0 + tid; eb < e1; eb += kUnroll * NT) {
+    int sz[kUnroll], g[kUnroll];
+    double2 ps[kUnroll];
+    double kv[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int e = min(eb + u * NT, e1 - 1);
+      sz[u] = esz[e];
+      g[u] = eg[e];
+      ps[u] = psi_b[g[u]];
+      kv[u] = kin[g[u]];
+    }
+    // each G is read and written by the one entry that owns it, so the stores stay guarded
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      pin(sz[u]);
+      pin(ps[u]);
+      pin(kv[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (eb + u * NT < e1) {
+        const int s = sz[u] / N3, z = sz[u] - s * N3;
+        const cplx<R> v = tile[z * TS + (s - s0)];
+        out_b[g[u]] = make_double2(kv[u] * ps[u].x + double(v.re), kv[u] * ps[u].y + double(v.im));
+      }
+    }
   }
 }
 
