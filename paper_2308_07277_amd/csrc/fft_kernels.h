@@ -268,6 +268,14 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
       const int i2 = r0 + rs;
       const bool act = rs < RW && i2 < NX;
       const int lrow = act ? (i2 / R2) + R1 * (i2 % R2) : 0;
+      // this row's V(r) values, loaded before the row's LDS exchanges (whose wave-level
+      // fences the loads could not be moved across); idle lanes read row 0
+      R vr[R1];
+      {
+        const R* Vrow = V + (act ? i2 : 0) * NX;
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) vr[k1] = Vrow[q + R2 * k1];
+      }
       if (act && q < R1) {
         cplx<R> x[R2];
 #pragma unroll
@@ -287,9 +295,8 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
 #pragma unroll
         for (int n1 = 0; n1 < R1; ++n1) y[n1] = Xr[n1 + R1 * q];
         Dft<R1, +1, R>::run(y);  // y[k1] is the row value at i1 = q + R2 k1
-        const R* Vrow = V + i2 * NX;
 #pragma unroll
-        for (int k1 = 0; k1 < R1; ++k1) y[k1] = cscale(y[k1], Vrow[q + R2 * k1]);
+        for (int k1 = 0; k1 < R1; ++k1) y[k1] = cscale(y[k1], vr[k1]);
         Dft<R1, -1, R>::run(y);  // forward, factorisation (R2, R1): first pass over n2' = k1
 #pragma unroll
         for (int k2 = 1; k2 < R1; ++k2) {
