@@ -218,6 +218,21 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
   const int k = a.sl[si].k, band = kb - a.pair0[si];
   const KInfo ki = a.kinfo[k];
   const int nax = ki.nax;
+  cplx<R>* plane = stick_base<R>(a.sbuf, ki) +
+                   (int64_t(band) * N3 + p) * ki.nstick;
+  const int32_t* spos = a.stick_pos + ki.stick_off;
+  // the first group of sticks is loaded before the tables, the zero fill and their barrier,
+  // so its round trip to memory overlaps theirs (nstick >= 1: every k has a plane wave)
+  int ps0[kUnroll];
+  R re0[kUnroll], im0[kUnroll];   // scalar arrays: an array of complex stayed in scratch
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    const int s = min(tid + u * 256, ki.nstick - 1);
+    ps0[u] = spos[s];
+    const cplx<R> v = plane[s];
+    re0[u] = v.re;
+    im0[u] = v.im;
+  }
   for (int i = tid; i < NX; i += 256) {
     double2 w = a.tw_x[i];
     tw[i] = {R(w.x), R(w.y)};
@@ -225,10 +240,9 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
   }
   for (int i = tid; i < NX * ns; i += 256) L[i] = {R(0), R(0)};
   __syncthreads();
-  cplx<R>* plane = stick_base<R>(a.sbuf, ki) +
-                   (int64_t(band) * N3 + p) * ki.nstick;
-  const int32_t* spos = a.stick_pos + ki.stick_off;
-  sticks_to_lds<R, 256>(plane, spos, ki.nstick, L, ns, tid);
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) L[(ps0[u] & 0xffff) * ns + (ps0[u] >> 16)] = cplx<R>{re0[u], im0[u]};
+  sticks_to_lds<R, 256>(plane, spos, ki.nstick, L, ns, tid + kUnroll * 256);
   __syncthreads();
   // ---- inverse y on active columns: pass 1 (R2-point, stride R1)
   for (int w = tid; w < nax * R1; w += 256) {
