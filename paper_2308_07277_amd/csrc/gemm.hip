@@ -228,6 +228,57 @@ __global__ void k_cn_reduce(const CNOutBatch outs, int nsplit,
 }
 
 // ------------------------------------------------------------------ EX
+// Makes a loaded value live in registers at this point, so that its load is not moved into
+// a later conditional block.
+__device__ __forceinline__ void hold(double x) { asm volatile("" ::"v"(x)); }
+
+// Y = alpha * acc + beta * Y for a wave's 2 x 2 accumulator tiles (element r of a lane at
+// row acc_row, column lane % 16).  With beta != 0 the eight old values of one tile row are
+// loaded together, from addresses clamped into the matrix, and held in registers before
+// the guarded stores: a load under each element's guard had compiled to one memory round
+// trip per element.
+template <typename T, typename AV>
+__device__ __forceinline__ void store_ex_tile(const EXDev& P, int m0, int n0, int wi, int wj, int lane,
+                                              const AV (&cr)[2][2], const AV (&ci)[2][2], double alpha,
+                                              double beta) {
+  double2* Y = reinterpret_cast<double2*>(P.Y);
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti) {
+    double ore[8], oim[8];
+    if (beta != 0.0) {
+#pragma unroll
+      for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int m = min(m0 + wi + ti * 16 + acc_row<T>(lane, r), P.M - 1);
+          const int n = min(n0 + wj + tj * 16 + (lane & 15), P.N - 1);
+          const double2 o = Y[int64_t(m) * P.ldy + n];
+          ore[tj * 4 + r] = o.x;
+          oim[tj * 4 + r] = o.y;
+        }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        hold(ore[e]);
+        hold(oim[e]);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) ore[e] = oim[e] = 0.0;
+    }
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wi + ti * 16 + acc_row<T>(lane, r);
+        const int n = n0 + wj + tj * 16 + (lane & 15);
+        if (m < P.M && n < P.N)
+          Y[int64_t(m) * P.ldy + n] =
+              make_double2(alpha * double(cr[ti][tj][r]) + beta * ore[tj * 4 + r],
+                           alpha * double(ci[ti][tj][r]) + beta * oim[tj * 4 + r]);
+      }
+  }
+}
+
 // Output tile TM x TN (64 x 64, or 32 x 128 when the row count is a multiple of 32 but not
 // of 64, e.g. 160 bands: no padded rows); four waves of 32 x 32 each.
 template <typename T, typename SW, typename SA, int TM, int TN>
@@ -312,26 +363,7 @@ __global__ void __launch_bounds__(256) k_cgemm_ex(const EXBatch batch, double al
     }
     __syncthreads();
   }
-  double2* Y = reinterpret_cast<double2*>(P.Y);
-#pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wi + ti * 16 + acc_row<T>(lane, r);
-        const int n = n0 + wj + tj * 16 + (lane & 15);
-        if (m < P.M && n < P.N) {
-          double2* y = Y + int64_t(m) * P.ldy + n;
-          const double vr = double(cr[ti][tj][r]), vi = double(ci[ti][tj][r]);
-          if (beta != 0.0) {
-            const double2 o = *y;
-            *y = make_double2(alpha * vr + beta * o.x, alpha * vi + beta * o.y);
-          } else {
-            *y = make_double2(alpha * vr, alpha * vi);
-          }
-        }
-      }
+  store_ex_tile<T>(P, m0, n0, wi, wj, lane, cr, ci, alpha, beta);
 }
 
 
@@ -586,26 +618,7 @@ __global__ void __launch_bounds__(256) k_cgemm_ex_bf16(const EXBatch batch, doub
       }
     __syncthreads();
   }
-  double2* Y = reinterpret_cast<double2*>(P.Y);
-#pragma unroll
-  for (int ti = 0; ti < 2; ++ti)
-#pragma unroll
-    for (int tj = 0; tj < 2; ++tj)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wi + ti * 16 + acc_row<float>(lane, r);
-        const int n = n0 + wj + tj * 16 + (lane & 15);
-        if (m < P.M && n < P.N) {
-          double2* y = Y + int64_t(m) * P.ldy + n;
-          const double vr = double(cr[ti][tj][r]), vi = double(ci[ti][tj][r]);
-          if (beta != 0.0) {
-            const double2 o = *y;
-            *y = make_double2(alpha * vr + beta * o.x, alpha * vi + beta * o.y);
-          } else {
-            *y = make_double2(alpha * vr, alpha * vi);
-          }
-        }
-      }
+  store_ex_tile<float>(P, m0, n0, wi, wj, lane, cr, ci, alpha, beta);
 }
 
 // beta (c128) -> float32 or bfloat16 complex copy
