@@ -18,11 +18,21 @@ def _setup(name, ik=0, vscale=1.0, nl=True, nbnd=None):
     return h, dense, kin, x0
 
 
-def test_teter_closed_form():
-    x = np.array([0.0, 0.5, 1.0, 2.0, 10.0])
-    num = 27 + 18 * x + 12 * x ** 2 + 8 * x ** 3
-    np.testing.assert_allclose(dav.teter(x), num / (num + 16 * x ** 4), rtol=1e-15)
-    assert dav.teter(0.0) == 1.0 and dav.teter(1e4) < 1e-3
+def test_teter_hand_values(golden):
+    """K(x) at x = 1/2, 1, 2, 3 against exact fractions evaluated by hand
+    (tests/golden/teter_hand.txt), plus the two limits of the Teter-Payne-Allan factor:
+    1 - K(x) = 16 x^4/27 + O(x^5) near 0 and x K(x) -> 1/2.  A dropped or wrong coefficient
+    in either polynomial changes at least one of the fractions."""
+    g = golden("teter_hand.txt")
+    x = np.array(g["x"])
+    np.testing.assert_allclose(dav.teter(x), np.array(g["num"]) / np.array(g["den"]), rtol=1e-15)
+    assert dav.teter(0.0) == 1.0
+    for h in (1e-2, 1e-3):
+        assert abs((1.0 - dav.teter(h)) / h ** 4 - 16.0 / 27.0) < 2.0 * h
+    for big in (1e4, 1e6):
+        assert abs(big * dav.teter(big) - 0.5) < 2.0 / big
+    xs = np.linspace(0.0, 50.0, 2001)
+    assert np.all(np.diff(dav.teter(xs)) < 0.0)
 
 
 def test_orthonormalise():

@@ -1,7 +1,7 @@
 """Pins for the learned-preconditioner oracle: finite differences, special cases, Adam."""
 import numpy as np
 
-from oracle import mlp
+from oracle import davidson as dav, mlp
 
 
 def _data(seed=0, nb=3, npw=40):
@@ -14,6 +14,24 @@ def _data(seed=0, nb=3, npw=40):
     f = mlp.features(kin, r, theta, tkin).reshape(-1, 5)
     ptr = np.arange(nb + 1) * npw
     return f, r.reshape(-1), delta.reshape(-1), ptr
+
+
+def test_features_hand_example(golden):
+    """The five input features on a 3-G, 2-band example evaluated by hand
+    (tests/golden/mlp_features_hand.txt): x = T(G)/T_n, log(1 + x), (theta_n - T_n)/T_n,
+    |r_n(G)| sqrt(npw)/||r_n|| and T(G).  A log written for log1p, a missing sqrt(npw), a
+    residual normalised by its square norm or x inverted each fail."""
+    g = golden("mlp_features_hand.txt")
+    kin = np.array(g["kin"])
+    r = np.array([np.array(g["r0_re"]) + 1j * np.array(g["r0_im"]),
+                  np.array(g["r1_re"]) + 1j * np.array(g["r1_im"])])
+    f = mlp.features(kin, r, np.array(g["theta"]), np.array(g["tkin"]))
+    assert f.shape == (2, 3, 5)
+    for n in range(2):
+        for q in range(3):
+            np.testing.assert_allclose(f[n, q], g[f"f{n}_{q}"], rtol=1e-15, atol=1e-15)
+    # the teter factor of the network's gain uses the same x as the Davidson's Teter step
+    np.testing.assert_allclose(mlp.teter_factor(f[..., 0]), dav.teter(f[..., 0]), rtol=1e-15)
 
 
 def test_gradient_matches_finite_differences():
