@@ -89,9 +89,12 @@ typedef struct {
   int32_t restart;        /* qm_davidson_step: 1 = discard state and start from psi [0] */
   double switch_resid;    /* precision ladder: while max residual > switch_resid the
                              corrections are applied with the plan's reduced-precision
-                             H and the subspace products (orthonormalisation, projected
-                             matrix, Ritz vectors) use float32 arithmetic on the float64
-                             basis; below it (and for every reported residual) float64.
+                             H (float32 FFTs; float32 or bfloat16 projector GEMMs with
+                             float32 accumulation); below it, and for every reported
+                             residual, float64.  It also switches when the max residual
+                             has not fallen by 20% over four iterations.  Residual
+                             norms, Rayleigh-Ritz, Cholesky orthonormalisation and the
+                             projected eigenproblem stay float64 unless subspace_fp32.
                              0 = float64 throughout [0] */
   const void *mlp_weights;/* device float32 weights of the learned preconditioner
                              (layout in qm_mlp_*), required for QM_PRECOND_MLP */
@@ -107,6 +110,11 @@ typedef struct {
                              decide convergence and are returned.  Keeps a degenerate level
                              cut by the band count from stalling the highest wanted bands.
                              Needs nbnd + extra_bands <= the plan's nbnd_max [0] */
+  int32_t subspace_fp32;  /* 1: while the ladder runs H in reduced precision, the subspace
+                             products (block Gram-Schmidt, CholQR Gram matrices and their
+                             application, V^H (H V), Ritz vectors) round the float64 basis
+                             to float32 and multiply in float32 MFMAs with float64 output.
+                             0: they stay float64 [0] */
 } qm_dav_opts;
 
 /* Davidson statistics (host), filled by qm_davidson_solve. */
@@ -116,9 +124,11 @@ typedef struct {
   int64_t n_hpsi_bands;   /* band-applications of H (all precisions) */
   int64_t n_hpsi_bands_lowp; /* of which in reduced precision */
   double max_resnorm;     /* final max residual, Ha */
-  double t_hpsi_ms;       /* device time in H application */
-  double t_subspace_ms;   /* subspace GEMMs, orthonormalisation and Ritz update */
-  double t_eig_ms;        /* projected eigenproblem */
+  double t_hpsi_ms;       /* device time in H application (HIP events) */
+  double t_subspace_ms;   /* device time in orthonormalisation, V^H (H V) and Ritz vectors
+                             with residuals (HIP events) */
+  double t_eig_ms;        /* device time in the projected eigenproblem (HIP events); with
+                             lanes, each of the three is the largest over the lanes */
   double t_total_ms;      /* wall time of the call */
 } qm_dav_stats;
 
@@ -199,7 +209,10 @@ qm_status qm_apply_h_timed(qm_hpsi_plan *plan, int32_t k, const void *psi, void 
 
 /* ------------------------------------------------------------------ Davidson */
 
-/* One Davidson iteration on k (or all k with k = -1), state kept in the plan.
+/* One block-Davidson iteration (Sec. 5, 'dft' module: the Davidson "with overlap" that
+ * only needs H applied to blocks of trial vectors; the algorithm's details are not given
+ * there, this is the block Davidson of Davidson 1975 and Liu 1978 with an explicitly
+ * orthonormalised basis) on k (or all k with k = -1), state kept in the plan.
  * First call (or opts->restart = 1): orthonormalise psi, apply H, Rayleigh-Ritz.
  * Later calls: corrections for unconverged bands, restart if the basis is full,
  * orthonormalise, apply H, Rayleigh-Ritz.  Every call writes the current Ritz
@@ -210,9 +223,12 @@ qm_status qm_davidson_step(qm_hpsi_plan *plan, int32_t k, void *psi, double *eig
                            double *resnorm, int32_t nbnd, const qm_dav_opts *opts,
                            int32_t *n_unconverged, void *stream);
 
-/* Iterate qm_davidson_step from the start block psi until every residual norm
- * is <= opts->tol or max_iter is reached (then QM_E_NOT_CONVERGED with all
- * outputs filled).  psi receives the Ritz vectors; stats may be NULL. */
+/* Iterate qm_davidson_step (same passage) from the start block psi until every
+ * residual norm is <= opts->tol or max_iter is reached (then QM_E_NOT_CONVERGED with
+ * all outputs filled).  psi receives the Ritz vectors; stats may be NULL.
+ * Errors: QM_E_NOT_SPD when a block to be orthonormalised is linearly dependent (for
+ * example two equal start vectors), QM_E_NAN when a residual norm is not finite; in both
+ * cases the Davidson state is dropped and the plan stays usable for qm_apply_h. */
 qm_status qm_davidson_solve(qm_hpsi_plan *plan, int32_t k, void *psi, double *eig,
                             double *resnorm, int32_t nbnd, const qm_dav_opts *opts,
                             qm_dav_stats *stats, void *stream);
@@ -252,7 +268,8 @@ qm_status qm_mlp_adam(float *weights, const float *grad, float *m, float *v, int
                       float lr, float beta1, float beta2, float eps, void *stream);
 
 /* Training rows from the current Davidson state of the plan (after a
- * qm_davidson_step): for every unconverged (k, band) of that state, npw_k rows
+ * qm_davidson_step without buffer bands, else QM_E_STATE): for every unconverged
+ * (k, band) of that state, npw_k rows
  * of features (as above), residual r_n(G) and target d_n(G) = P x_n/||P x_n|| - x_n,
  * with P the projector onto the converged eigenvectors x_star (device c128,
  * layout as psi) whose eigenvalues eig_star (host [nk_sel][nbnd]) lie within

@@ -48,7 +48,7 @@ class qm_dav_opts(ctypes.Structure):
                 ("max_basis", ctypes.c_int32), ("precond", ctypes.c_int32),
                 ("restart", ctypes.c_int32), ("switch_resid", ctypes.c_double),
                 ("mlp_weights", ctypes.c_void_p), ("lanes", ctypes.c_int32),
-                ("extra_bands", ctypes.c_int32)]
+                ("extra_bands", ctypes.c_int32), ("subspace_fp32", ctypes.c_int32)]
 
 
 class qm_dav_stats(ctypes.Structure):
@@ -234,10 +234,11 @@ def qm_apply_h_timed(plan, k, psi, hpsi, nbnd, stream=None):
 
 
 def _opts(tol=1e-8, max_iter=200, max_basis=0, precond=QM_PRECOND_TETER, restart=0,
-          switch_resid=0.0, mlp_weights=None, lanes=0, extra_bands=0):
+          switch_resid=0.0, mlp_weights=None, lanes=0, extra_bands=0, subspace_fp32=0):
     w = 0 if mlp_weights is None else mlp_weights.data_ptr()
     return qm_dav_opts(float(tol), int(max_iter), int(max_basis), int(precond), int(restart),
-                       float(switch_resid), ctypes.c_void_p(w), int(lanes), int(extra_bands))
+                       float(switch_resid), ctypes.c_void_p(w), int(lanes), int(extra_bands),
+                       int(subspace_fp32))
 
 
 def qm_davidson_step(plan, k, psi, nbnd, stream=None, **opts):

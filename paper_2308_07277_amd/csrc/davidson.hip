@@ -31,6 +31,7 @@ struct DavState {
   ProjScratch ps;            // own projector scratch (lanes only; else the plan's)
   bool ready = false;
   bool lowp = false;
+  bool sub32 = false;        // float32-arithmetic subspace products while lowp
   double2 *V = nullptr, *HV = nullptr, *X = nullptr, *HX = nullptr, *R = nullptr, *TS = nullptr;
   double2 *Hs = nullptr, *Aw = nullptr, *Z = nullptr, *tau = nullptr, *Cw = nullptr, *G = nullptr,
           *W = nullptr;
@@ -53,13 +54,14 @@ struct DavState {
   std::vector<double> hist;  // max residual per step (precision-ladder stagnation test)
   double* estar = nullptr;   // converged eigenvalues for training-pair generation
   double t_hpsi = 0, t_sub = 0, t_eig = 0;
-  hipEvent_t ev[6] = {};
+  hipEvent_t ev[8] = {};     // 0-1 H application, 2-3 eigenproblem, 4-5 orthonormalisation,
+                             // 6-7 Ritz vectors and residuals
 };
 
 static void dav_release(DavState* d) {
   void* dev[] = {d->V, d->HV, d->X, d->HX, d->R, d->TS, d->Hs, d->Aw, d->Z, d->tau, d->Cw, d->G,
                  d->W, d->theta, d->d, d->e, d->resn, d->tkin, d->yw, d->fw, d->unconv, d->info,
-                 d->goff, d->work, d->estar, d->ps.part, d->trd.v, d->trd.w, d->trd.p, d->trd.cnt,
+                 d->goff, d->work, d->estar, d->ps.part, d->trd.v, d->trd.w, d->trd.part, d->trd.cnt,
                  d->ew.sc, d->ew.nrm, d->chol_dmax, d->chol_ld, d->bt_t};
   for (void* q : dev)
     if (q) (void)hipFree(q);
@@ -130,7 +132,8 @@ static DavState* dav_create(qm_hpsi_plan* p, int k0, int k1, int nb, int mb, boo
     QM_REQUIRE(mb <= kTrdMaxBasis, QM_E_ARG, "max_basis above the tridiagonalisation limit (2048)");
     d->trd.v = dalloc<double2>(nk * 2 * mb);
     d->trd.w = dalloc<double2>(nk * mb);
-    d->trd.p = dalloc<double2>(nk * mb);
+    d->trd.ptiles = trd_tile_slots(mb);
+    d->trd.part = dalloc<double2>(nk * size_t(d->trd.ptiles) * 2 * kTrdTile);
     d->trd.cnt = dalloc<uint32_t>(nk);
     d->ew.sc = dalloc<double>(nk * nb);
     d->ew.nrm = dalloc<double>(nk);
@@ -191,7 +194,7 @@ static void cholesky_inverse(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hi
   int numax = 0;
   for (int i = 0; i < jobs.n; ++i) numax = std::max(numax, jobs.j[i].nu);
   const int nblk = (numax + kCholBlk - 1) / kCholBlk;
-  hipLaunchKernelGGL(k_chol_prep, dim3(jobs.n), dim3(256), 0, s, jobs, d->G, d->chol_dmax, d->info);
+  hipLaunchKernelGGL(k_chol_prep, dim3(jobs.n), dim3(256), 0, s, jobs, d->G, d->chol_dmax);
   for (int jb = 0; jb < nblk; ++jb)
     hipLaunchKernelGGL(k_chol_col, dim3(nblk - jb, jobs.n), dim3(256), 0, s, jobs, jb, d->G,
                        d->chol_ld, d->chol_dmax, d->info);
@@ -201,10 +204,11 @@ static void cholesky_inverse(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hi
   QM_HIP(hipGetLastError());
 }
 
-// Subspace products (Gram-Schmidt, CholQR, projected matrix, Ritz vectors) use float32
-// arithmetic on the float64 basis while H itself runs in reduced precision: there the basis
-// only has to be accurate to the reduced-precision H; float64 from the switch on.
-static int subspace_lp(const DavState* d) { return d->lowp ? 3 : 0; }
+// Subspace products (Gram-Schmidt, CholQR, projected matrix, Ritz vectors) run in float64
+// unless the caller opts in (qm_dav_opts.subspace_fp32) to float32 arithmetic on the float64
+// basis while H itself runs in reduced precision: there the basis only has to be accurate
+// to the reduced-precision H.  From the switch on they are float64 either way.
+static int subspace_lp(const DavState* d) { return (d->lowp && d->sub32) ? 3 : 0; }
 
 // T = rows [m - nu, m) of V; orthogonalise against rows [0, m - nu) (two CGS passes) and
 // orthonormalise (two CholQR passes).  Returns false if a Gram matrix was not positive definite.
@@ -212,6 +216,10 @@ static bool orthonormalise(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipS
   const int lp = subspace_lp(d);
   std::vector<GemmCN> cn;
   std::vector<GemmEX> ex;
+  QM_HIP(hipEventRecord(d->ev[4], s));
+  // cleared once here and only ever set by a failed pivot, so a failure in the first CholQR
+  // pass is still reported after the second
+  QM_HIP(hipMemsetAsync(d->info, 0, sizeof(int32_t) * d->nk, s));
   for (int pass = 0; pass < 2; ++pass) {
     cn.clear();
     ex.clear();
@@ -243,8 +251,12 @@ static bool orthonormalise(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipS
     cholesky_inverse(p, d, jobs, s);
     zgemm_ex_batched(ex, 1.0, 0.0, s, lp);
   }
+  QM_HIP(hipEventRecord(d->ev[5], s));
   QM_HIP(hipMemcpyAsync(d->h_info, d->info, sizeof(int32_t) * d->nk, hipMemcpyDeviceToHost, s));
   QM_HIP(hipStreamSynchronize(s));
+  float ms = 0.f;
+  QM_HIP(hipEventElapsedTime(&ms, d->ev[4], d->ev[5]));
+  d->t_sub += ms;
   for (int i = 0; i < jobs.n; ++i)
     if (d->h_info[jobs.j[i].k] != 0) return false;
   return true;
@@ -257,10 +269,11 @@ constexpr int kTrdMultiMin = 192;
 static void tridiagonalise(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipStream_t s) {
   int mmax = 0;
   for (int i = 0; i < jobs.n; ++i) mmax = std::max(mmax, jobs.j[i].m);
-  const bool multi = p->trd_forced == 2 || (p->trd_forced != 1 && mmax >= kTrdMultiMin);
+  const bool multi = p->trd_forced == 2 || mmax > kTridiagMaxM ||
+                     (p->trd_forced != 1 && mmax >= kTrdMultiMin);
   if (!multi) {
-    hipLaunchKernelGGL(k_tridiag, dim3(jobs.n), dim3(1024), size_t(5) * d->mb * sizeof(double2), s,
-                       jobs, d->Aw, d->d, d->e, d->tau);
+    hipLaunchKernelGGL(k_tridiag, dim3(jobs.n), dim3(1024), size_t(20) * mmax * sizeof(double2), s,
+                       jobs, d->Aw, d->d, d->e, d->tau, mmax);
     QM_HIP(hipGetLastError());
     return;
   }
@@ -285,6 +298,7 @@ static void tridiagonalise(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipS
 static void rayleigh_ritz(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipStream_t s) {
   const int lp = subspace_lp(d);
   std::vector<GemmCN> cn;
+  QM_HIP(hipEventRecord(d->ev[6], s));
   for (int i = 0; i < jobs.n; ++i) {
     const DJob& j = jobs.j[i];
     double2* Hk = d->Hs + int64_t(j.k) * d->mb * d->mb;
@@ -332,12 +346,16 @@ static void rayleigh_ritz(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipSt
   hipLaunchKernelGGL(k_residual, dim3(d->nb, jobs.n), dim3(256), 0, s, jobs, d->X, d->HX, d->R,
                      d->theta, p->g.kin, d->goff, d->resn, d->tkin);
   QM_HIP(hipGetLastError());
+  QM_HIP(hipEventRecord(d->ev[7], s));
   QM_HIP(hipMemcpyAsync(d->h_resn, d->resn, sizeof(double) * d->nk * d->nb, hipMemcpyDeviceToHost, s));
   QM_HIP(hipMemcpyAsync(d->h_theta, d->theta, sizeof(double) * d->nk * d->mb, hipMemcpyDeviceToHost, s));
   QM_HIP(hipStreamSynchronize(s));
-  float ms = 0.f;
+  float ms = 0.f, ms_h = 0.f, ms_r = 0.f;
   QM_HIP(hipEventElapsedTime(&ms, d->ev[2], d->ev[3]));
+  QM_HIP(hipEventElapsedTime(&ms_h, d->ev[6], d->ev[2]));
+  QM_HIP(hipEventElapsedTime(&ms_r, d->ev[3], d->ev[7]));
   d->t_eig += ms;
+  d->t_sub += ms_h + ms_r;
 }
 
 static DJob make_job(qm_hpsi_plan* p, DavState* d, int k) {
@@ -412,6 +430,8 @@ static qm_status dav_step_range(qm_hpsi_plan* p, DavState** slot, bool own_scrat
                                 const qm_dav_opts* o, int32_t* n_unconv, hipStream_t s) {
   QM_REQUIRE(nwant >= 1, QM_E_ARG, "need nbnd >= 1");
   QM_REQUIRE(!o || o->extra_bands >= 0, QM_E_ARG, "extra_bands must be >= 0");
+  QM_REQUIRE(!o || o->subspace_fp32 == 0 || o->subspace_fp32 == 1, QM_E_ARG,
+             "subspace_fp32 must be 0 or 1");
   const int nb = nwant + (o ? o->extra_bands : 0);   // block size: wanted + buffer bands
   QM_REQUIRE(nb <= p->nbnd_max, QM_E_ARG, "need nbnd + extra_bands <= nbnd_max");
   QM_REQUIRE(k0 >= 0 && k0 < k1 && k1 <= p->nk, QM_E_ARG, "k out of range");
@@ -441,6 +461,7 @@ static qm_status dav_step_range(qm_hpsi_plan* p, DavState** slot, bool own_scrat
     d->n_hpsi = d->n_hpsi_lowp = 0;
     d->t_hpsi = d->t_sub = d->t_eig = 0;
     d->lowp = o && o->switch_resid > 0.0 && p->prec != QM_PREC_FP64;
+    d->sub32 = o && o->subspace_fp32 != 0;
   }
   DJobs jobs{};
   jobs.nb = nb;
@@ -614,13 +635,11 @@ __global__ void __launch_bounds__(256) k_pairs(DJobs jobs, PairArgs pa, const do
   const int64_t row0 = pa.rowbase[blockIdx.y] + int64_t(j) * J.npw;
   for (int g = threadIdx.x; g < J.npw; g += blockDim.x) {
     const int64_t row = row0 + g;
-    const double kv = kin[g], x2 = kv / tn;
     const double2 rv = r[g];
-    feat[row * 5 + 0] = float(x2);
-    feat[row * 5 + 1] = float(log1p(x2));
-    feat[row * 5 + 2] = float((th - tn) / tn);
-    feat[row * 5 + 3] = float(sqrt(rv.x * rv.x + rv.y * rv.y) * rs);
-    feat[row * 5 + 4] = float(kv);
+    float f[QM_MLP_NIN];
+    make_feat(kin[g], tn, th, sqrt(rv.x * rv.x + rv.y * rv.y) * rs, f);
+#pragma unroll
+    for (int i = 0; i < QM_MLP_NIN; ++i) feat[row * QM_MLP_NIN + i] = f[i];
     resid[2 * row] = float(rv.x);
     resid[2 * row + 1] = float(rv.y);
     target[2 * row] = float(pn[g].x * ip - x[g].x);
@@ -634,6 +653,10 @@ static void training_pairs(qm_hpsi_plan* p, const void* xstar, const double* est
                            hipStream_t s) {
   DavState* d = p->dav;
   QM_REQUIRE(d && d->ready, QM_E_STATE, "no Davidson state: call qm_davidson_step first");
+  // x_star and eig_star are laid out [nk][nbnd] like psi: a state with buffer bands holds
+  // rows the caller's arrays do not have
+  QM_REQUIRE(d->nb == d->nwant, QM_E_STATE,
+             "training pairs need a Davidson state without buffer bands (extra_bands = 0)");
   QM_REQUIRE(xstar && estar && feat && resid && target && band_ptr && nrows && nbands, QM_E_ARG,
              "NULL argument");
   if (!d->estar) d->estar = dalloc<double>(size_t(d->nk) * d->nb);
@@ -805,7 +828,7 @@ qm_status qm_davidson_solve(qm_hpsi_plan* plan, int32_t k, void* psi, double* ei
   }
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
-    double mr = 0.0, th = 0.0, te = 0.0;
+    double mr = 0.0, th = 0.0, te = 0.0, ts = 0.0;
     int itmax = 0;
     for (int i = 0; i < nlanes; ++i) {
       const DavState* d = nlanes == 1 ? plan->dav : plan->dav_lanes[i];
@@ -818,6 +841,7 @@ qm_status qm_davidson_solve(qm_hpsi_plan* plan, int32_t k, void* psi, double* ei
       stats->n_hpsi_bands_lowp += d->n_hpsi_lowp;
       th = std::max(th, d->t_hpsi);   // lanes overlap in time: the slowest lane's phases
       te = std::max(te, d->t_eig);
+      ts = std::max(ts, d->t_sub);
     }
     stats->iterations = itmax;
     stats->converged = (st == QM_OK && nun == 0) ? 1 : 0;
@@ -826,7 +850,7 @@ qm_status qm_davidson_solve(qm_hpsi_plan* plan, int32_t k, void* psi, double* ei
     stats->t_eig_ms = te;
     stats->t_total_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    stats->t_subspace_ms = stats->t_total_ms - th - te;
+    stats->t_subspace_ms = ts;
   }
   if (st == QM_OK && nun > 0) {
     plan->err = "Davidson did not converge within max_iter";

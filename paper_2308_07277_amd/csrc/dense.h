@@ -25,9 +25,15 @@ constexpr int kTrdMaxBasis = 2048; // rows of a column one 256-thread workgroup 
 struct TrdWork {
   double2* v;      // [k][2][mb] reflectors of the current and the previous step (slot j & 1)
   double2* w;      // [k][mb]    w of the previous step (the pending rank-2 update is v w^H + w v^H)
-  double2* p;      // [k][mb]    accumulator of A v (returned to zero after every step)
+  double2* part;   // [k][ptiles][2][kTrdTile] each tile's share of A v: its 64 row sums and
+                   //            its 64 column sums, summed in a fixed order by the last workgroup
   uint32_t* cnt;   // [k]        workgroups of the current step that have finished
+  int32_t ptiles;  // tile slots per k: nt (nt + 1) / 2 with nt = ceil(mb / kTrdTile)
 };
+inline int trd_tile_slots(int mb) {
+  const int nt = (mb + kTrdTile - 1) / kTrdTile;
+  return nt * (nt + 1) / 2;
+}
 
 // Scratch of the tridiagonal eigensolver, per k.
 struct EigWork {
@@ -35,12 +41,28 @@ struct EigWork {
   double* nrm;   // [k]     norm estimate of the tridiagonal
 };
 
+// Input features of the learned preconditioner at one (G, band): x = T(G)/T_n, log(1 + x),
+// (theta_n - T_n)/T_n, the residual amplitude |r_n(G)| sqrt(npw)/||r_n|| (passed in as ramp)
+// and T(G) = 1/2|k+G|^2, computed in float64 and stored as float32.  The one definition used
+// by inference inside the Davidson and by the training-row generation.
+__device__ __forceinline__ void make_feat(double kin, double tn, double theta, double ramp,
+                                          float f[QM_MLP_NIN]) {
+  const double x = kin / tn;
+  f[0] = float(x);
+  f[1] = float(log1p(x));
+  f[2] = float((theta - tn) / tn);
+  f[3] = float(ramp);
+  f[4] = float(kin);
+}
+
 }  // namespace qm
 
 namespace qm {
 __global__ void k_hs_fill(DJobs jobs, double2* Hs);
 __global__ void k_hs_copy(DJobs jobs, const double2* Hs, double2* Aw);
-__global__ void k_tridiag(DJobs jobs, double2* Aw, double* dd, double* ee, double2* tau);
+__global__ void k_tridiag(DJobs jobs, double2* Aw, double* dd, double* ee, double2* tau, int ms);
+// largest basis the one-workgroup reduction takes: 4 + 16 vectors of m complex entries in LDS
+constexpr int kTridiagMaxM = (160 * 1024 - 2048) / (20 * 16);
 __global__ void k_trd_start(DJobs jobs, double2* Aw, double* dd, double* ee, double2* tau, TrdWork tw);
 __global__ void k_trd_step(DJobs jobs, int j, double2* Aw, double* dd, double* ee, double2* tau,
                            TrdWork tw);
@@ -57,7 +79,7 @@ constexpr int kCholBlk = 16;        // block size of the many-workgroup Cholesky
 // largest band count whose Linv column block fits in LDS next to the kernel's static
 // 13 KiB: 36 blocks of 16 x 16 complex (147 KiB)
 constexpr int kCholMaxBlocked = 576;
-__global__ void k_chol_prep(DJobs jobs, const double2* Gm, double* dmax, int32_t* info);
+__global__ void k_chol_prep(DJobs jobs, const double2* Gm, double* dmax);
 __global__ void k_chol_col(DJobs jobs, int jb, double2* Gm, double2* Ldw, const double* dmaxw,
                            int32_t* info);
 __global__ void k_chol_inv_cols(DJobs jobs, const double2* Gm, const double2* Ldw, double2* Wm,

@@ -107,18 +107,19 @@ __global__ void k_hs_copy(DJobs jobs, const double2* __restrict__ Hs, double2* _
 // triangle of the trailing block that applies the pending update and accumulates
 // p = tau A v at the same time (one read and one write per stored element and step).
 // A stored element a_rc (c < r) serves both halves of the Hermitian product: a_rc v_c
-// goes to p_r (summed in the wave that owns row r) and conj(a_rc) v_r to p_c (summed
-// across waves with LDS atomics).  A (row-major, stride mb) holds the Hermitian matrix in
-// its lower triangle (the upper one is never read) and is destroyed; column j below the
-// subdiagonal receives v_j (v_j[j+1] = 1 implicit).
+// goes to p_r (summed in the wave that owns row r) and conj(a_rc) v_r to p_c (summed in
+// a column-sum slice of the wave's own, and the slices added in wave order, so the result
+// does not depend on the order the waves ran in).  A (row-major, stride mb) holds the
+// Hermitian matrix in its lower triangle (the upper one is never read) and is destroyed;
+// column j below the subdiagonal receives v_j (v_j[j+1] = 1 implicit).
+// Dynamic LDS: 4 + 16 vectors of ms >= m complex entries (ms = the launch's largest m).
 __global__ void __launch_bounds__(1024) k_tridiag(DJobs jobs, double2* __restrict__ Aw,
                                                   double* __restrict__ dd, double* __restrict__ ee,
-                                                  double2* __restrict__ tau) {
-  extern __shared__ double2 sh[];   // vA, vB, pA, pB, column sums: [mb] each
+                                                  double2* __restrict__ tau, int ms) {
+  extern __shared__ double2 sh[];   // vA, vB, pA, pB, then the 16 waves' column sums: [ms] each
   const DJob& J = jobs.j[blockIdx.x];
   const int mb = jobs.mb, m = J.m;
   double2* A = Aw + int64_t(J.k) * mb * mb;
-  double2* colsum = sh + 4 * mb;
   double* d = dd + int64_t(J.k) * mb;
   double* e = ee + int64_t(J.k) * mb;
   double2* tk = tau + int64_t(J.k) * mb;
@@ -126,13 +127,14 @@ __global__ void __launch_bounds__(1024) k_tridiag(DJobs jobs, double2* __restric
   __shared__ double2 s_tau, s_scale, s_alpha;
   __shared__ double s_beta, s_dj;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = blockDim.x >> 6;
-  for (int i = tid; i < 5 * mb; i += blockDim.x) sh[i] = make_double2(0.0, 0.0);
+  double2* colsum = sh + int64_t(4 + wave) * ms;   // this wave's column sums
+  for (int i = tid; i < (4 + nw) * ms; i += blockDim.x) sh[i] = make_double2(0.0, 0.0);
   __syncthreads();
   for (int j = 0; j < m - 1; ++j) {
-    double2* vc = sh + (j & 1 ? mb : 0);          // this step's reflector
-    double2* pc = sh + 2 * mb + (j & 1 ? mb : 0);  // this step's p, then w
-    const double2* vq = sh + (j & 1 ? 0 : mb);     // pending reflector (step j-1)
-    const double2* wq = sh + 2 * mb + (j & 1 ? 0 : mb);  // pending w
+    double2* vc = sh + (j & 1 ? ms : 0);          // this step's reflector
+    double2* pc = sh + 2 * ms + (j & 1 ? ms : 0);  // this step's p, then w
+    const double2* vq = sh + (j & 1 ? 0 : ms);     // pending reflector (step j-1)
+    const double2* wq = sh + 2 * ms + (j & 1 ? 0 : ms);  // pending w
     // column j, rows >= j, brought up to date and kept in registers (m <= 2 blockDim)
     const double2 vqj = vq[j], wqj = wq[j];
     double2 colv[2];
@@ -184,9 +186,9 @@ __global__ void __launch_bounds__(1024) k_tridiag(DJobs jobs, double2* __restric
           if (r > j + 1) A[int64_t(r) * mb + j] = x;
         }
         vc[r] = x;
-        colsum[r] = make_double2(0.0, 0.0);
       }
     }
+    for (int i = tid; i < nw * ms; i += blockDim.x) sh[4 * ms + i] = make_double2(0.0, 0.0);
     if (tid == 0) vc[j] = make_double2(0.0, 0.0);
     __syncthreads();
     // fused pass over the lower triangle of [j+1, m): pending update, then A v.  A wave
@@ -226,9 +228,9 @@ __global__ void __launch_bounds__(1024) k_tridiag(DJobs jobs, double2* __restric
             ti += a.x * br.y - a.y * br.x;
           }
         }
-        if (c < rmax) {
-          atomicAdd(&colsum[c].x, tr);
-          atomicAdd(&colsum[c].y, ti);
+        if (c < rmax) {   // lanes of a wave hold distinct c: a plain update of its own slice
+          colsum[c].x += tr;
+          colsum[c].y += ti;
         }
       }
 #pragma unroll
@@ -244,7 +246,9 @@ __global__ void __launch_bounds__(1024) k_tridiag(DJobs jobs, double2* __restric
     __syncthreads();
     double pr = 0.0, pi = 0.0;   // p = tau (row part + column part); p^H v
     for (int c = j + 1 + tid; c < m; c += blockDim.x) {
-      const double2 pv = cmul2(t, cadd2(pc[c], colsum[c])), vv = vc[c];
+      double2 cs = pc[c];
+      for (int w = 0; w < nw; ++w) cs = cadd2(cs, sh[int64_t(4 + w) * ms + c]);
+      const double2 pv = cmul2(t, cs), vv = vc[c];
       pc[c] = pv;
       pr += pv.x * vv.x + pv.y * vv.y;
       pi += pv.x * vv.y - pv.y * vv.x;
@@ -256,8 +260,8 @@ __global__ void __launch_bounds__(1024) k_tridiag(DJobs jobs, double2* __restric
   }
   if (tid == 0) {
     const int j = m - 1;  // pending update of step m-2 on the last diagonal element
-    const double2* vq = sh + ((m - 2) & 1 ? mb : 0);
-    const double2* wq = sh + 2 * mb + ((m - 2) & 1 ? mb : 0);
+    const double2* vq = sh + ((m - 2) & 1 ? ms : 0);
+    const double2* wq = sh + 2 * ms + ((m - 2) & 1 ? ms : 0);
     double a = A[int64_t(j) * mb + j].x;
     if (m >= 2) a -= 2.0 * (vq[j].x * wq[j].x + vq[j].y * wq[j].y);
     d[j] = a;
@@ -270,16 +274,19 @@ __global__ void __launch_bounds__(1024) k_tridiag(DJobs jobs, double2* __restric
 // The same reduction (same reflectors, same lazy rank-2 update) spread over the whole GPU:
 // one launch per step j, one 256-thread workgroup per 64 x 64 tile of the lower triangle of
 // the trailing block [j+1, m).  A tile applies the pending update of step j-1 to its
-// elements and adds its share of A v_j to a global accumulator p (row part a_rc v_c,
-// column part conj(a_rc) v_r); the workgroup that finishes last (arrival counter) forms
-// p = tau A v and w = p - (tau/2)(p^H v) v, brings column j+1 up to date and builds the
-// next reflector, so the following launch can start at once.  Only the order of the
-// floating-point additions into p differs from the one-workgroup kernel.
-// Cross-workgroup traffic inside a launch is atomics only, so no workgroup needs a memory
-// fence (an agent-scope release writes back the whole L2 and costs ~70 ns per workgroup,
-// serialised): a tile's additions into p return their old values, and its counter increment
-// is issued only once every value is back; the last workgroup reads p with atomic swaps
-// (which also zero it for the next step).  Column j+1 is never stored by the tiles (it is
+// elements and writes its share of A v_j to a slot of its own: 64 row sums (a_rc v_c) and
+// 64 column sums (conj(a_rc) v_r).  The workgroup that finishes last (arrival counter) adds
+// the slots in a fixed order (for a row block: the row sums of the tiles left of the
+// diagonal, left to right, then the column sums of the tiles below it, top to bottom), so
+// the result does not depend on which workgroup ran when, forms p = tau A v and
+// w = p - (tau/2)(p^H v) v, brings column j+1 up to date and builds the next reflector, so
+// the following launch can start at once.  Only the order of the floating-point additions
+// into p differs from the one-workgroup kernel.
+// Cross-workgroup traffic inside a launch goes through agent-scope atomics only, so no
+// workgroup needs a memory fence (an agent-scope release writes back the whole L2 and costs
+// ~70 ns per workgroup, serialised): a tile writes its slot with atomic exchanges, whose
+// returned values it waits for before its counter increment, and the last workgroup reads
+// the slots with agent-scope atomic loads.  Column j+1 is never stored by the tiles (it is
 // dead after this step): the last workgroup rebuilds it from the values of the previous
 // launch with both pending updates.
 constexpr int kTrdRows = kTrdMaxBasis / 256;   // column rows per tail thread
@@ -356,7 +363,6 @@ __global__ void __launch_bounds__(256) k_trd_start(DJobs jobs, double2* __restri
   const DJob& J = jobs.j[blockIdx.x];
   const int mb = jobs.mb, m = J.m, k = J.k;
   double2* A = Aw + int64_t(k) * mb * mb;
-  for (int r = threadIdx.x; r < m; r += 256) tw.p[int64_t(k) * mb + r] = make_double2(0.0, 0.0);
   if (threadIdx.x == 0) tw.cnt[k] = 0u;
   double2 a[kTrdRows];
 #pragma unroll
@@ -395,7 +401,7 @@ __global__ void __launch_bounds__(256) k_trd_step(DJobs jobs, int j, double2* __
   const double2* vj = tw.v + (int64_t(k) * 2 + (j & 1)) * mb;        // this step's reflector
   const double2* vp = tw.v + (int64_t(k) * 2 + ((j + 1) & 1)) * mb;  // pending: v_{j-1}
   double2* W = tw.w + int64_t(k) * mb;                                // pending: w_{j-1}
-  double2* P = tw.p + int64_t(k) * mb;
+  double* PS = reinterpret_cast<double*>(tw.part + int64_t(k) * tw.ptiles * 2 * T);
   const bool pend = j > 0;
   const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15, lane = tid & 63, wave = tid >> 6;
   const double2 z = make_double2(0.0, 0.0);
@@ -465,9 +471,10 @@ __global__ void __launch_bounds__(256) k_trd_step(DJobs jobs, int j, double2* __
     }
   }
   // row parts summed over the 16 column groups (lane bits 0-3), column parts over the 16 row
-  // groups (lane bits 4-5, then the four waves); then one round of additions into p, 64 row
-  // and 64 column entries.  chk collects the values the additions return, so a thread
-  // cannot pass the barrier below before its additions are done.
+  // groups (lane bits 4-5, then the four waves, in order); then one round of exchanges into
+  // the tile's slot, 64 row and 64 column entries (zero where the row or column is outside
+  // the block, or for a diagonal tile's last column).  chk collects the values the exchanges
+  // return, so a thread cannot pass the barrier below before its writes are done.
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     for (int o = 1; o < 16; o <<= 1) {
@@ -485,17 +492,19 @@ __global__ void __launch_bounds__(256) k_trd_step(DJobs jobs, int j, double2* __
   double chk = 0.0;
   if (tid < T) {
     const int r = R0 + tid;
-    if (r >= j1 && r < m) {
-      chk += atomicAdd(&P[r].x, s_row[tid].x);
-      chk += atomicAdd(&P[r].y, s_row[tid].y);
-    }
+    const double2 s = keep(s_row[tid], r >= j1 && r < m);
+    chk += __hip_atomic_exchange(&PS[(int64_t(t) * 2 * T + tid) * 2], s.x, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+    chk += __hip_atomic_exchange(&PS[(int64_t(t) * 2 * T + tid) * 2 + 1], s.y, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
   } else if (tid < 2 * T) {
     const int i = tid - T, c = C0 + i;
-    if (c >= j1 && c < m && c < R0 + T - 1) {
-      const double2 s = cadd2(cadd2(s_col[0][i], s_col[1][i]), cadd2(s_col[2][i], s_col[3][i]));
-      chk += atomicAdd(&P[c].x, s.x);
-      chk += atomicAdd(&P[c].y, s.y);
-    }
+    const double2 s = keep(cadd2(cadd2(s_col[0][i], s_col[1][i]), cadd2(s_col[2][i], s_col[3][i])),
+                           c >= j1 && c < m && c < R0 + T - 1);
+    chk += __hip_atomic_exchange(&PS[(int64_t(t) * 2 * T + tid) * 2], s.x, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+    chk += __hip_atomic_exchange(&PS[(int64_t(t) * 2 * T + tid) * 2 + 1], s.y, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
   }
   // the last workgroup of this job to finish carries on
   if (chk == 1.0e300) s_last = 2u;   // never true; makes the thread wait for its additions
@@ -508,7 +517,7 @@ __global__ void __launch_bounds__(256) k_trd_step(DJobs jobs, int j, double2* __
   double2* tk = tau + int64_t(k) * mb;
   const double2 tj_ = tk[j];
   // column j+1 as the previous launch left it, with the update of step j-1 applied; every
-  // independent load is issued before the swaps that read p
+  // independent load is issued before the slot reads
   const double2 wpj1c = keep(cconj(W[j1]), pend), vpj1c = keep(cconj(vp[j1]), pend);
   double2 pq[kTrdRows], vq[kTrdRows], col[kTrdRows], vpq[kTrdRows], wpq[kTrdRows];
 #pragma unroll
@@ -519,14 +528,26 @@ __global__ void __launch_bounds__(256) k_trd_step(DJobs jobs, int j, double2* __
     vpq[q] = vp[rc];
     wpq[q] = W[rc];
   }
+  // (A v)_r for row r of block ib: row sums of tiles (ib, 0..ib), then column sums of tiles
+  // (ib..nt-1, ib), always in this order
 #pragma unroll
   for (int q = 0; q < kTrdRows; ++q) {
     const int r = j1 + tid + q * 256;
     pq[q] = z;
     if (r < m) {
-      unsigned long long* pr = reinterpret_cast<unsigned long long*>(&P[r]);
-      pq[q].x = __longlong_as_double(static_cast<long long>(atomicExch(pr, 0ull)));
-      pq[q].y = __longlong_as_double(static_cast<long long>(atomicExch(pr + 1, 0ull)));
+      const int ib = r / T - b0, i = r - (b0 + ib) * T;
+      double sx = 0.0, sy = 0.0;
+      for (int tj = 0; tj <= ib; ++tj) {
+        const int64_t o = ((int64_t(ib * (ib + 1) / 2 + tj) * 2) * T + i) * 2;
+        sx += __hip_atomic_load(&PS[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sy += __hip_atomic_load(&PS[o + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      for (int ti = ib; ti < nt; ++ti) {
+        const int64_t o = ((int64_t(ti * (ti + 1) / 2 + ib) * 2 + 1) * T + i) * 2;
+        sx += __hip_atomic_load(&PS[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        sy += __hip_atomic_load(&PS[o + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      pq[q] = make_double2(sx, sy);
     }
   }
   double sr = 0.0, si = 0.0;
@@ -1105,7 +1126,9 @@ __global__ void __launch_bounds__(256) k_bt_apply(DJobs jobs, const double2* __r
 
 // ---------------------------------------------------------------- Cholesky + inverse
 // G [k][nb][nb] (leading nu x nu, Hermitian PD) -> W[k][i][n] = conj(Linv[n][i]);
-// info[k] = 0 on success, j+1 if pivot j failed.  Right-looking, one workgroup.
+// info[k] is left as it is on success and set to j+1 if pivot j failed; a non-zero info[k]
+// on entry skips the job (the caller clears info once per orthonormalisation, so a failure
+// stays visible through its later passes).  Right-looking, one workgroup.
 __global__ void __launch_bounds__(1024) k_chol_inv(DJobs jobs, double2* __restrict__ Gm,
                                                    double2* __restrict__ Wm, int32_t* __restrict__ info) {
   const DJob& J = jobs.j[blockIdx.x];
@@ -1115,6 +1138,7 @@ __global__ void __launch_bounds__(1024) k_chol_inv(DJobs jobs, double2* __restri
   __shared__ int s_fail;
   __shared__ double s_dmax;
   const int tid = threadIdx.x;
+  if (info[J.k] != 0) return;   // an earlier factorisation of this orthonormalisation failed
   if (tid == 0) {
     s_fail = 0;
     double mx = 0.0;
@@ -1148,8 +1172,10 @@ __global__ void __launch_bounds__(1024) k_chol_inv(DJobs jobs, double2* __restri
     }
     __syncthreads();
   }
-  if (tid == 0) info[J.k] = s_fail;
-  if (s_fail) return;
+  if (s_fail) {
+    if (tid == 0) info[J.k] = s_fail;
+    return;
+  }
   // Linv column c by forward substitution; W[i][c'] = conj(Linv[c'][i])  (i <= c')
   for (int c = tid; c < n; c += blockDim.x) {
     // x = Linv[:, c]: x[r] = 0 for r < c
@@ -1172,7 +1198,8 @@ __global__ void __launch_bounds__(1024) k_chol_inv(DJobs jobs, double2* __restri
 
 // ---------------------------------------------------------------- blocked Cholesky + inverse
 // The same factorisation and inverse on many workgroups, in blocks of kCholB = 16:
-//   k_chol_prep      largest diagonal entry (pivot test) and info = 0
+//   k_chol_prep      largest diagonal entry (pivot test); info is cleared by the caller once
+//                    per orthonormalisation and only ever set by a failed pivot
 //   k_chol_col       block column jb of L (Crout order, one launch per block column): the
 //                    workgroup of row block ib forms [S_jj; S_ib,j] = G - (finished columns)
 //                    through LDS tiles, factors S_jj itself (every workgroup of the launch
@@ -1186,7 +1213,7 @@ __global__ void __launch_bounds__(1024) k_chol_inv(DJobs jobs, double2* __restri
 constexpr int kCholB = kCholBlk;
 
 __global__ void __launch_bounds__(256) k_chol_prep(DJobs jobs, const double2* __restrict__ Gm,
-                                                   double* __restrict__ dmax, int32_t* __restrict__ info) {
+                                                   double* __restrict__ dmax) {
   __shared__ double red[4];
   const DJob& J = jobs.j[blockIdx.x];
   const int nb = jobs.nb, n = J.nu;
@@ -1196,10 +1223,7 @@ __global__ void __launch_bounds__(256) k_chol_prep(DJobs jobs, const double2* __
   for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 64));
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    dmax[J.k] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-    info[J.k] = 0;
-  }
+  if (threadIdx.x == 0) dmax[J.k] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
 }
 
 // Grid (row blocks from jb on, jobs), 256 threads: thread (r = tid / 16, c = tid % 16).

@@ -57,15 +57,6 @@ __device__ __forceinline__ void mlp_fwd(const float* __restrict__ w, const float
   g1 = 0.5f * k * tanhf(o1);
 }
 
-__device__ __forceinline__ void make_feat(double kin, double tn, double theta, double ramp, float f[NIN]) {
-  const double x = kin / tn;
-  f[0] = float(x);
-  f[1] = float(log1p(x));
-  f[2] = float((theta - tn) / tn);
-  f[3] = float(ramp);
-  f[4] = float(kin);
-}
-
 __device__ double block_sum_d(double v, double* red) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;

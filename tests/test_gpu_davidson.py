@@ -133,8 +133,8 @@ def test_step_api_and_errors():
 def test_lanes_match_single_group():
     """Two concurrent lanes (k-points 0-1 and 2-3 of the 8-atom cell, each on its own stream
     and host thread) solve the same independent per-k problems as one group: eigenvalues
-    within 1e-10 Ha, iteration counts within one (the tridiagonal reduction sums with LDS
-    atomics, so runs agree to rounding), every residual below tol, and the Ritz vectors below
+    within 1e-10 Ha, iteration counts within one (the lanes' GEMM batches differ, so
+    runs agree to rounding), every residual below tol, and the Ritz vectors below
     the widest gap of each k span the same space within the Davis-Kahan bound."""
     import torch
     import paper_2308_07277_amd as qm
@@ -304,9 +304,9 @@ def test_default_dense_paths_at_larger_bases():
 
 
 def test_float32_ladder_subspace_products():
-    """Float32 ladder on the 8-atom cell (4 k): before the switch at 1e-5 both H and the
-    subspace products (Gram-Schmidt, CholQR, projected matrix, Ritz vectors) run in float32
-    arithmetic.  The float64 phase after the switch must still deliver the dense-matrix
+    """Float32 ladder on the 8-atom cell (4 k) with subspace_fp32 = 1: before the switch at
+    1e-5 both H and the subspace products (Gram-Schmidt, CholQR, projected matrix, Ritz
+    vectors) run in float32 arithmetic.  The float64 phase after the switch must still deliver the dense-matrix
     eigenvalues (1e-8 Ha), orthonormal vectors (1e-10) and oracle-recomputed residuals
     <= 1.5e-8; the reduced-precision phase must do real work and not cost more than six
     extra iterations over the float64 solve."""
@@ -316,7 +316,8 @@ def test_float32_ladder_subspace_products():
     e64, r64, s64, st64, _ = _solve(plan64, w, w.nbnd, _start(w, w.nbnd), tol=1e-8)
     plan64.close()
     plan, _ = make_plan(w, w.nbnd, prec=1, arrays=a)
-    eig, res, stats, st, x = _solve(plan, w, w.nbnd, _start(w, w.nbnd), tol=1e-8, switch_resid=1e-5)
+    eig, res, stats, st, x = _solve(plan, w, w.nbnd, _start(w, w.nbnd), tol=1e-8, switch_resid=1e-5,
+                                    subspace_fp32=1)
     plan.close()
     print("float64", s64["iterations"], "float32 ladder", stats)
     assert st64 == 0 and st == 0 and stats["converged"] == 1
@@ -332,3 +333,116 @@ def test_float32_ladder_subspace_products():
         print(f"k={ik} max eig err {err:.2e} max residual {r.max():.2e}")
         assert err <= 1e-8 and r.max() <= 1.5e-8
         np.testing.assert_allclose(xs[ik].conj() @ xs[ik].T, np.eye(w.nbnd), atol=1e-10)
+
+
+def _hpsi_ok(plan, w, a):
+    """The plan still applies H correctly after a failed Davidson call (oracle, 1e-12)."""
+    import torch
+    import paper_2308_07277_amd as qm
+    psi = w.psi(0, nbnd=w.nbnd)
+    x = torch.from_numpy(psi.reshape(-1).copy()).cuda()
+    y = torch.empty_like(x)
+    qm.qm_apply_h(plan, 0, x, y, w.nbnd)
+    h, _ = _oracle_h(w, a, 0)
+    ref = h(psi)
+    got = y.cpu().numpy().reshape(w.nbnd, -1)
+    err = (np.linalg.norm(got - ref, axis=1) / np.linalg.norm(ref, axis=1)).max()
+    assert err <= 1e-12, err
+
+
+def test_error_paths_forced_from_the_host():
+    """Failure handling, each condition made on the host from valid inputs:
+    - a NaN coefficient in the start block: QM_E_NAN or QM_E_NOT_SPD, never QM_OK;
+    - two equal start vectors (a rank-deficient block): QM_E_NOT_SPD, also when the first of
+      the two CholQR passes is the one that fails;
+    - max_iter = 2: QM_E_NOT_CONVERGED with eigenvalues, residual norms and statistics filled.
+    After each, the same plan gives the oracle's H|psi> (1e-12) and a fresh solve converges."""
+    import torch
+    import paper_2308_07277_amd as qm
+    w = workload.make_workload("c1")
+    plan, a = make_plan(w, w.nbnd)
+    start = _start(w, w.nbnd)[0]
+    # NaN in one coefficient
+    bad = start.copy()
+    bad[3, 17] = np.nan
+    with pytest.raises(qm.QmError) as e:
+        _solve(plan, w, w.nbnd, [bad])
+    print("NaN start:", e.value)
+    assert e.value.code in (qm.QM_E_NAN, qm.QM_E_NOT_SPD)
+    _hpsi_ok(plan, w, a)
+    # two equal start vectors
+    bad = start.copy()
+    bad[5] = bad[2]
+    with pytest.raises(qm.QmError) as e:
+        _solve(plan, w, w.nbnd, [bad])
+    print("equal start vectors:", e.value)
+    assert e.value.code == qm.QM_E_NOT_SPD
+    _hpsi_ok(plan, w, a)
+    # iteration limit
+    eig, res, stats, st, x = _solve(plan, w, w.nbnd, [start], tol=1e-9, max_iter=2)
+    print("max_iter 2:", st, stats)
+    assert st == qm.QM_E_NOT_CONVERGED
+    assert stats["iterations"] == 2 and stats["converged"] == 0 and stats["n_hpsi_bands"] > 0
+    assert np.isfinite(eig).all() and np.isfinite(res).all() and res.max() > 1e-9
+    assert stats["max_resnorm"] == pytest.approx(res.max())
+    h, beta = _oracle_h(w, a, 0)
+    xs = x.reshape(w.nbnd, -1)
+    r = np.linalg.norm(h(xs) - eig[0][:, None] * xs, axis=1)
+    np.testing.assert_allclose(r, res[0], rtol=1e-6, atol=1e-12)
+    _hpsi_ok(plan, w, a)
+    eig, res, stats, st, _ = _solve(plan, w, w.nbnd, [start], tol=1e-9)
+    assert st == 0 and res.max() <= 1e-9
+
+
+@pytest.mark.parametrize("prec,sw", [(1, 3e-4), (2, 1e-3)])
+def test_ladder_with_float64_subspace(prec, sw):
+    """Precision ladder with the subspace work in float64 (subspace_fp32 = 0, the default):
+    H in float32 FFTs with float32 (prec 1) or bfloat16 (prec 2) projector GEMMs while the
+    max residual is above the switch, float64 afterwards; Gram-Schmidt, CholQR, V^H (H V),
+    the projected eigenproblem and the residual norms in float64 throughout.  On the 8-atom
+    cell (4 k) the result must reach the dense-matrix eigenvalues (1e-8 Ha) with orthonormal
+    vectors and oracle-recomputed residuals <= 1.5e-8, after real reduced-precision work,
+    within six iterations of the float64 solve."""
+    w = workload.make_workload("c2")
+    a = plan_arrays(w)
+    plan64, _ = make_plan(w, w.nbnd, arrays=a)
+    e64, r64, s64, st64, _ = _solve(plan64, w, w.nbnd, _start(w, w.nbnd), tol=1e-8)
+    plan64.close()
+    plan, _ = make_plan(w, w.nbnd, prec=prec, arrays=a)
+    eig, res, stats, st, x = _solve(plan, w, w.nbnd, _start(w, w.nbnd), tol=1e-8, switch_resid=sw,
+                                    subspace_fp32=0)
+    plan.close()
+    print("float64", s64["iterations"], f"prec {prec} ladder", stats)
+    assert st64 == 0 and st == 0 and stats["converged"] == 1
+    assert stats["n_hpsi_bands_lowp"] > 0
+    assert stats["iterations"] <= s64["iterations"] + 6
+    xs = split_k(x, w, w.nbnd)
+    for ik in range(w.nk):
+        h, beta = _oracle_h(w, a, ik)
+        dense = ham.dense_h(w.cell, w.grid, w.k_cryst[ik], w.miller[ik], a["vloc"], beta, a["dmat"])
+        err = np.abs(eig[ik] - np.linalg.eigvalsh(dense)[:w.nbnd]).max()
+        r = np.linalg.norm(h(xs[ik]) - eig[ik][:, None] * xs[ik], axis=1)
+        print(f"k={ik} max eig err {err:.2e} max residual {r.max():.2e}")
+        assert err <= 1e-8 and r.max() <= 1.5e-8
+        np.testing.assert_allclose(xs[ik].conj() @ xs[ik].T, np.eye(w.nbnd), atol=1e-10)
+
+
+def test_float64_solve_is_reproducible():
+    """The float64 Davidson has no order-dependent reductions (split-K sums, the Householder
+    steps' A v and the one-workgroup reduction's column sums are added in a fixed order):
+    two solves of the 8-atom cell with 64 bands, 16 buffer bands and bases up to 320 columns
+    (both tridiagonalisation paths run) give bit-identical eigenvalues, residual norms,
+    vectors and iteration counts, with one lane and with two concurrent lanes."""
+    w = workload.make_workload("c2")
+    nb = 64
+    plan, a = make_plan(w, nb + 16)
+    starts = [w.psi(ik, purpose=2, nbnd=nb) for ik in range(w.nk)]
+    for lanes in (1, 2):
+        runs = [_solve(plan, w, nb, starts, tol=1e-8, extra_bands=16, max_basis=320, lanes=lanes)
+                for _ in range(2)]
+        (e1, r1, s1, st1, x1), (e2, r2, s2, st2, x2) = runs
+        print("lanes", lanes, "iterations", s1["iterations"], s2["iterations"],
+              "max eig diff", np.abs(e1 - e2).max(), "max vector diff", np.abs(x1 - x2).max())
+        assert st1 == 0 and st2 == 0
+        assert s1["iterations"] == s2["iterations"]
+        assert np.array_equal(e1, e2) and np.array_equal(r1, r2) and np.array_equal(x1, x2)

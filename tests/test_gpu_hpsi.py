@@ -124,7 +124,7 @@ def test_error_paths():
 
 
 @pytest.mark.parametrize("name,prec,bound", [("c3", 0, 1e-12), ("c5", 0, 1e-12), ("c3", 1, 1e-5),
-                                             ("c3", 2, 3e-2)])
+                                             ("c3", 2, 3e-2), ("c5", 1, 1e-5), ("c5", 2, 3e-2)])
 def test_full_size_sampled(name, prec, bound):
     """The full workloads in one batched launch; sampled bands checked against the oracle
     (bounds per precision as in test_c2_reduced_precision)."""
@@ -245,3 +245,40 @@ def test_c2_mixed_against_float32():
     worst = max(band_rel_err(outs[1][ik], outs[0][ik]).max() for ik in range(w.nk))
     print(f"c2 mixed vs float32: max per-band rel diff {worst:.3e}")
     assert worst <= 2e-3
+
+
+def test_c2_permuted_miller_order():
+    """The caller's G order is arbitrary: the 8-atom cell with every k-point's Miller list
+    (and with it the columns of beta and of psi) in a seeded random order gives the oracle's
+    H|psi> in that order (float64, 1e-12 per band), and the same values as the canonical
+    order after undoing the permutation."""
+    import paper_2308_07277_amd as qm
+    w = workload.make_workload("c2")
+    from hpsi_inputs import plan_arrays
+    a = plan_arrays(w)
+    rng = np.random.Generator(np.random.PCG64(2024))
+    perms = [rng.permutation(int(n)) for n in w.npw]
+    b = dict(a)
+    b["miller"] = np.concatenate([m[p] for m, p in zip(w.miller, perms)]).astype(np.int32)
+    betas, off = [], 0
+    for ik in range(w.nk):
+        n = int(w.npw[ik])
+        bk = a["beta"][off:off + w.nproj * n].reshape(w.nproj, n)
+        betas.append(bk[:, perms[ik]].reshape(-1))
+        off += w.nproj * n
+    b["beta"] = np.concatenate(betas)
+    flat, per = psi_block(w, w.nbnd)
+    per_p = [p[:, q] for p, q in zip(per, perms)]
+    plan_p, _ = make_plan(w, w.nbnd, arrays=b)
+    out_p = split_k(_run(plan_p, w, w.nbnd, psi_flat=np.concatenate([x.reshape(-1) for x in per_p])),
+                    w, w.nbnd)
+    plan_c, _ = make_plan(w, w.nbnd, arrays=a)
+    out_c = split_k(_run(plan_c, w, w.nbnd, psi_flat=flat), w, w.nbnd)
+    for ik in range(w.nk):
+        m = w.miller[ik][perms[ik]]
+        bk = betas[ik].reshape(w.nproj, -1)
+        ref = ham.apply_h_ref(w.cell, w.grid, w.k_cryst[ik], m, a["vloc"], bk, a["dmat"], per_p[ik])
+        err = band_rel_err(out_p[ik], ref)
+        back = band_rel_err(out_p[ik], out_c[ik][:, perms[ik]])
+        print(f"k={ik}: permuted order vs oracle {err.max():.2e}, vs canonical {back.max():.2e}")
+        assert err.max() <= 1e-12 and back.max() <= 1e-12

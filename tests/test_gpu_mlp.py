@@ -2,8 +2,9 @@
 
 Bounds (float32 kernels vs float64 oracle): forward gains 1e-5 relative to the gain
 scale; loss within 1e-5; gradient within 1e-4 relative in norm (float32 accumulation over
-~1e3 rows per band); Adam update within 1e-6.  Training pairs: features, residuals and
-targets recomputed by the oracle from the returned Ritz vectors within 2e-5 relative."""
+~1e3 rows per band); Adam update within 1e-6.  Training pairs (test_training_pairs_vs_oracle):
+features, residuals and targets recomputed by the oracle from the returned Ritz vectors
+within 2e-5 relative (float32 storage of float64 values)."""
 import numpy as np
 import pytest
 
@@ -126,3 +127,90 @@ def test_trained_network_gain_on_small_cell():
     print("teter", it_t, "trained network", it_m)
     assert it_m < it_t
     assert np.abs(eig_t - eig_m).max() <= 1e-9
+
+
+def test_training_pairs_vs_oracle():
+    """qm_dav_training_pairs on the 8-atom cell (4 k, 32 bands) after three Davidson steps
+    from a random start: every row's features, residual and target recomputed by the oracle
+    from the Ritz vectors and Ritz values the step returned (residual r = H x - theta x with
+    oracle.hamiltonian, band kinetic energy <x|T|x>, oracle.mlp.features and
+    oracle.mlp.correction_target against the same converged eigenvectors).  The rows are
+    stored in float32, so the bound is 2e-5 relative: per element for the features (scale
+    max(1, |f|)), per band in norm for residuals and targets.  Rows are grouped by k-point,
+    then by unconverged band in ascending order."""
+    import torch
+    import workload
+    import paper_2308_07277_amd as qm
+    from oracle import hamiltonian as ham
+    from hpsi_inputs import make_plan, split_k
+    w = workload.make_workload("c2")
+    plan, a = make_plan(w, w.nbnd)
+    flat = lambda p: torch.cat([torch.from_numpy(w.psi(ik, purpose=p).reshape(-1)) for ik in range(w.nk)]).cuda()
+    xstar = flat(2)
+    estar, res, stats, st = qm.qm_davidson_solve(plan, -1, xstar, w.nbnd, tol=1e-10, max_iter=300)
+    assert st == 0
+    psi = flat(7)
+    eig, res, nun = qm.qm_davidson_step(plan, -1, psi, w.nbnd, tol=1e-8, restart=1)
+    for _ in range(2):
+        eig, res, nun = qm.qm_davidson_step(plan, -1, psi, w.nbnd, tol=1e-8)
+    cap = int(w.nbnd * w.npw.sum())
+    feat = torch.empty((cap, 5), dtype=torch.float32, device="cuda")
+    resid = torch.empty((cap, 2), dtype=torch.float32, device="cuda")
+    target = torch.empty((cap, 2), dtype=torch.float32, device="cuda")
+    bptr = torch.empty(w.nk * w.nbnd + 1, dtype=torch.int32, device="cuda")
+    nrows, nbands = qm.qm_dav_training_pairs(plan, xstar, estar, feat, resid, target, bptr)
+    f_g = feat[:nrows].cpu().numpy().astype(np.float64)
+    r_g = resid[:nrows].cpu().numpy().astype(np.float64)
+    t_g = target[:nrows].cpu().numpy().astype(np.float64)
+    ptr = bptr[:nbands + 1].cpu().numpy()
+    xs = split_k(psi.cpu().numpy(), w, w.nbnd)
+    xst = split_k(xstar.cpu().numpy(), w, w.nbnd)
+    b = 0
+    worst = {"feat": 0.0, "resid": 0.0, "target": 0.0}
+    for ik in range(w.nk):
+        un = np.nonzero(res[ik] > 1e-8)[0]
+        if un.size == 0:
+            continue
+        m = w.miller[ik]
+        off = int(sum(w.npw[:ik])) * w.nproj
+        beta = a["beta"][off:off + w.nproj * m.shape[0]].reshape(w.nproj, m.shape[0])
+        x = xs[ik][un]
+        r = ham.apply_h_ref(w.cell, w.grid, w.k_cryst[ik], m, a["vloc"], beta, a["dmat"], x) - eig[ik][un, None] * x
+        kin = ham.kinetic(w.cell, w.k_cryst[ik], m)
+        tkin = (np.abs(x) ** 2 * kin[None, :]).sum(1)
+        f_ref = omlp.features(kin, r, eig[ik][un], tkin)
+        d_ref = omlp.correction_target(xs[ik], xst[ik], estar[ik])[un]
+        for j in range(un.size):
+            s = slice(ptr[b], ptr[b + 1])
+            assert ptr[b + 1] - ptr[b] == m.shape[0]
+            fe = np.abs(f_g[s] - f_ref[j]) / np.maximum(1.0, np.abs(f_ref[j]))
+            re = np.linalg.norm(r_g[s, 0] + 1j * r_g[s, 1] - r[j]) / np.linalg.norm(r[j])
+            te = np.linalg.norm(t_g[s, 0] + 1j * t_g[s, 1] - d_ref[j]) / np.linalg.norm(d_ref[j])
+            worst["feat"] = max(worst["feat"], fe.max())
+            worst["resid"] = max(worst["resid"], re)
+            worst["target"] = max(worst["target"], te)
+            b += 1
+    print("training rows", nrows, "bands", nbands, "worst relative errors", worst)
+    assert b == nbands and b > 0
+    assert worst["feat"] <= 2e-5 and worst["resid"] <= 2e-5 and worst["target"] <= 2e-5
+
+
+def test_training_pairs_reject_buffer_bands():
+    """A Davidson state with buffer bands holds rows that the [nk][nbnd] arrays of the
+    converged eigenvectors do not have: qm_dav_training_pairs refuses it (QM_E_STATE)."""
+    import torch
+    import workload
+    import paper_2308_07277_amd as qm
+    from hpsi_inputs import make_plan
+    w = workload.make_workload("c1")
+    plan, a = make_plan(w, w.nbnd + 4)
+    x = torch.from_numpy(w.psi(0, purpose=2).reshape(-1).copy()).cuda()
+    qm.qm_davidson_step(plan, 0, x, w.nbnd, restart=1, extra_bands=4)
+    n = int(w.nbnd * w.npw[0])
+    feat = torch.empty((n, 5), dtype=torch.float32, device="cuda")
+    r2 = torch.empty((n, 2), dtype=torch.float32, device="cuda")
+    t2 = torch.empty((n, 2), dtype=torch.float32, device="cuda")
+    bptr = torch.empty(w.nbnd + 1, dtype=torch.int32, device="cuda")
+    with pytest.raises(qm.QmError) as e:
+        qm.qm_dav_training_pairs(plan, x, np.zeros((1, w.nbnd)), feat, r2, t2, bptr)
+    assert e.value.code == qm.QM_E_STATE
