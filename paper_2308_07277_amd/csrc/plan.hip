@@ -400,7 +400,13 @@ qm_status qm_apply_h_timed(qm_hpsi_plan* plan, int32_t k, const void* psi, void*
                            int32_t nbnd, double* times_ms, void* stream) {
   if (!plan) return QM_E_ARG;
   StageEvents ev{};
-  bool created = false;
+  struct Release {   // the events are destroyed on every return path
+    StageEvents& e;
+    ~Release() {
+      for (hipEvent_t& x : e.ev)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } release{ev};
   QM_API_GUARD(plan, {
     QM_REQUIRE(times_ms, QM_E_ARG, "times_ms must be non-NULL");
     QM_REQUIRE(psi && hpsi && psi != hpsi, QM_E_ARG, "psi and hpsi must be distinct and non-NULL");
@@ -409,7 +415,6 @@ qm_status qm_apply_h_timed(qm_hpsi_plan* plan, int32_t k, const void* psi, void*
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     ev.s = s;
     for (int i = 0; i <= QM_NSTAGES; ++i) QM_HIP(hipEventCreate(&ev.ev[i]));
-    created = true;
     for (int i = 0; i < QM_NSTAGES; ++i) ev.used[i] = false;
     const int k0 = k < 0 ? 0 : k, k1 = k < 0 ? plan->nk : k + 1;
     QM_REQUIRE(k1 - k0 <= kMaxSlices, QM_E_ARG, "timed application handles at most 32 k-points");
@@ -426,8 +431,6 @@ qm_status qm_apply_h_timed(qm_hpsi_plan* plan, int32_t k, const void* psi, void*
         last = i + 1;
       }
     }
-    for (int i = 0; i <= QM_NSTAGES; ++i) (void)hipEventDestroy(ev.ev[i]);
-    created = false;
   })
 }
 
