@@ -207,6 +207,26 @@ qm_status qm_apply_h(qm_hpsi_plan *plan, int32_t k, const void *psi, void *hpsi,
 qm_status qm_apply_h_timed(qm_hpsi_plan *plan, int32_t k, const void *psi, void *hpsi,
                            int32_t nbnd, double *times_ms, void *stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph capture, serving
+ * loops, harnesses that forbid hipMalloc.  The same H|psi> as qm_apply_h (same arguments,
+ * layouts, precision and results to rounding), launched kernel by kernel on stream, with no
+ * device or pinned allocation and no graph of its own.  Its working memory (stick buffer,
+ * projections, split-K partial sums) is one static device array of QM_NOALLOC_SCRATCH_MIB
+ * MiB, of which each GPU the library runs on holds its own copy until the process ends, in
+ * place of the plan's own buffers; k-points are applied one after the other, their bands in
+ * chunks that fit in the array.  Every call on one GPU shares that GPU's array: calls whose
+ * work may overlap in time on one GPU (different streams, or different host threads) race
+ * and give wrong results - serialise them.  Errors: QM_E_ARG as for qm_apply_h, and when one
+ * band of a k-point needs more working memory than the array holds (sizes below); QM_E_STATE
+ * when the plan's precision needs the reduced-precision copy of beta and it has
+ * not been built (call qm_hpsi_plan_set_precision, which builds it, before capturing).
+ * Per band of k the array must hold nstick_k * N3 * (16 in float64, 8 otherwise) bytes of
+ * sticks plus 3 * nproj * 16 bytes: the 216-atom cell at 108^3 needs 3.9 MB per band in
+ * float64, so 64 MiB processes 17 bands at a time. */
+#define QM_NOALLOC_SCRATCH_MIB 64
+qm_status qm_apply_h_noalloc(qm_hpsi_plan *plan, int32_t k, const void *psi, void *hpsi,
+                             int32_t nbnd, void *stream);
+
 /* ------------------------------------------------------------------ Davidson */
 
 /* One block-Davidson iteration (Sec. 5, 'dft' module: the Davidson "with overlap" that

@@ -84,6 +84,7 @@ def _load():
         "qm_hpsi_plan_autotune": [_P, i32, _P],
         "qm_apply_h": [_P, i32, _P, _P, i32, _P],
         "qm_apply_h_timed": [_P, i32, _P, _P, i32, _P, _P],
+        "qm_apply_h_noalloc": [_P, i32, _P, _P, i32, _P],
         "qm_davidson_step": [_P, i32, _P, _P, _P, i32, ctypes.POINTER(qm_dav_opts), _P, _P],
         "qm_davidson_solve": [_P, i32, _P, _P, _P, i32, ctypes.POINTER(qm_dav_opts),
                               ctypes.POINTER(qm_dav_stats), _P],
@@ -214,6 +215,18 @@ def qm_apply_h(plan, k, psi, hpsi, nbnd, stream=None):
     _check(_load().qm_apply_h(plan.handle, int(k), _dev(psi, torch.complex128, "psi"),
                               _dev(hpsi, torch.complex128, "hpsi"), int(nbnd), _stream(stream)),
            plan.handle)
+
+
+def qm_apply_h_noalloc(plan, k, psi, hpsi, nbnd, stream=None):
+    """qm_apply_h without any device allocation (working memory in the library's static
+    scratch array); same arguments and results."""
+    import torch
+    n = plan.band_block_numel(nbnd, k)
+    if n is not None and (psi.numel() != n or hpsi.numel() != n):
+        raise ValueError(f"psi/hpsi must hold {n} elements for nbnd={nbnd}, k={k}")
+    _check(_load().qm_apply_h_noalloc(plan.handle, int(k), _dev(psi, torch.complex128, "psi"),
+                                      _dev(hpsi, torch.complex128, "hpsi"), int(nbnd),
+                                      _stream(stream)), plan.handle)
 
 
 QM_NSTAGES = 7

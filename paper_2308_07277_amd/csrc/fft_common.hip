@@ -5,9 +5,9 @@
 namespace qm {
 
 void launch_local_f64(qm_hpsi_plan*, const std::vector<KSlice>&, const void*, void*, hipStream_t,
-                      StageEvents*);
+                      StageEvents*, const HpsiWork*);
 void launch_local_f32(qm_hpsi_plan*, const std::vector<KSlice>&, const void*, void*, hipStream_t,
-                      StageEvents*);
+                      StageEvents*, const HpsiWork*);
 
 bool fft_len_supported(int n) {
   switch (n) {
@@ -39,11 +39,11 @@ int fft_split_r2(int n) {
 }
 
 void launch_hpsi_local(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
-                       hipStream_t s, bool fp32, StageEvents* ev) {
+                       hipStream_t s, bool fp32, StageEvents* ev, const HpsiWork* wk) {
   if (fp32)
-    launch_local_f32(p, sl, psi, hpsi, s, ev);
+    launch_local_f32(p, sl, psi, hpsi, s, ev, wk);
   else
-    launch_local_f64(p, sl, psi, hpsi, s, ev);
+    launch_local_f64(p, sl, psi, hpsi, s, ev, wk);
 }
 
 int xy_group_lanes(int nx) { return nx == 20 || nx == 40 ? 2 : (nx == 72 ? 8 : 0); }
@@ -69,15 +69,17 @@ std::vector<KSlice> contiguous_slices(const qm_hpsi_plan* p, int k0, int k1, int
 }
 
 void apply_h_slices(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
-                    hipStream_t s, qm_prec prec, StageEvents* ev, const ProjScratch* ps) {
+                    hipStream_t s, qm_prec prec, StageEvents* ev, const ProjScratch* ps,
+                    const HpsiWork* wk) {
+  QM_REQUIRE(!wk || sl.size() == 1, QM_E_STATE, "caller-given working memory takes one slice");
   for (size_t b = 0; b < sl.size(); b += kMaxSlices) {
     std::vector<KSlice> chunk(sl.begin() + b, sl.begin() + std::min(sl.size(), b + kMaxSlices));
     std::vector<KSlice> nz;
     for (const KSlice& x : chunk)
       if (x.nb > 0) nz.push_back(x);
     if (nz.empty()) continue;
-    launch_hpsi_local(p, nz, psi, hpsi, s, prec != QM_PREC_FP64, ev);
-    launch_nonlocal(p, nz, psi, hpsi, s, prec, ev, ps);
+    launch_hpsi_local(p, nz, psi, hpsi, s, prec != QM_PREC_FP64, ev, wk);
+    launch_nonlocal(p, nz, psi, hpsi, s, prec, ev, ps, wk);
   }
 }
 

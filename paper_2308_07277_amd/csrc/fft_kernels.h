@@ -48,14 +48,17 @@ struct LocalArgs {
   const double2* tw_x;      // exp(+2 pi i m / N1)
   int32_t ts;               // sticks per tile
   int32_t nax_stride;       // row stride of the xy-plane buffer (elements)
+  int32_t sbuf_per_k;       // 1: k's stick block at sbuf + kinfo[k].sbuf_off; 0: at sbuf (one slice)
 };
 
-// This k's stick buffer.  Its region starts at the same byte offset (sbuf_off complex
-// double elements) whatever the working precision, so k-points that run in different
-// precisions at the same time (concurrent Davidson lanes) never share bytes.
+// This k's stick buffer.  In the plan's buffer its region starts at the same byte offset
+// (sbuf_off complex double elements) whatever the working precision, so k-points that run in
+// different precisions at the same time (concurrent Davidson lanes) never share bytes.  A
+// caller-given buffer holds the one slice of its launch from its start.
 template <typename R>
-__device__ __forceinline__ cplx<R>* stick_base(void* sbuf, const KInfo& ki) {
-  return reinterpret_cast<cplx<R>*>(reinterpret_cast<char*>(sbuf) + ki.sbuf_off * int64_t(16));
+__device__ __forceinline__ cplx<R>* stick_base(const LocalArgs& a, const KInfo& ki) {
+  return reinterpret_cast<cplx<R>*>(reinterpret_cast<char*>(a.sbuf) +
+                                    (a.sbuf_per_k ? ki.sbuf_off * int64_t(16) : int64_t(0)));
 }
 
 // slice holding z-kernel block bid; bid becomes the block index within the slice
@@ -175,7 +178,7 @@ __global__ void __launch_bounds__(TS * Split<N3>::R2) k_zinv(LocalArgs a) {
 #pragma unroll
     for (int n1 = 0; n1 < R1; ++n1) y[n1] = tile[(n1 + R1 * j) * TS + sl];
     Dft<R1, +1, R>::run(y);
-    cplx<R>* out = stick_base<R>(a.sbuf, ki) +
+    cplx<R>* out = stick_base<R>(a, ki) +
                    int64_t(band) * N3 * ki.nstick + s0 + sl;
 #pragma unroll
     for (int k1 = 0; k1 < R1; ++k1) out[int64_t(k1 + R1 * j) * ki.nstick] = y[k1];
@@ -218,7 +221,7 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
   const int k = a.sl[si].k, band = kb - a.pair0[si];
   const KInfo ki = a.kinfo[k];
   const int nax = ki.nax;
-  cplx<R>* plane = stick_base<R>(a.sbuf, ki) +
+  cplx<R>* plane = stick_base<R>(a, ki) +
                    (int64_t(band) * N3 + p) * ki.nstick;
   const int32_t* spos = a.stick_pos + ki.stick_off;
   // the first group of sticks is loaded before the tables, the zero fill and their barrier,
@@ -501,7 +504,7 @@ __global__ void __launch_bounds__(L * NX) k_xy_group(LocalArgs a) {
   }
   for (int i = tid; i < NX * ns; i += NT) Lp[i] = {R(0), R(0)};
   __syncthreads();
-  cplx<R>* plane = stick_base<R>(a.sbuf, ki) +
+  cplx<R>* plane = stick_base<R>(a, ki) +
                    (int64_t(band) * N3 + p) * ki.nstick;
   const int32_t* spos = a.stick_pos + ki.stick_off;
   sticks_to_lds<R, NT>(plane, spos, ki.nstick, Lp, ns, tid);
@@ -578,7 +581,7 @@ __global__ void __launch_bounds__(TS * Split<N3>::R2) k_zfwd(LocalArgs a) {
   __syncthreads();
   const int sl = tid % TS, j = tid / TS;  // j in [0, R2)
   {
-    const cplx<R>* in = static_cast<const cplx<R>*>(stick_base<R>(a.sbuf, ki)) +
+    const cplx<R>* in = static_cast<const cplx<R>*>(stick_base<R>(a, ki)) +
                         int64_t(band) * N3 * ki.nstick + s0 + sl;
     cplx<R> x[R1];
 #pragma unroll

@@ -9,7 +9,7 @@ constexpr int kZTile = 32;  // sticks per z-kernel tile (the plan's tile tables 
 
 template <typename R>
 void launch_local_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
-                    hipStream_t s, StageEvents* ev) {
+                    hipStream_t s, StageEvents* ev, const HpsiWork* wk) {
   LocalArgs a{};
   QM_REQUIRE(!sl.empty() && sl.size() <= size_t(kMaxSlices), QM_E_STATE, "bad slice count");
   a.kinfo = p->g.kinfo;
@@ -27,7 +27,8 @@ void launch_local_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* 
   a.pair0[sl.size()] = int32_t(npair);
   a.psi = reinterpret_cast<const double2*>(psi);
   a.hpsi = reinterpret_cast<double2*>(hpsi);
-  a.sbuf = p->sbuf;
+  a.sbuf = wk ? wk->sbuf : p->sbuf;
+  a.sbuf_per_k = wk ? 0 : 1;
   a.ent_g = p->g.ent_g;
   a.ent_sz = p->g.ent_sz;
   a.tile_ptr = p->g.tile_ptr;

@@ -29,15 +29,18 @@ __global__ void k_apply_d(const double2* __restrict__ P, double2* __restrict__ Q
 }
 
 void launch_nonlocal_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi,
-                       void* hpsi, hipStream_t s, StageEvents* ev, int lp, const ProjScratch* ps) {
+                       void* hpsi, hipStream_t s, StageEvents* ev, int lp, const ProjScratch* ps,
+                       const HpsiWork* wk) {
   if (p->nproj == 0) return;
   const int np = p->nproj;
-  double2* P = reinterpret_cast<double2*>(p->proj_q);
-  double2* Q = P + int64_t(p->nk) * np * p->nbnd_max;
+  double2* P = wk ? wk->P : reinterpret_cast<double2*>(p->proj_q);
+  double2* Q = wk ? wk->Q : P + int64_t(p->nk) * np * p->nbnd_max;
+  // P and Q blocks of slice x: at k nproj nbnd_max in the plan's buffers, at 0 in the caller's
+  auto pq_off = [&](const KSlice& x) { return wk ? int64_t(0) : int64_t(x.k) * np * p->nbnd_max; };
   std::vector<GemmCN> cn;
   std::vector<GemmEX> ex;
   for (const KSlice& x : sl) {
-    const int64_t off = int64_t(x.k) * np * p->nbnd_max;   // P and Q blocks of this k
+    const int64_t off = pq_off(x);
     const KInfo& ki = p->kinfo[x.k];
     const char* bbase = reinterpret_cast<const char*>(lp == 0 ? p->beta64 : p->beta_lp);
     const size_t esz = lp == 0 ? 16 : (lp == 1 ? 8 : 4);
@@ -47,12 +50,12 @@ void launch_nonlocal_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const voi
     cn.push_back(GemmCN{bk, pk, P + off, np, x.nb, ki.npw, ki.npw, ki.npw, x.nb});
     ex.push_back(GemmEX{Q + off, bk, hk, x.nb, ki.npw, np, x.nb, ki.npw, ki.npw});
   }
-  void* part = ps ? ps->part : p->proj_part;
-  const int64_t part_bytes = ps ? ps->bytes : p->proj_part_bytes;
+  void* part = wk ? wk->part : (ps ? ps->part : p->proj_part);
+  const int64_t part_bytes = wk ? wk->part_bytes : (ps ? ps->bytes : p->proj_part_bytes);
   zgemm_cn_batched(cn, 1.0, 0.0, part, part_bytes, s, ev, 3, lp, p->tuned_splits[lp]);
   // D acts on each slice's [np][nb] block
   for (const KSlice& x : sl) {
-    const int64_t base = int64_t(x.k) * np * p->nbnd_max;
+    const int64_t base = pq_off(x);
     const int64_t total = int64_t(np) * x.nb;
     const int blocks = int(std::min<int64_t>((total + 255) / 256, 16384));
     hipLaunchKernelGGL(k_apply_d, dim3(blocks), dim3(256), 0, s, P + base, Q + base, p->dmat,
@@ -65,10 +68,14 @@ void launch_nonlocal_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const voi
 }
 
 void launch_nonlocal(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
-                     hipStream_t s, qm_prec prec, StageEvents* ev, const ProjScratch* ps) {
+                     hipStream_t s, qm_prec prec, StageEvents* ev, const ProjScratch* ps,
+                     const HpsiWork* wk) {
   const int lp = prec == QM_PREC_FP64 ? 0 : (prec == QM_PREC_FP32 ? 1 : 2);
-  if (lp != 0 && p->beta_lp_kind != lp) convert_beta(p, prec, s);
-  launch_nonlocal_t(p, sl, psi, hpsi, s, ev, lp, ps);
+  if (lp != 0 && p->beta_lp_kind != lp) {
+    QM_REQUIRE(!wk, QM_E_STATE, "the reduced-precision copy of beta is not built");
+    convert_beta(p, prec, s);
+  }
+  launch_nonlocal_t(p, sl, psi, hpsi, s, ev, lp, ps, wk);
 }
 
 // low-precision copy of beta for the FP32 (c64) or MIXED (bf16 pairs) projector GEMMs

@@ -146,9 +146,22 @@ struct qm_hpsi_plan {
 };
 
 namespace qm {
+// Working memory of one H application given by the caller instead of the plan's buffers
+// (the allocation-free entry point): one k-point slice per launch sequence, its stick block
+// at sbuf, its projections P and D-applied block Q at P and Q ([nproj][nb] c128 each), the
+// projector GEMM's split-K partial sums in part.  nullptr everywhere below means the plan's
+// own buffers (stick block of k at kinfo[k].sbuf_off, P/Q blocks of k at k nproj nbnd_max).
+struct HpsiWork {
+  void* sbuf = nullptr;
+  double2* P = nullptr;
+  double2* Q = nullptr;
+  void* part = nullptr;
+  int64_t part_bytes = 0;
+};
 // launchers (fft.hip / gemm.hip); k0..k1 is the k range, psi/hpsi point at k0's first band
 void launch_hpsi_local(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
-                       hipStream_t s, bool fp32, StageEvents* ev = nullptr);
+                       hipStream_t s, bool fp32, StageEvents* ev = nullptr,
+                       const HpsiWork* wk = nullptr);
 void launch_vplan(qm_hpsi_plan* p, const double* vloc_r, hipStream_t s);
 // Split-K scratch of the projector GEMM.  Calls that may run at the same time on different
 // streams (Davidson lanes, which own disjoint k-points) each pass their own.
@@ -158,12 +171,12 @@ struct ProjScratch {
 };
 void launch_nonlocal(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
                      hipStream_t s, qm_prec prec, StageEvents* ev = nullptr,
-                     const ProjScratch* ps = nullptr);
+                     const ProjScratch* ps = nullptr, const HpsiWork* wk = nullptr);
 // H applied to every slice (local + non-local), in chunks of kMaxSlices.  At most one slice
 // per k-point per call (stick buffer, P and Q are addressed per k).
 void apply_h_slices(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
                     hipStream_t s, qm_prec prec, StageEvents* ev = nullptr,
-                    const ProjScratch* ps = nullptr);
+                    const ProjScratch* ps = nullptr, const HpsiWork* wk = nullptr);
 std::vector<KSlice> contiguous_slices(const qm_hpsi_plan* p, int k0, int k1, int nbnd);
 int xy_group_lanes(int nx);                       // lanes per line of the lane-group kernel, 0: none
 int xy_pick(const qm_hpsi_plan* p, int real_type);  // 1 two-pass, 2 lane-group
