@@ -14,6 +14,7 @@ Modules
                dense H_GG' and apply_h_ref (Secs. 2.2, 2.3, 4.3)
   davidson     block Davidson with Teter preconditioner (Sec. 5 'dft' module)
   mlp          2-layer residual->correction MLP: forward, backward, Adam, loss
+  density      electron density, Hartree potential and energy, Hartree-only SCF (Sec. 2.1)
 
 Parity pins live in tests/ (``-m "not gpu"``); functions without a pin say
 "parity unpinned" in their docstring.
