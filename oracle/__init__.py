@@ -15,6 +15,7 @@ Modules
   davidson     block Davidson with Teter preconditioner (Sec. 5 'dft' module)
   mlp          2-layer residual->correction MLP: forward, backward, Adam, loss
   density      electron density, Hartree potential and energy, Hartree-only SCF (Sec. 2.1)
+  tddft        Taylor exponential, ETRS propagation of the Hartree-only model (Secs. 2.4, 5)
 
 Parity pins live in tests/ (``-m "not gpu"``); functions without a pin say
 "parity unpinned" in their docstring.
