@@ -16,6 +16,7 @@ Modules
   mlp          2-layer residual->correction MLP: forward, backward, Adam, loss
   density      electron density, Hartree potential and energy, Hartree-only SCF (Sec. 2.1)
   tddft        Taylor exponential, ETRS propagation of the Hartree-only model (Secs. 2.4, 5)
+  gw           plane-wave matrix elements M_nn'(k, q, G) of the GW polarizability (Sec. 5)
 
 Parity pins live in tests/ (``-m "not gpu"``); functions without a pin say
 "parity unpinned" in their docstring.
