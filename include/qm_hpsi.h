@@ -301,6 +301,112 @@ qm_status qm_dav_training_pairs(qm_hpsi_plan *plan, const void *x_star, const do
                                 int32_t *band_ptr, int64_t cap_rows, int32_t cap_bands,
                                 int64_t *nrows, int32_t *nbands, void *stream);
 
+/* ------------------------------------------------------------------ density, Hartree, SCF */
+
+/* Electron density (Sec. 2.1: n(r) = sum_i f_i |psi_i(r)|^2 over the occupied states) of
+ * the band block psi on the plan's FFT grid:
+ *   rho(r) = sum_k weights[k] sum_n occ[k][n] |psi_kn(r)|^2,
+ *   psi_kn(r) = Omega^-1/2 sum_G c_kn(G) e^{i(k+G).r},
+ * so unit-norm bands integrate to one over the cell and rho integrates to
+ * sum_k weights[k] sum_n occ[k][n] (occ = 2 for a doubly occupied band, weights summing to 1).
+ *  k        k index, or -1 for every k of the plan (at most 32).
+ *  psi      device c128 [nk_sel][nbnd][npw_k] (as qm_apply_h).
+ *  weights  host float64 [nk_sel] k-point weights; occ host float64 [nk_sel][nbnd].
+ *  rho      device float64 [N1][N2][N3], C order, grid point j at sum_i (j_i/N_i) a_i; e/bohr^3.
+ * Float64 whatever the plan's precision; deterministic (groups of bands are summed in a
+ * fixed order).  Uses the plan's stick buffer: not concurrent with other calls on the plan. */
+qm_status qm_density(qm_hpsi_plan *plan, int32_t k, const void *psi, int32_t nbnd,
+                     const double *weights, const double *occ, double *rho, void *stream);
+
+/* Hartree potential (Sec. 2.1, the Hartree term of V_aux: the classical potential of the
+ * charge density), the periodic solution of Poisson's equation in Hartree units:
+ *   V_H(G) = 4 pi n(G) / |G|^2 for G != 0, V_H(G = 0) = 0,
+ *   n(G) = (1/N_r) sum_r rho(r) e^{-iG.r}, G = m.B with m in the centred range of the grid.
+ *  rho, vh    device float64 [N1][N2][N3] (layout as qm_density); vh must not alias rho.
+ *  e_hartree  host, may be NULL: 1/2 integral V_H rho = 1/2 (Omega/N_r) sum_r V_H rho (Ha).
+ * Synchronises the stream when e_hartree is requested. */
+qm_status qm_hartree(qm_hpsi_plan *plan, const double *rho, double *vh, double *e_hartree,
+                     void *stream);
+
+/* Replace the plan's local potential V(r) (device float64 [N1][N2][N3], Ha, layout as in
+ * qm_hpsi_plan_create); later H applications (and captured graphs) use the new values. */
+qm_status qm_hpsi_plan_set_vloc(qm_hpsi_plan *plan, const double *vloc_r, void *stream);
+
+/* Hartree-only SCF options (host); zero fields take the defaults in brackets. */
+typedef struct {
+  double alpha;           /* linear mixing n <- n + alpha (n_out - n) [0.7] */
+  double tol;             /* stop when ||n_out - n||_2 over the cell <= tol (electrons/bohr^1.5) [1e-9] */
+  int32_t max_iter;       /* SCF iterations [100] */
+  int32_t pad;
+  qm_dav_opts dav;        /* options of the Davidson solve of every iteration [tol 1e-10] */
+} qm_scf_opts;
+
+typedef struct {
+  int32_t iterations;     /* SCF iterations done */
+  int32_t converged;      /* 1 if the density residual reached tol */
+  int64_t dav_iterations; /* Davidson iterations summed over the SCF iterations */
+  int64_t n_hpsi_bands;   /* band-applications of H summed over the SCF iterations */
+  double residual;        /* final ||n_out - n||_2 */
+  double e_hartree;       /* Hartree energy of the final density, Ha */
+  double t_total_ms;      /* wall time */
+} qm_scf_stats;
+
+/* Hartree-only self-consistent field (Sec. 2.1, the cycle n -> V -> {psi} -> n_out, mixed until
+ * n_out = n; exchange-correlation left out): starting from the uniform density, every
+ * iteration sets V = vext + V_H[n] (qm_hartree, qm_hpsi_plan_set_vloc), solves the Davidson
+ * for nbnd bands of every k from the previous iteration's vectors (qm_davidson_solve), forms
+ * n_out from the nocc lowest bands of every k doubly occupied with the k weights (qm_density)
+ * and mixes linearly (the paper's code uses Broyden mixing; linear mixing here).
+ *  vext      device float64 [N1][N2][N3] external (ionic) potential, Ha.
+ *  kweights  host float64 [nk]; the electron count is 2 nocc sum_k kweights[k].
+ *  psi       device c128 [nk][nbnd][npw_k]: in, start vectors; out, the last Davidson vectors.
+ *  eig       host float64 [nk][nbnd]: last Ritz values.  rho, vh: device float64 grids, out:
+ *            the final density and its Hartree potential.
+ * The plan keeps the last iteration's V.  QM_E_NOT_CONVERGED (outputs filled) when max_iter is
+ * reached; Davidson errors are passed on. */
+qm_status qm_scf_hartree(qm_hpsi_plan *plan, const double *vext_r, const double *kweights,
+                         int32_t nocc, void *psi, int32_t nbnd, const qm_scf_opts *opts,
+                         double *eig, double *rho, double *vh, qm_scf_stats *stats, void *stream);
+
+/* ------------------------------------------------------------------ real-time propagation */
+
+/* psi_out = sum_{r=0}^{order} (-i dt)^r / r! H^r psi_in (Sec. 5, 'tddft' module: the Taylor
+ * expansion of exp(-i dt H) truncated at order k), with the plan's H and precision; the
+ * series is built term by term, t_r = (-i dt / r) H t_{r-1}.
+ *  k             k index or -1 for every k (layouts as qm_apply_h); psi_in may equal psi_out.
+ *  dt            time step in Hartree atomic units (hbar / Ha); 1 <= order <= 64.
+ * Work buffers (4 band blocks of nbnd_max bands over every k, 3 grids) are allocated in the
+ * plan on first use. */
+qm_status qm_expm_taylor(qm_hpsi_plan *plan, int32_t k, const void *psi_in, void *psi_out,
+                         int32_t nbnd, double dt, int32_t order, void *stream);
+
+/* nsteps steps of the enforced-time-reversal-symmetry propagator (Sec. 5, 'tddft' module, prop;
+ * the time-dependent Kohn-Sham equations of Sec. 2.4) for the Hartree-only model
+ * H[psi] = T + V_ext + V_H[n(psi)] + V_NL, n(psi) = sum_k kweights[k] sum_n occ[k][n] |psi_kn|^2:
+ *   psi_bar   = exp(-i dt H[psi_n]) psi_n,
+ *   psi_{n+1} = exp(-i dt H[psi_bar] / 2) exp(-i dt H[psi_n] / 2) psi_n,
+ * each exponential by qm_expm_taylor with the given order.  psi (device c128 [nk][nbnd][npw_k])
+ * is advanced in place; the plan's V is left at V_ext + V_H[n(psi_bar)] of the last step. */
+qm_status qm_td_etrs(qm_hpsi_plan *plan, const double *vext_r, const double *kweights,
+                     const double *occ, void *psi, int32_t nbnd, double dt, int32_t order,
+                     int32_t nsteps, void *stream);
+
+/* ------------------------------------------------------------------ GW matrix elements */
+
+/* Plane-wave matrix elements of the GW polarizability (Sec. 5, 'gw' module, Epsilon matrix
+ * elements):  M[n][n'][g] = <n k+q| e^{i(q+G_g).r} |n' k> = sum_G' conj(c_{n,kq}(G_g + G'))
+ * c_{n',k}(G'), computed as the paper describes: both band sets to real space (inverse FFT),
+ * the product conj(u_{n,k+q}(r)) u_{n',k}(r), its inverse FFT (with 1/N_r) read at G_g.
+ *  kq, k     plan k-point indices of k+q and of k (their spheres hold the coefficients).
+ *  psi_kq    device c128 [nb1][npw_kq]; psi_k device c128 [nb2][npw_k].
+ *  miller_g  host int32 [ng][3], 2|m_i| < N_i; mtx device c128 [nb1][nb2][ng].
+ * The grid must hold the products without aliasing (components up to the sum of the two
+ * spheres' radii).  Float64; allocates (nb1 + 2 nb2) full complex grids for the call;
+ * synchronises the stream. */
+qm_status qm_mtxel(qm_hpsi_plan *plan, int32_t kq, const void *psi_kq, int32_t nb1, int32_t k,
+                   const void *psi_k, int32_t nb2, const int32_t *miller_g, int32_t ng, void *mtx,
+                   void *stream);
+
 #ifdef __cplusplus
 }
 #endif

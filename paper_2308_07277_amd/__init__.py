@@ -51,6 +51,21 @@ class qm_dav_opts(ctypes.Structure):
                 ("extra_bands", ctypes.c_int32), ("subspace_fp32", ctypes.c_int32)]
 
 
+class qm_scf_opts(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_double), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("dav", qm_dav_opts)]
+
+
+class qm_scf_stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("dav_iterations", ctypes.c_int64), ("n_hpsi_bands", ctypes.c_int64),
+                ("residual", ctypes.c_double), ("e_hartree", ctypes.c_double),
+                ("t_total_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class qm_dav_stats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("n_hpsi_bands", ctypes.c_int64), ("n_hpsi_bands_lowp", ctypes.c_int64),
@@ -92,6 +107,14 @@ def _load():
         "qm_mlp_loss_grad": [_P, _P, _P, _P, _P, i32, _P, _P, _P],
         "qm_dav_training_pairs": [_P, _P, _P, dbl, _P, _P, _P, _P, i64, i32, _P, _P, _P],
         "qm_mlp_adam": [_P, _P, _P, _P, i32, flt, flt, flt, flt, _P],
+        "qm_density": [_P, i32, _P, i32, _P, _P, _P, _P],
+        "qm_hartree": [_P, _P, _P, _P, _P],
+        "qm_hpsi_plan_set_vloc": [_P, _P, _P],
+        "qm_scf_hartree": [_P, _P, _P, i32, _P, i32, ctypes.POINTER(qm_scf_opts), _P, _P, _P,
+                           ctypes.POINTER(qm_scf_stats), _P],
+        "qm_expm_taylor": [_P, i32, _P, _P, i32, dbl, i32, _P],
+        "qm_td_etrs": [_P, _P, _P, _P, _P, i32, dbl, i32, i32, _P],
+        "qm_mtxel": [_P, i32, _P, i32, i32, _P, i32, _P, i32, _P, _P],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -331,3 +354,105 @@ def qm_mlp_adam(weights, grad, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-
                                _dev(grad, torch.float32, "grad"), _dev(m, torch.float32, "m"),
                                _dev(v, torch.float32, "v"), int(t), float(lr), float(beta1),
                                float(beta2), float(eps), _stream(stream)))
+
+
+def qm_density(plan, k, psi, nbnd, weights, occ, rho, stream=None):
+    """rho <- sum_k w_k sum_n f_kn |psi_kn(r)|^2 on the plan's grid (float64 device tensor
+    [N1, N2, N3]); weights [nk_sel], occ [nk_sel, nbnd] host arrays."""
+    import torch
+    nks = plan.nk if k < 0 else 1
+    w = np.ascontiguousarray(weights, np.float64).reshape(-1)
+    f = np.ascontiguousarray(occ, np.float64).reshape(-1)
+    if w.size != nks or f.size != nks * nbnd:
+        raise ValueError("weights must hold nk_sel values and occ nk_sel * nbnd")
+    n = plan.band_block_numel(nbnd, k)
+    if n is not None and psi.numel() != n:
+        raise ValueError(f"psi must hold {n} elements")
+    if rho.numel() != int(np.prod(plan.grid)):
+        raise ValueError("rho must hold N1*N2*N3 values")
+    _check(_load().qm_density(plan.handle, int(k), _dev(psi, torch.complex128, "psi"), int(nbnd),
+                              w.ctypes.data, f.ctypes.data, _dev(rho, torch.float64, "rho"),
+                              _stream(stream)), plan.handle)
+
+
+def qm_hartree(plan, rho, vh, energy=False, stream=None):
+    """vh <- Hartree potential of rho (float64 device grids); returns E_H if energy."""
+    import torch
+    for t, nm in ((rho, "rho"), (vh, "vh")):
+        if t.numel() != int(np.prod(plan.grid)):
+            raise ValueError(f"{nm} must hold N1*N2*N3 values")
+    e = ctypes.c_double(0.0)
+    _check(_load().qm_hartree(plan.handle, _dev(rho, torch.float64, "rho"), _dev(vh, torch.float64, "vh"),
+                              ctypes.byref(e) if energy else None, _stream(stream)), plan.handle)
+    return e.value if energy else None
+
+
+def qm_hpsi_plan_set_vloc(plan, vloc_r, stream=None):
+    import torch
+    if vloc_r.numel() != int(np.prod(plan.grid)):
+        raise ValueError("vloc_r must hold N1*N2*N3 values")
+    _check(_load().qm_hpsi_plan_set_vloc(plan.handle, _dev(vloc_r, torch.float64, "vloc_r"),
+                                         _stream(stream)), plan.handle)
+
+
+def qm_scf_hartree(plan, vext, kweights, nocc, psi, nbnd, rho, vh, alpha=0.0, tol=0.0, max_iter=0,
+                   stream=None, **dav_opts):
+    """Hartree-only SCF; returns (eig [nk, nbnd], stats dict, status)."""
+    import torch
+    kw = np.ascontiguousarray(kweights, np.float64).reshape(-1)
+    if kw.size != plan.nk:
+        raise ValueError("kweights must hold nk values")
+    n = plan.band_block_numel(nbnd, -1)
+    if psi.numel() != n:
+        raise ValueError(f"psi must hold {n} elements")
+    for t, nm in ((vext, "vext"), (rho, "rho"), (vh, "vh")):
+        if t.numel() != int(np.prod(plan.grid)):
+            raise ValueError(f"{nm} must hold N1*N2*N3 values")
+    o = qm_scf_opts(float(alpha), float(tol), int(max_iter), 0, _opts(**dav_opts))
+    eig = np.zeros((plan.nk, nbnd))
+    st = qm_scf_stats()
+    status = _load().qm_scf_hartree(plan.handle, _dev(vext, torch.float64, "vext"), kw.ctypes.data,
+                                    int(nocc), _dev(psi, torch.complex128, "psi"), int(nbnd),
+                                    ctypes.byref(o), eig.ctypes.data, _dev(rho, torch.float64, "rho"),
+                                    _dev(vh, torch.float64, "vh"), ctypes.byref(st), _stream(stream))
+    if status not in (QM_OK, QM_E_NOT_CONVERGED):
+        _check(status, plan.handle)
+    return eig, st.as_dict(), status
+
+
+def qm_expm_taylor(plan, k, psi_in, psi_out, nbnd, dt, order, stream=None):
+    """psi_out <- sum_{r<=order} (-i dt)^r / r! H^r psi_in (complex128 device tensors)."""
+    import torch
+    n = plan.band_block_numel(nbnd, k)
+    if n is not None and (psi_in.numel() != n or psi_out.numel() != n):
+        raise ValueError(f"psi_in/psi_out must hold {n} elements for nbnd={nbnd}, k={k}")
+    _check(_load().qm_expm_taylor(plan.handle, int(k), _dev(psi_in, torch.complex128, "psi_in"),
+                                  _dev(psi_out, torch.complex128, "psi_out"), int(nbnd), float(dt),
+                                  int(order), _stream(stream)), plan.handle)
+
+
+def qm_td_etrs(plan, vext, kweights, occ, psi, nbnd, dt, order, nsteps, stream=None):
+    """nsteps ETRS steps of the Hartree-only model, psi advanced in place."""
+    import torch
+    kw = np.ascontiguousarray(kweights, np.float64).reshape(-1)
+    f = np.ascontiguousarray(occ, np.float64).reshape(-1)
+    if kw.size != plan.nk or f.size != plan.nk * nbnd:
+        raise ValueError("kweights must hold nk values and occ nk * nbnd")
+    if psi.numel() != plan.band_block_numel(nbnd, -1) or vext.numel() != int(np.prod(plan.grid)):
+        raise ValueError("psi or vext has the wrong size")
+    _check(_load().qm_td_etrs(plan.handle, _dev(vext, torch.float64, "vext"), kw.ctypes.data, f.ctypes.data,
+                              _dev(psi, torch.complex128, "psi"), int(nbnd), float(dt), int(order),
+                              int(nsteps), _stream(stream)), plan.handle)
+
+
+def qm_mtxel(plan, kq, psi_kq, nb1, k, psi_k, nb2, miller_g, mtx, stream=None):
+    """mtx [nb1, nb2, ng] <- <n k+q| e^{i(q+G).r} |n' k> for the G of miller_g [ng, 3]."""
+    import torch
+    mg = np.ascontiguousarray(miller_g, np.int32).reshape(-1, 3)
+    if psi_kq.numel() != nb1 * int(plan.npw[kq]) or psi_k.numel() != nb2 * int(plan.npw[k]):
+        raise ValueError("psi_kq / psi_k sizes do not match nb1, nb2 and the spheres")
+    if mtx.numel() != nb1 * nb2 * mg.shape[0]:
+        raise ValueError("mtx must hold nb1 * nb2 * ng values")
+    _check(_load().qm_mtxel(plan.handle, int(kq), _dev(psi_kq, torch.complex128, "psi_kq"), int(nb1), int(k),
+                            _dev(psi_k, torch.complex128, "psi_k"), int(nb2), mg.ctypes.data, int(mg.shape[0]),
+                            _dev(mtx, torch.complex128, "mtx"), _stream(stream)), plan.handle)

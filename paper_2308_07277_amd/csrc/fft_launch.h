@@ -7,15 +7,18 @@ namespace qm {
 constexpr int kZTile = 32;  // sticks per z-kernel tile (the plan's tile tables use it)
 
 
+// Kernel arguments of the local-part kernels for the slices sl; nblk_z / npair receive the
+// z-kernel block count and the number of (k, band) pairs.
 template <typename R>
-void launch_local_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
-                    hipStream_t s, StageEvents* ev, const HpsiWork* wk) {
+LocalArgs make_local_args(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi,
+                          void* hpsi, const HpsiWork* wk, int64_t& nblk_z, int64_t& npair) {
   LocalArgs a{};
   QM_REQUIRE(!sl.empty() && sl.size() <= size_t(kMaxSlices), QM_E_STATE, "bad slice count");
   a.kinfo = p->g.kinfo;
   a.nsl = int32_t(sl.size());
   a.N3 = p->N3;
-  int64_t nblk_z = 0, npair = 0;
+  nblk_z = 0;
+  npair = 0;
   for (size_t i = 0; i < sl.size(); ++i) {
     a.sl[i] = sl[i];
     a.blk_z[i] = int32_t(nblk_z);
@@ -40,9 +43,33 @@ void launch_local_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* 
   a.tw_x = p->tw_x;
   a.ts = kZTile;
   a.nax_stride = p->nax_max | 1;
+  QM_REQUIRE(nblk_z < (int64_t(1) << 31), QM_E_SHAPE, "launch too large");
+  return a;
+}
+
+// scatter + inverse z transform of every slice into the stick buffer
+template <typename R>
+void launch_zinv_t(const LocalArgs& a, int64_t nblk_z, int N3, hipStream_t s) {
+#define QM_ZINV_ONLY(n)                                                                     \
+  case n:                                                                                   \
+    hipLaunchKernelGGL((k_zinv<R, n, kZTile>), dim3(unsigned(nblk_z)),                      \
+                       dim3(kZTile * Split<n>::R2), 0, s, a);                               \
+    break;
+  switch (N3) {
+    QM_FOR_EACH_FFT_LEN(QM_ZINV_ONLY)
+    default: throw Error(QM_E_SHAPE, "unsupported N3");
+  }
+#undef QM_ZINV_ONLY
+  QM_HIP(hipGetLastError());
+}
+
+template <typename R>
+void launch_local_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
+                    hipStream_t s, StageEvents* ev, const HpsiWork* wk) {
+  int64_t nblk_z = 0, npair = 0;
+  LocalArgs a = make_local_args<R>(p, sl, psi, hpsi, wk, nblk_z, npair);
   const int64_t nblk_xy = npair * p->N3;
-  QM_REQUIRE(nblk_z < (int64_t(1) << 31) && nblk_xy < (int64_t(1) << 31), QM_E_SHAPE,
-             "launch too large");
+  QM_REQUIRE(nblk_xy < (int64_t(1) << 31), QM_E_SHAPE, "launch too large");
   const int NX = p->N1;
   const int r2x = fft_split_r2(NX);
   const size_t smem_xy = sizeof(cplx<R>) * (size_t(NX) * a.nax_stride + size_t(NX + 1) * (256 / r2x) + NX) +

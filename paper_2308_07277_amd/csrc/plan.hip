@@ -35,11 +35,13 @@ static T* upload(const std::vector<T>& v, hipStream_t s) {
 static void plan_free(qm_hpsi_plan* p) {
   if (!p) return;
   davidson_free(p);
+  density_free(p);
+  td_free(p);
   for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
   p->graphs.clear();
   if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
   void* ptrs[] = {p->g.kinfo, p->g.ent_g, p->g.ent_sz, p->g.tile_ptr, p->g.stick_pos,
-                  p->g.col_of_i1, p->g.kin, p->vplan64, p->vplan32, p->beta64, p->beta_lp,
+                  p->g.col_of_i1, p->g.flat, p->g.kin, p->vplan64, p->vplan32, p->beta64, p->beta_lp,
                   p->dmat, p->drange, p->tw_z, p->tw_x, p->sbuf, p->proj_part, p->proj_q};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -87,7 +89,7 @@ static void build_plan(qm_hpsi_plan* p, const double cell[9], const int32_t grid
   std::memcpy(p->recip, b, sizeof(b));
 
   const int N1 = p->N1, N2 = p->N2, N3 = p->N3;
-  std::vector<int32_t> ent_g, ent_sz, tile_ptr, stick_pos, col_of_i1(size_t(p->nk) * N1, -1);
+  std::vector<int32_t> ent_g, ent_sz, tile_ptr, stick_pos, col_of_i1(size_t(p->nk) * N1, -1), flat;
   std::vector<double> kin;
   p->kinfo.resize(p->nk);
   int64_t g_off = 0, stick_off = 0, tile_off = 0;
@@ -107,6 +109,7 @@ static void build_plan(qm_hpsi_plan* p, const double cell[9], const int32_t grid
         ii[3 * g + d] = ((v % Ns[d]) + Ns[d]) % Ns[d];
       }
       keys[g] = (int64_t(ii[3 * g]) * N2 + ii[3 * g + 1]) * N3 + ii[3 * g + 2];
+      flat.push_back(int32_t(keys[g]));
     }
     {
       std::vector<int64_t> sk(keys);
@@ -197,6 +200,7 @@ static void build_plan(qm_hpsi_plan* p, const double cell[9], const int32_t grid
   p->g.tile_ptr = upload(tile_ptr, s);
   p->g.stick_pos = upload(stick_pos, s);
   p->g.col_of_i1 = upload(col_of_i1, s);
+  p->g.flat = upload(flat, s);
   p->g.kin = upload(kin, s);
   // twiddles exp(+2 pi i m / N), exact octant reduction
   auto roots = [](int n) {

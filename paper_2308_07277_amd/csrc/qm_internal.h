@@ -62,10 +62,12 @@ struct GTables {
   int32_t* tile_ptr = nullptr;   // [sum (ntile+1)] entry offset (within k) of each tile
   int32_t* stick_pos = nullptr;  // [sum nstick] i2 | (ia << 16)
   int32_t* col_of_i1 = nullptr;  // [nk][N1] active-column index of i1, or -1
+  int32_t* flat = nullptr;       // [sum npw] C-order grid index of each G, caller order
   double* kin = nullptr;         // [sum npw] 1/2|k+G|^2 in caller order
 };
 
 struct DavState;  // Davidson workspace (davidson.hip)
+struct TdWork;    // real-time propagation workspace (tddft.hip)
 
 // One k-point's band block in a batched H application: nb rows of npw_k
 // coefficients starting at element offsets psi_off / hpsi_off of the call's
@@ -143,6 +145,14 @@ struct qm_hpsi_plan {
   // CholQR Cholesky + inverse: 1 one workgroup per k-point, 2 blocked on many workgroups,
   // 0 blocked up to 576 bands (environment QM_CHOL_MODE).
   int32_t chol_forced = 0;
+  // density / Hartree workspace (density.hip), allocated on first use
+  double* rho_part = nullptr;     // per band-group partial densities [G][slot][i2][i1]
+  int64_t rho_part_bytes = 0;
+  double* dens_wf = nullptr;      // per (k, band) pair weight w_k f_kn / Omega
+  int64_t dens_wf_n = 0;
+  void* grid_c = nullptr;         // complex float64 grid [N1][N2][N3] of the Poisson solve
+  double* grid_sum = nullptr;     // [2] reduction results
+  qm::TdWork* td = nullptr;       // propagation work buffers (tddft.hip), allocated on first use
 };
 
 namespace qm {
@@ -163,6 +173,8 @@ void launch_hpsi_local(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const voi
                        hipStream_t s, bool fp32, StageEvents* ev = nullptr,
                        const HpsiWork* wk = nullptr);
 void launch_vplan(qm_hpsi_plan* p, const double* vloc_r, hipStream_t s);
+// scatter + float64 inverse z transform of the slices into the plan's stick buffer
+void launch_zinv_f64(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, hipStream_t s);
 // Split-K scratch of the projector GEMM.  Calls that may run at the same time on different
 // streams (Davidson lanes, which own disjoint k-points) each pass their own.
 struct ProjScratch {
@@ -212,4 +224,11 @@ void convert_beta_lp(const void* beta64, void* out, int64_t n, int kind, hipStre
 
 void plan_upload_davidson(qm_hpsi_plan* p);
 void davidson_free(qm_hpsi_plan* p);
+void density_free(qm_hpsi_plan* p);
+void td_free(qm_hpsi_plan* p);
+// unnormalised 3-D transform (sign +1: sum e^{+iG.r}; -1: e^{-iG.r}) of nbatch complex
+// float64 grids [N1][N2][N3], consecutive in memory, in place
+void fft3_batched(qm_hpsi_plan* p, double2* c, int64_t nbatch, int sign, hipStream_t s);
+// y = x + z over the plan's grid (float64), on stream s
+void grid_add(qm_hpsi_plan* p, const double* x, const double* z, double* y, hipStream_t s);
 }  // namespace qm

@@ -55,7 +55,8 @@ def test_struct_sizes_match_header(tmp_path):
     the header's structures (a small C program built with gcc prints them)."""
     import ctypes
     import subprocess
-    structs = {"qm_dav_opts": qm.qm_dav_opts, "qm_dav_stats": qm.qm_dav_stats, "qm_kset": qm.qm_kset}
+    structs = {"qm_dav_opts": qm.qm_dav_opts, "qm_dav_stats": qm.qm_dav_stats, "qm_kset": qm.qm_kset,
+               "qm_scf_opts": qm.qm_scf_opts, "qm_scf_stats": qm.qm_scf_stats}
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "qm_hpsi.h"', "int main(void) {"]
     for name, cls in structs.items():
         lines.append(f'  printf("{name} %zu\\n", sizeof({name}));')
