@@ -247,22 +247,32 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
   for (int u = 0; u < kUnroll; ++u) L[(ps0[u] & 0xffff) * ns + (ps0[u] >> 16)] = cplx<R>{re0[u], im0[u]};
   sticks_to_lds<R, 256>(plane, spos, ki.nstick, L, ns, tid + kUnroll * 256);
   __syncthreads();
+  // y-pass items w = ia + nax j: thread tid starts at (tid % nax, tid / nax) and steps by
+  // 256 = dj nax + dia, so each pass walks its items without a division per item
+  const int ia0 = tid % nax, j0 = tid / nax, dj = 256 / nax, dia = 256 - dj * nax;
   // ---- inverse y on active columns: pass 1 (R2-point, stride R1)
-  for (int w = tid; w < nax * R1; w += 256) {
-    const int ia = w % nax, n1 = w / nax;
+  for (int w = tid, ia = ia0, n1 = j0; w < nax * R1; w += 256, ia += dia, n1 += dj) {
+    if (ia >= nax) {
+      ia -= nax;
+      ++n1;
+    }
     cplx<R> x[R2];
 #pragma unroll
     for (int n2 = 0; n2 < R2; ++n2) x[n2] = L[(n1 + R1 * n2) * ns + ia];
     Dft<R2, +1, R>::run(x);
+    // twiddle exponents n1 k2 <= (R1 - 1)(R2 - 1) < NX: no reduction modulo NX needed
 #pragma unroll
-    for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tw[(n1 * k2) % NX]);
+    for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tw[n1 * k2]);
 #pragma unroll
     for (int k2 = 0; k2 < R2; ++k2) L[(n1 + R1 * k2) * ns + ia] = x[k2];
   }
   __syncthreads();
   // pass 2 (R1-point on contiguous runs); output X[k2 + R2 k1] at position k1 + R1 k2
-  for (int w = tid; w < nax * R2; w += 256) {
-    const int ia = w % nax, k2 = w / nax;
+  for (int w = tid, ia = ia0, k2 = j0; w < nax * R2; w += 256, ia += dia, k2 += dj) {
+    if (ia >= nax) {
+      ia -= nax;
+      ++k2;
+    }
     cplx<R> y[R1];
 #pragma unroll
     for (int n1 = 0; n1 < R1; ++n1) y[n1] = L[(n1 + R1 * k2) * ns + ia];
@@ -281,6 +291,18 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
     const int wave = tid >> 6, lane = tid & 63;
     const int q = lane % R2, rs = lane / R2;
     cplx<R>* Xr = X + (wave * RW + (rs < RW ? rs : 0)) * NXP;
+    // per-lane constants of every row: the active-column slots of the row samples
+    // i1 = q + R1 j (read by the inverse pass, written by the forward one) and the twiddles
+    // w^{q j}, used for j < R2 by lanes q < R1 (inverse pass 1) and for j < R1 by lanes
+    // q < R2 (forward pass): those exponents stay below NX, so no reduction modulo NX is
+    // needed; the other (unused) combinations are clamped into the table
+    int cq[R2];
+    cplx<R> tq[R2];
+#pragma unroll
+    for (int j = 0; j < R2; ++j) {
+      cq[j] = col[min(q, R1 - 1) + R1 * j];
+      tq[j] = tw[min(q * j, NX - 1)];
+    }
     for (int r0 = wave * RW; r0 < NX; r0 += 4 * RW) {
       const int i2 = r0 + rs;
       const bool act = rs < RW && i2 < NX;
@@ -293,16 +315,14 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
 #pragma unroll
         for (int k1 = 0; k1 < R1; ++k1) vr[k1] = Vrow[q + R2 * k1];
       }
+      const cplx<R>* Lrow = L + lrow * ns;
       if (act && q < R1) {
         cplx<R> x[R2];
 #pragma unroll
-        for (int n2 = 0; n2 < R2; ++n2) {
-          const int c = col[q + R1 * n2];
-          x[n2] = c >= 0 ? L[lrow * ns + c] : cplx<R>{R(0), R(0)};
-        }
+        for (int n2 = 0; n2 < R2; ++n2) x[n2] = cq[n2] >= 0 ? Lrow[cq[n2]] : cplx<R>{R(0), R(0)};
         Dft<R2, +1, R>::run(x);
 #pragma unroll
-        for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tw[(q * k2) % NX]);
+        for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tq[k2]);
 #pragma unroll
         for (int k2 = 0; k2 < R2; ++k2) Xr[q + R1 * k2] = x[k2];
       }
@@ -316,10 +336,7 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
         for (int k1 = 0; k1 < R1; ++k1) y[k1] = cscale(y[k1], vr[k1]);
         Dft<R1, -1, R>::run(y);  // forward, factorisation (R2, R1): first pass over n2' = k1
 #pragma unroll
-        for (int k2 = 1; k2 < R1; ++k2) {
-          const cplx<R> w = tw[(q * k2) % NX];
-          y[k2] = cmul(y[k2], cplx<R>{w.re, -w.im});
-        }
+        for (int k2 = 1; k2 < R1; ++k2) y[k2] = cmul(y[k2], cplx<R>{tq[k2].re, -tq[k2].im});
       }
       wave_lds_sync();
       if (act) {
@@ -332,34 +349,39 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
 #pragma unroll
         for (int n1 = 0; n1 < R2; ++n1) z[n1] = Xr[n1 + R2 * q];
         Dft<R2, -1, R>::run(z);  // natural output at i1 = q + R1 k1
+        cplx<R>* Lw = L + lrow * ns;
 #pragma unroll
-        for (int k1 = 0; k1 < R2; ++k1) {
-          const int c = col[q + R1 * k1];
-          if (c >= 0) L[lrow * ns + c] = z[k1];
-        }
+        for (int k1 = 0; k1 < R2; ++k1)
+          if (cq[k1] >= 0) Lw[cq[k1]] = z[k1];
       }
       wave_lds_sync();
     }
   }
   __syncthreads();
   // ---- forward y on active columns, input in the transposed order left above
-  for (int w = tid; w < nax * R2; w += 256) {
-    const int ia = w % nax, n1 = w / nax;  // n1 in [0, R2)
+  for (int w = tid, ia = ia0, n1 = j0; w < nax * R2; w += 256, ia += dia, n1 += dj) {  // n1 < R2
+    if (ia >= nax) {
+      ia -= nax;
+      ++n1;
+    }
     cplx<R> x[R1];
 #pragma unroll
     for (int n2 = 0; n2 < R1; ++n2) x[n2] = L[(n2 + R1 * n1) * ns + ia];
     Dft<R1, -1, R>::run(x);
 #pragma unroll
-    for (int k2 = 1; k2 < R1; ++k2) {
-      const cplx<R> t = tw[(n1 * k2) % NX];
+    for (int k2 = 1; k2 < R1; ++k2) {   // n1 k2 <= (R2 - 1)(R1 - 1) < NX
+      const cplx<R> t = tw[n1 * k2];
       x[k2] = cmul(x[k2], cplx<R>{t.re, -t.im});
     }
 #pragma unroll
     for (int k2 = 0; k2 < R1; ++k2) L[(k2 + R1 * n1) * ns + ia] = x[k2];
   }
   __syncthreads();
-  for (int w = tid; w < nax * R1; w += 256) {
-    const int ia = w % nax, k2 = w / nax;  // k2 in [0, R1)
+  for (int w = tid, ia = ia0, k2 = j0; w < nax * R1; w += 256, ia += dia, k2 += dj) {  // k2 < R1
+    if (ia >= nax) {
+      ia -= nax;
+      ++k2;
+    }
     cplx<R> z[R2];
 #pragma unroll
     for (int n1 = 0; n1 < R2; ++n1) z[n1] = L[(k2 + R1 * n1) * ns + ia];
