@@ -150,9 +150,10 @@ typedef struct {
  *  out      receives the plan.
  * The plan copies V, beta and D (in its working precisions) and owns its
  * workspace, so inputs may be freed after the call returns.  Environment:
- * QM_XY_MODE=1 forces the two-pass xy-plane kernel, QM_XY_MODE=2 the lane-group kernel
- * (grids of 20, 40 and 72 points along x; same transform, for comparisons); otherwise
- * qm_hpsi_plan_autotune picks one per precision.  For the Davidson calls on the plan
+ * QM_XY_MODE=1 forces the two-pass xy-plane kernel with a row scratch, QM_XY_MODE=2 the
+ * lane-group kernel (grids of 20, 40 and 72 points along x), QM_XY_MODE=3 the two-pass kernel
+ * with the x-row exchanges in the plane rows' own LDS slots (same transform, for
+ * comparisons); otherwise qm_hpsi_plan_autotune picks one per precision.  For the Davidson calls on the plan
  * (same results up to the order of float64 additions, for comparisons):
  * QM_TRIDIAG_MODE=1 reduces the projected matrix in one workgroup per k-point, =2 with one
  * launch per Householder step on many workgroups (default: from a basis of 192 columns);

@@ -1,4 +1,5 @@
 // Plan-side helpers of the local part: supported lengths, V(r) re-layout.
+#include <algorithm>
 #include "cplx.h"
 #include "qm_internal.h"
 
@@ -38,6 +39,24 @@ int fft_split_r2(int n) {
   }
 }
 
+int xy_row_stride(int n, int nax_max, bool own) {
+  const int r2 = fft_split_r2(n), r1 = r2 ? n / r2 : 0;
+  // one slot past the active columns reads as zero; odd, so that rows at this stride fall on
+  // different LDS banks; with the exchanges in the rows' own slots each round of the x-row
+  // transform pair holds half of the row's values
+  int ns = nax_max + 1;
+  if (own) ns = std::max({ns, (r1 + 1) / 2 * (r2 | 1), r1 * ((r2 + 1) / 2 | 1)});
+  return ns | 1;
+}
+
+size_t xy_lds_bytes(int n, int ns, size_t real_bytes, bool own) {
+  const int r2 = fft_split_r2(n);
+  size_t cplx_elems = size_t(n) * ns + n;            // plane + twiddles
+  if (!own) cplx_elems += size_t(4 * (64 / r2)) * (n + 1);   // row scratch
+  if (own && real_bytes == 8) cplx_elems += size_t(r2) * r2;  // [j][q] twiddle table
+  return 2 * real_bytes * cplx_elems + sizeof(int) * n;
+}
+
 void launch_hpsi_local(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
                        hipStream_t s, bool fp32, StageEvents* ev, const HpsiWork* wk) {
   if (fp32)
@@ -50,12 +69,21 @@ int xy_group_lanes(int nx) { return nx == 20 || nx == 40 ? 2 : (nx == 72 ? 8 : 0
 
 int xy_pick(const qm_hpsi_plan* p, int rt) {
   const bool group_ok = xy_group_lanes(p->N1) > 0;
-  if (p->xy_forced == 1) return 1;
-  if (p->xy_forced == 2) return group_ok ? 2 : 1;
-  if (p->xy_variant[rt] == 2 && group_ok) return 2;
-  if (p->xy_variant[rt] == 1) return 1;
-  // built-in choice, as measured on the workloads: lane pairs for float64 20 and 40
-  return rt == 0 && (p->N1 == 20 || p->N1 == 40) ? 2 : 1;
+  const int forced = p->xy_forced, v = p->xy_variant[rt];
+  if (forced == 1 || forced == 3) return forced;
+  if (forced == 2) return group_ok ? 2 : 1;
+  if (v == 2 && group_ok) return 2;
+  if (v == 1 || v == 3) return v;
+  // built-in choice, as measured on the workloads: lane pairs for float64 20 and 40; for other
+  // float64 grids the own-slot exchanges where they fit more workgroups on a CU
+  if (rt == 0 && (p->N1 == 20 || p->N1 == 40)) return 2;
+  if (rt == 0) {
+    const size_t lds = 160 * 1024;
+    const size_t b1 = xy_lds_bytes(p->N1, xy_row_stride(p->N1, p->nax_max, false), 8, false);
+    const size_t b3 = xy_lds_bytes(p->N1, xy_row_stride(p->N1, p->nax_max, true), 8, true);
+    if (b3 <= lds && (b1 > lds || lds / b3 > lds / b1)) return 3;
+  }
+  return 1;
 }
 
 std::vector<KSlice> contiguous_slices(const qm_hpsi_plan* p, int k0, int k1, int nbnd) {

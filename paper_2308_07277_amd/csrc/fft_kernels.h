@@ -47,7 +47,8 @@ struct LocalArgs {
   const double2* tw_z;      // exp(+2 pi i m / N3), m < N3
   const double2* tw_x;      // exp(+2 pi i m / N1)
   int32_t ts;               // sticks per tile
-  int32_t nax_stride;       // row stride of the xy-plane buffer (elements)
+  int32_t nax_stride;       // row stride of the lane-group xy-plane buffer (elements)
+  int32_t xy_stride;        // row stride of the two-pass xy-plane buffer (elements)
   int32_t sbuf_per_k;       // 1: k's stick block at sbuf + kinfo[k].sbuf_off; 0: at sbuf (one slice)
 };
 
@@ -194,16 +195,28 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename R, int NX>
-__global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
+// Waves per SIMD the two-pass xy kernel is compiled for.  Without the row scratch a float64
+// plane of up to 80 points takes at most 53 KB of LDS, so three workgroups fit on a CU if the
+// registers allow it.
+template <typename R, int NX, bool OWN>
+constexpr int xy_min_waves() { return OWN && sizeof(R) == 8 && NX <= 80 ? 3 : 1; }
+
+// OWN = false: the x-row exchanges go through a row scratch of NX + 1 slots per row in flight
+// (4 R_W rows).  OWN = true: they go through the rows' own ns slots in two rounds each, which
+// leaves the plane as the only large LDS buffer (more workgroups per CU, more LDS operations);
+// float64 then reads its x-row twiddles from a [j][q] table instead of holding them in VGPRs.
+template <typename R, int NX, bool OWN>
+__global__ void __launch_bounds__(256, (xy_min_waves<R, NX, OWN>())) k_xy(LocalArgs a) {
   constexpr int R1 = Split<NX>::R1, R2 = Split<NX>::R2;
-  constexpr int RG = 256 / R2;  // rows per x-pass group
+  constexpr int RW = 64 / R2, NXP = NX + 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int ns = a.nax_stride;
+  const int ns = a.xy_stride;
+  constexpr bool kTwReg = !OWN || sizeof(R) == 4;
   cplx<R>* L = reinterpret_cast<cplx<R>*>(smem_raw);  // [NX positions][ns]
-  cplx<R>* X = L + NX * ns;                              // [RG rows][NX + 1]
-  cplx<R>* tw = X + (NX + 1) * RG;                       // [NX]
-  int* col = reinterpret_cast<int*>(tw + NX);            // [NX]
+  cplx<R>* X = L + NX * ns;                              // [4 R_W rows][NX + 1] (OWN = false)
+  cplx<R>* tw = X + (OWN ? 0 : 4 * RW * NXP);            // [NX]
+  cplx<R>* twr = tw + NX;                                // [R2 j][R2 q] = w^{q j} (!kTwReg)
+  int* col = reinterpret_cast<int*>(twr + (kTwReg ? 0 : R2 * R2));  // [NX]
   const int tid = threadIdx.x;
   const int N3 = a.N3;
   // (k, band) pair and z-slot; each XCD keeps a fixed eighth of the slots when N3 % 8 == 0
@@ -240,6 +253,13 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
     double2 w = a.tw_x[i];
     tw[i] = {R(w.x), R(w.y)};
     col[i] = a.col_of_i1[int64_t(k) * NX + i];
+  }
+  if (!kTwReg) {
+    for (int i = tid; i < R2 * R2; i += 256) {
+      const int j = i / R2, qq = i - j * R2;
+      const double2 w = a.tw_x[min(qq * j, NX - 1)];
+      twr[i] = {R(w.x), R(w.y)};
+    }
   }
   for (int i = tid; i < NX * ns; i += 256) L[i] = {R(0), R(0)};
   __syncthreads();
@@ -282,59 +302,175 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
   }
   __syncthreads();
   // ---- x rows: inverse x, * V / N_r, forward x; active columns only written back.
-  // Each wave owns whole rows (R2 lanes per row, 64 / R2 rows at a time) and its own row
-  // scratch, so the exchanges between the two passes of a row need only wave-level ordering.
-  // Lanes run over the intra-row index q (consecutive LDS columns, consecutive V entries).
   const R* V = reinterpret_cast<const R*>(a.vplan) + int64_t(p) * NX * NX;  // [i2][i1]
-  constexpr int NXP = NX + 1, RW = 64 / R2;
+  if constexpr (OWN) {
+  // Each wave owns R_W = 64 / R2 consecutive rows of L at a time (R2 lanes per row, lanes over
+  // the intra-row index q).  The two exchanges between the passes of a row's transform pair go
+  // through the row's own ns slots, in two rounds each (ns holds half of the R1 R2 values), so
+  // the plane is the only large LDS buffer and only wave-level ordering is required.
+  // L row lr holds plane row i2 = R2 (lr % R1) + lr / R1 (the y-pass order).
+  // inverse exchange: values of n1 < HA in the first round, value (n1, k2) at slot
+  // (n1 - round start) PA + k2; forward exchange: values of n < HB in the first round, value
+  // (n, k2) at slot k2 QB + (n - round start).  PA and QB are odd, so the lanes of a row that
+  // write (inverse) or read (forward) one value each fall on different LDS banks.
+  constexpr int HA = (R1 + 1) / 2, PA = R2 | 1;
+  constexpr int HB = (R2 + 1) / 2, QB = HB | 1;
   {
     const int wave = tid >> 6, lane = tid & 63;
     const int q = lane % R2, rs = lane / R2;
+    // per-lane constants of every row: the slots of the row samples i1 = q + R1 j (read by
+    // the inverse pass, written by the forward one; inactive columns read the row's last
+    // slot, which no y pass writes, so it holds zero until the row's exchanges start) and the
+    // twiddles w^{q j}, used for j < R2 by lanes q < R1 (inverse pass 1) and for j < R1 by
+    // lanes q < R2 (forward pass): those exponents stay below NX, so no reduction modulo NX
+    // is needed; the other (unused) combinations are clamped into the table
+    // (float64 reads the twiddles from the [j][q] LDS table at each use instead, consecutive
+    // lanes at consecutive entries: held in registers they would cost 4 R2 VGPRs and a wave
+    // slot per SIMD)
+    int cr[R2];  // active columns are below nax < ns - 1, so cr[j] != ns - 1 marks them
+    cplx<R> tq[kTwReg ? R2 : 1];
+#pragma unroll
+    for (int j = 0; j < R2; ++j) {
+      const int c = col[min(q, R1 - 1) + R1 * j];
+      cr[j] = c >= 0 ? c : ns - 1;
+      if (kTwReg) tq[j] = tw[min(q * j, NX - 1)];
+    }
+    auto twq = [&](int j) { return kTwReg ? tq[kTwReg ? j : 0] : twr[j * R2 + q]; };
+    for (int r0 = wave * RW; r0 < NX; r0 += 4 * RW) {
+      const int lr = r0 + rs;
+      const bool act = rs < RW && lr < NX;
+      const int i2 = act ? R2 * (lr % R1) + lr / R1 : 0;
+      // this row's V(r) values, loaded before the row's LDS exchanges (whose wave-level
+      // fences the loads could not be moved across); idle lanes read row 0
+      R vr[R1];
+      {
+        const R* Vrow = V + i2 * NX;
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) vr[k1] = Vrow[q + R2 * k1];
+      }
+      cplx<R>* Lr = L + (act ? lr : 0) * ns;
+      // inverse pass 1: lanes q < R1 (n1 = q), R2-point DFT over n2 of x[q + R1 n2], twiddle
+      cplx<R> x[R2];
+      if (act && q < R1) {
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) x[n2] = Lr[cr[n2]];
+        Dft<R2, +1, R>::run(x);
+#pragma unroll
+        for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], twq(k2));
+      }
+      wave_lds_sync();
+      // inverse exchange; lane q collects k2 = q
+      cplx<R> y[R1];
+      if (act && q < HA) {
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) Lr[q * PA + k2] = x[k2];
+      }
+      wave_lds_sync();
+      if (act) {
+#pragma unroll
+        for (int n1 = 0; n1 < HA; ++n1) y[n1] = Lr[n1 * PA + q];
+      }
+      wave_lds_sync();
+      if (act && q >= HA && q < R1) {
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) Lr[(q - HA) * PA + k2] = x[k2];
+      }
+      wave_lds_sync();
+      if (act) {
+#pragma unroll
+        for (int n1 = HA; n1 < R1; ++n1) y[n1] = Lr[(n1 - HA) * PA + q];
+        Dft<R1, +1, R>::run(y);  // y[k1] is the row value at i1 = q + R2 k1
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) y[k1] = cscale(y[k1], vr[k1]);
+        Dft<R1, -1, R>::run(y);  // forward, factorisation (R2, R1): first pass over n = k1
+#pragma unroll
+        for (int k2 = 1; k2 < R1; ++k2) {
+          const cplx<R> t = twq(k2);
+          y[k2] = cmul(y[k2], cplx<R>{t.re, -t.im});
+        }
+      }
+      wave_lds_sync();
+      // forward exchange; lane q < R1 collects k2 = q
+      cplx<R> z[R2];
+      if (act && q < HB) {
+#pragma unroll
+        for (int k2 = 0; k2 < R1; ++k2) Lr[k2 * QB + q] = y[k2];
+      }
+      wave_lds_sync();
+      if (act && q < R1) {
+#pragma unroll
+        for (int n = 0; n < HB; ++n) z[n] = Lr[q * QB + n];
+      }
+      wave_lds_sync();
+      if (act && q >= HB) {
+#pragma unroll
+        for (int k2 = 0; k2 < R1; ++k2) Lr[k2 * QB + (q - HB)] = y[k2];
+      }
+      wave_lds_sync();
+      if (act && q < R1) {
+#pragma unroll
+        for (int n = HB; n < R2; ++n) z[n] = Lr[q * QB + (n - HB)];
+        Dft<R2, -1, R>::run(z);  // natural output at i1 = q + R1 k1
+      }
+      wave_lds_sync();
+      if (act && q < R1) {
+#pragma unroll
+        for (int k1 = 0; k1 < R2; ++k1)
+          if (cr[k1] != ns - 1) Lr[cr[k1]] = z[k1];
+      }
+    }
+  }
+  } else {
+  // Each wave owns whole rows (R2 lanes per row, R_W rows at a time) and its own row scratch,
+  // so the exchanges between the two passes of a row need only wave-level ordering.  Lanes run
+  // over the intra-row index q (consecutive LDS columns, consecutive V entries).  In the
+  // inverse exchange lane q < R1 writes its R2 values at slots q R2 + k2 and lane q reads
+  // slots n1 R2 + q; in the forward one lane q writes slots q + R2 k2 and lane q < R1 reads
+  // slots n + R2 q: odd strides between lanes, so a row's lanes fall on different LDS banks.
+    const int wave = tid >> 6, lane = tid & 63;
+    const int q = lane % R2, rs = lane / R2;
     cplx<R>* Xr = X + (wave * RW + (rs < RW ? rs : 0)) * NXP;
-    // per-lane constants of every row: the active-column slots of the row samples
-    // i1 = q + R1 j (read by the inverse pass, written by the forward one) and the twiddles
-    // w^{q j}, used for j < R2 by lanes q < R1 (inverse pass 1) and for j < R1 by lanes
-    // q < R2 (forward pass): those exponents stay below NX, so no reduction modulo NX is
-    // needed; the other (unused) combinations are clamped into the table
-    int cq[R2];
+    // per-lane constants of every row: the slots of the row samples i1 = q + R1 j (read by
+    // the inverse pass, written by the forward one; inactive columns read the row's last slot,
+    // which no pass writes) and the twiddles w^{q j} (exponents below NX, as above)
+    int cr[R2];
     cplx<R> tq[R2];
 #pragma unroll
     for (int j = 0; j < R2; ++j) {
-      cq[j] = col[min(q, R1 - 1) + R1 * j];
+      const int c = col[min(q, R1 - 1) + R1 * j];
+      cr[j] = c >= 0 ? c : ns - 1;
       tq[j] = tw[min(q * j, NX - 1)];
     }
     for (int r0 = wave * RW; r0 < NX; r0 += 4 * RW) {
       const int i2 = r0 + rs;
       const bool act = rs < RW && i2 < NX;
       const int lrow = act ? (i2 / R2) + R1 * (i2 % R2) : 0;
-      // this row's V(r) values, loaded before the row's LDS exchanges (whose wave-level
-      // fences the loads could not be moved across); idle lanes read row 0
       R vr[R1];
       {
         const R* Vrow = V + (act ? i2 : 0) * NX;
 #pragma unroll
         for (int k1 = 0; k1 < R1; ++k1) vr[k1] = Vrow[q + R2 * k1];
       }
-      const cplx<R>* Lrow = L + lrow * ns;
+      cplx<R>* Lrow = L + lrow * ns;
       if (act && q < R1) {
         cplx<R> x[R2];
 #pragma unroll
-        for (int n2 = 0; n2 < R2; ++n2) x[n2] = cq[n2] >= 0 ? Lrow[cq[n2]] : cplx<R>{R(0), R(0)};
+        for (int n2 = 0; n2 < R2; ++n2) x[n2] = Lrow[cr[n2]];
         Dft<R2, +1, R>::run(x);
 #pragma unroll
         for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tq[k2]);
 #pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) Xr[q + R1 * k2] = x[k2];
+        for (int k2 = 0; k2 < R2; ++k2) Xr[q * R2 + k2] = x[k2];
       }
       wave_lds_sync();
       cplx<R> y[R1];
       if (act) {
 #pragma unroll
-        for (int n1 = 0; n1 < R1; ++n1) y[n1] = Xr[n1 + R1 * q];
+        for (int n1 = 0; n1 < R1; ++n1) y[n1] = Xr[n1 * R2 + q];
         Dft<R1, +1, R>::run(y);  // y[k1] is the row value at i1 = q + R2 k1
 #pragma unroll
         for (int k1 = 0; k1 < R1; ++k1) y[k1] = cscale(y[k1], vr[k1]);
-        Dft<R1, -1, R>::run(y);  // forward, factorisation (R2, R1): first pass over n2' = k1
+        Dft<R1, -1, R>::run(y);  // forward, factorisation (R2, R1): first pass over n = k1
 #pragma unroll
         for (int k2 = 1; k2 < R1; ++k2) y[k2] = cmul(y[k2], cplx<R>{tq[k2].re, -tq[k2].im});
       }
@@ -347,12 +483,11 @@ __global__ void __launch_bounds__(256) k_xy(LocalArgs a) {
       if (act && q < R1) {
         cplx<R> z[R2];
 #pragma unroll
-        for (int n1 = 0; n1 < R2; ++n1) z[n1] = Xr[n1 + R2 * q];
+        for (int n = 0; n < R2; ++n) z[n] = Xr[n + R2 * q];
         Dft<R2, -1, R>::run(z);  // natural output at i1 = q + R1 k1
-        cplx<R>* Lw = L + lrow * ns;
 #pragma unroll
         for (int k1 = 0; k1 < R2; ++k1)
-          if (cq[k1] >= 0) Lw[cq[k1]] = z[k1];
+          if (cr[k1] != ns - 1) Lrow[cr[k1]] = z[k1];
       }
       wave_lds_sync();
     }

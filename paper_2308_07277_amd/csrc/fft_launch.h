@@ -43,6 +43,7 @@ LocalArgs make_local_args(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const 
   a.tw_x = p->tw_x;
   a.ts = kZTile;
   a.nax_stride = p->nax_max | 1;
+  a.xy_stride = xy_row_stride(p->N1, p->nax_max, false);
   QM_REQUIRE(nblk_z < (int64_t(1) << 31), QM_E_SHAPE, "launch too large");
   return a;
 }
@@ -71,9 +72,10 @@ void launch_local_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* 
   const int64_t nblk_xy = npair * p->N3;
   QM_REQUIRE(nblk_xy < (int64_t(1) << 31), QM_E_SHAPE, "launch too large");
   const int NX = p->N1;
-  const int r2x = fft_split_r2(NX);
-  const size_t smem_xy = sizeof(cplx<R>) * (size_t(NX) * a.nax_stride + size_t(NX + 1) * (256 / r2x) + NX) +
-                         sizeof(int) * NX;
+  const int xy_mode = xy_pick(p, sizeof(R) == 8 ? 0 : 1);
+  const bool own = xy_mode == 3;
+  if (own) a.xy_stride = xy_row_stride(NX, p->nax_max, true);
+  const size_t smem_xy = xy_lds_bytes(NX, a.xy_stride, sizeof(R), own);
   QM_REQUIRE(smem_xy <= 160 * 1024, QM_E_SHAPE, "xy-plane does not fit in LDS for this grid/precision");
 #define QM_ZINV(n)                                                                          \
   case n:                                                                                   \
@@ -87,12 +89,17 @@ void launch_local_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* 
     break;
 #define QM_XY(n)                                                                            \
   case n: {                                                                                 \
-    static bool attr_set = false;                                                           \
-    if (!attr_set) {                                                                        \
-      QM_HIP(allow_full_lds(reinterpret_cast<const void*>(&k_xy<R, n>)));                  \
-      attr_set = true;                                                                      \
+    static bool attr_set[2] = {false, false};                                               \
+    const void* fn = own ? reinterpret_cast<const void*>(&k_xy<R, n, true>)                 \
+                         : reinterpret_cast<const void*>(&k_xy<R, n, false>);               \
+    if (!attr_set[own]) {                                                                   \
+      QM_HIP(allow_full_lds(fn));                                                           \
+      attr_set[own] = true;                                                                 \
     }                                                                                       \
-    hipLaunchKernelGGL((k_xy<R, n>), dim3(unsigned(nblk_xy)), dim3(256), smem_xy, s, a);    \
+    if (own)                                                                                \
+      hipLaunchKernelGGL((k_xy<R, n, true>), dim3(unsigned(nblk_xy)), dim3(256), smem_xy, s, a); \
+    else                                                                                    \
+      hipLaunchKernelGGL((k_xy<R, n, false>), dim3(unsigned(nblk_xy)), dim3(256), smem_xy, s, a); \
   } break;
   switch (p->N3) {
     QM_FOR_EACH_FFT_LEN(QM_ZINV)
@@ -100,7 +107,7 @@ void launch_local_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* 
   }
   QM_HIP(hipGetLastError());
   if (ev) ev->mark(0);
-  if (xy_pick(p, sizeof(R) == 8 ? 0 : 1) == 2) {
+  if (xy_mode == 2) {
     const size_t smem_p = sizeof(cplx<R>) * (size_t(NX) * a.nax_stride + NX) + sizeof(int) * NX;
 #define QM_XYP(n, l)                                                                        \
   case n: {                                                                                 \

@@ -183,7 +183,7 @@ void autotune_projection(qm_hpsi_plan* p, int nbnd, hipStream_t s, int lp, doubl
 // time the local part (scatter, FFTs, V, gather) of min(nk, 32) k-points at nbnd bands with
 // each xy-plane kernel, per real type; keep the faster one
 static void autotune_xy(qm_hpsi_plan* p, int nbnd, hipStream_t s) {
-  if (p->xy_forced != 0 || xy_group_lanes(p->N1) == 0) return;
+  if (p->xy_forced != 0) return;
   const char* path = std::getenv("QM_AUTOTUNE_CACHE");
   std::map<std::string, int> cache = load_cache(path);
   const int k1 = std::min(p->nk, kMaxSlices);
@@ -211,7 +211,12 @@ static void autotune_xy(qm_hpsi_plan* p, int nbnd, hipStream_t s) {
     }
     int best = 1;
     double bms = 1e30;
-    for (int v = 1; v <= 2; ++v) {
+    for (int v = 1; v <= 3; ++v) {
+      if (v == 2 && xy_group_lanes(p->N1) == 0) continue;
+      const size_t real_bytes = rt == 0 ? 8 : 4;
+      if (v != 2 && xy_lds_bytes(p->N1, xy_row_stride(p->N1, p->nax_max, v == 3), real_bytes,
+                                 v == 3) > 160 * 1024)
+        continue;
       p->xy_variant[rt] = v;
       launch_hpsi_local(p, sl, psi, out, s, rt == 1, nullptr);  // warm
       QM_HIP(hipEventRecord(e0, s));

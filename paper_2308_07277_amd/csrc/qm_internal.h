@@ -135,8 +135,9 @@ struct qm_hpsi_plan {
   hipStream_t capture_stream = nullptr;
   int32_t use_graphs = 1;
   // xy-plane kernel per real type of the local part (0 float64, 1 float32): 1 the two-pass
-  // kernel, 2 the lane-group kernel (grids 20, 40, 72), 0 the built-in choice; set by the
-  // autotuner.  xy_forced (environment QM_XY_MODE = 1 or 2) overrides both.
+  // kernel with a row scratch, 2 the lane-group kernel (grids 20, 40, 72), 3 the two-pass
+  // kernel with the x-row exchanges in the rows' own slots, 0 the built-in choice; set by the
+  // autotuner.  xy_forced (environment QM_XY_MODE = 1, 2 or 3) overrides both.
   int32_t xy_variant[2] = {0, 0};
   int32_t xy_forced = 0;
   // Davidson tridiagonalisation: 1 one workgroup per k-point, 2 many workgroups per k-point
@@ -191,7 +192,12 @@ void apply_h_slices(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* 
                     const ProjScratch* ps = nullptr, const HpsiWork* wk = nullptr);
 std::vector<KSlice> contiguous_slices(const qm_hpsi_plan* p, int k0, int k1, int nbnd);
 int xy_group_lanes(int nx);                       // lanes per line of the lane-group kernel, 0: none
-int xy_pick(const qm_hpsi_plan* p, int real_type);  // 1 two-pass, 2 lane-group
+// 1 two-pass with row scratch, 2 lane-group, 3 two-pass with the exchanges in the rows' slots
+int xy_pick(const qm_hpsi_plan* p, int real_type);
+// row stride (complex elements) of the two-pass xy-plane kernel's LDS plane for an N1 = n grid,
+// and the kernel's LDS bytes (own: exchanges in the rows' own slots)
+int xy_row_stride(int n, int nax_max, bool own);
+size_t xy_lds_bytes(int n, int ns, size_t real_bytes, bool own);
 void convert_beta(qm_hpsi_plan* p, qm_prec prec, hipStream_t s);
 bool fft_len_supported(int n);
 int fft_split_r1(int n);
