@@ -427,6 +427,150 @@ def davidson_run(name, weights=None, tol=1e-8, max_basis_factor=4, lanes=3, only
                                     "eigenvalue against the exact one (Krylov-Weinstein)"}
 
 
+def _timed(fn, reps):
+    """Median wall time (s) of fn() over reps calls, each bracketed by device synchronisation,
+    after one untimed call."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def _cpu_timed(fn, reps=1):
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts))
+
+
+def adjacent_rows(reps=5):
+    """The parts built on the H|psi> kernels, each timed on the GPU (median of reps calls
+    after an untimed one) with the FP64 CPU oracle timed beside it on a bounded sample:
+    electron density and Hartree potential on the 64-atom cell, the Hartree-only SCF on the
+    2- and 8-atom cells, ETRS real-time propagation and GW plane-wave matrix elements on the
+    64-atom cell."""
+    import torch
+    import workload
+    import paper_2308_07277_amd as qm
+    from oracle import density as od, tddft as otd, gw as ogw, hamiltonian as ham
+    out = {}
+    w = workload.make_workload("c3")
+    miller, beta, vloc, psi = build_inputs(w)
+    plan = qm.qm_hpsi_plan_create(w.cell, w.grid, w.k_cart, w.npw, miller, w.nbnd, w.nproj,
+                                  vloc, beta, w.dmat(), 0)
+    nst = _nsticks(w.miller[0], w.grid)
+    bands = w.nk * w.nbnd
+    # density: sphere -> sticks -> planes, |psi(r)|^2 accumulated over every k and band
+    rho = torch.empty(tuple(w.grid), dtype=torch.float64, device="cuda")
+    wk = np.full(w.nk, 1.0 / w.nk)
+    occ = np.full((w.nk, w.nbnd), 2.0)
+    t = _timed(lambda: qm.qm_density(plan, -1, psi, w.nbnd, wk, occ, rho), reps)
+    # algorithmic bytes per band: psi read, float64 sticks written and read back
+    per_band = 16.0 * float(w.npw.mean()) + 2 * 16.0 * nst * w.grid[2]
+    per_k = [w.psi(0)[:16]]
+    tc = _cpu_timed(lambda: od.density_ref(w.cell, w.grid, [w.miller[0]], [1.0], [np.full(16, 2.0)], per_k))
+    out["density"] = {"workload": "c3: 16 k x 160 bands -> rho on the 72^3 grid, float64",
+                      "ms_per_call": 1e3 * t, "bands_per_s": bands / t,
+                      "hbm": {"algorithmic_bytes_per_band": per_band,
+                              "achieved_GBps": bands * per_band / t / 1e9, "peak_GBps": HBM_PEAK_GBS,
+                              "frac": bands * per_band / t / 1e9 / HBM_PEAK_GBS},
+                      "cpu_oracle": {"bands_per_s": 16 / tc, "cores": 1,
+                                     "sample": "oracle.density.density_ref, k = 0, 16 bands"}}
+    # Hartree potential: forward + inverse 3-D FFT of the grid and the Poisson multiply
+    vh = torch.empty_like(rho)
+    t = _timed(lambda: qm.qm_hartree(plan, rho, vh), reps)
+    r_h = rho.cpu().numpy()
+    tc = _cpu_timed(lambda: od.hartree_ref(w.cell, w.grid, r_h), 3)
+    nr = int(np.prod(w.grid))
+    # float64 complex grid read and written by each of the 3 + 3 line-FFT passes
+    hb = 6 * 2 * 16.0 * nr
+    out["hartree"] = {"workload": "c3: 72^3 grid, float64", "ms_per_call": 1e3 * t,
+                      "hbm": {"algorithmic_bytes": hb, "achieved_GBps": hb / t / 1e9,
+                              "peak_GBps": HBM_PEAK_GBS, "frac": hb / t / 1e9 / HBM_PEAK_GBS},
+                      "cpu_oracle": {"ms_per_call": 1e3 * tc, "cores": 1,
+                                     "sample": "oracle.density.hartree_ref on the same grid"}}
+    progress("density and Hartree potential measured")
+    # ETRS: nocc doubly occupied bands of every k, Taylor order 4, two steps per call
+    nocc, dt, order, nsteps = 64, 0.05, 4, 2
+    occ_t = np.full((w.nk, nocc), 2.0)
+    flat = torch.cat([torch.from_numpy(w.psi(ik, purpose=7, nbnd=nocc).reshape(-1)) for ik in range(w.nk)]).cuda()
+    vx = torch.from_numpy(w.vloc_r()).cuda()
+    tstep = _timed(lambda: qm.qm_td_etrs(plan, vx, wk, occ_t, flat, nocc, dt, order, nsteps), 3) / nsteps
+    happ = 3 * order * nocc * w.nk   # three exponentials of `order` H applications per band
+    m0 = w.miller[0]
+    b0 = w.beta(0)
+    x0 = w.psi(0, purpose=7, nbnd=8)
+    build = otd.hartree_model_h(w.cell, w.grid, [m0], [w.k_cryst[0]], [1.0], [np.full(8, 2.0)],
+                                w.vloc_r(), [b0], w.dmat())
+    tc = _cpu_timed(lambda: otd.etrs_step(build, [x0], dt, order))
+    out["etrs"] = {"workload": f"c3: 16 k x {nocc} doubly occupied bands, Hartree-only model, Taylor "
+                               f"order {order}, dt {dt}",
+                   "ms_per_step": 1e3 * tstep, "h_band_applications_per_step": happ,
+                   "h_band_applications_per_s": happ / tstep,
+                   "cpu_oracle": {"ms_per_step": 1e3 * tc, "h_band_applications_per_step": 3 * order * 8,
+                                  "cores": 1, "sample": "oracle.tddft.etrs_step, k = 0, 8 bands"}}
+    progress("ETRS propagation measured")
+    # GW matrix elements: k+q = k-point 1, k = k-point 0, 32 x 32 bands, 500 G vectors
+    nb1 = nb2 = 32
+    ng = 500
+    ckq = torch.from_numpy(w.psi(1, purpose=5, nbnd=nb1).reshape(-1)).cuda()
+    ck = torch.from_numpy(w.psi(0, purpose=6, nbnd=nb2).reshape(-1)).cuda()
+    mg = w.miller[0][:ng]
+    mtx = torch.empty((nb1, nb2, ng), dtype=torch.complex128, device="cuda")
+    t = _timed(lambda: qm.qm_mtxel(plan, 1, ckq, nb1, 0, ck, nb2, mg, mtx), reps)
+    a_kq = w.psi(1, purpose=5, nbnd=4)
+    a_k = w.psi(0, purpose=6, nbnd=4)
+    tc = _cpu_timed(lambda: ogw.mtxel_fft(w.grid, a_kq, w.miller[1], a_k, w.miller[0], mg))
+    out["gw_mtxel"] = {"workload": f"c3: k+q = k-point 1, k = k-point 0, {nb1} x {nb2} bands, {ng} G",
+                       "ms_per_call": 1e3 * t, "pairs_per_s": nb1 * nb2 / t,
+                       "cpu_oracle": {"pairs_per_s": 16 / tc, "cores": 1,
+                                      "sample": "oracle.gw.mtxel_fft, 4 x 4 bands, same G"}}
+    progress("GW matrix elements measured")
+    plan.close()
+    del psi, flat, rho, vh, vx, mtx
+    torch.cuda.empty_cache()
+    # Hartree-only SCF to a density residual of 1e-9
+    scf = {}
+    for name, nocc_s, nb_s in (("c1", 1, 4), ("c2", 4, 8)):
+        ws = workload.make_workload(name)
+        ms, bs, vs, _ = build_inputs(ws)
+        pl = qm.qm_hpsi_plan_create(ws.cell, ws.grid, ws.k_cart, ws.npw, ms, nb_s, ws.nproj, vs, bs,
+                                    ws.dmat(), 0)
+        start = torch.cat([torch.from_numpy(ws.psi(ik, purpose=2, nbnd=nb_s).reshape(-1))
+                           for ik in range(ws.nk)]).cuda()
+        r_s = torch.empty(tuple(ws.grid), dtype=torch.float64, device="cuda")
+        v_s = torch.empty_like(r_s)
+        kw = np.full(ws.nk, 1.0 / ws.nk)
+        ps = start.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st, status = qm.qm_scf_hartree(pl, vs, kw, nocc_s, ps, nb_s, r_s, v_s, alpha=0.7, tol=1e-9)
+        torch.cuda.synchronize()
+        scf[name] = {"status": int(status), "s": time.perf_counter() - t0, **st}
+        if name == "c1":
+            beta_c1 = [bs.cpu().numpy().reshape(ws.nproj, -1)]
+            tc = _cpu_timed(lambda: od.hartree_scf_ref(ws.cell, ws.grid, ws.miller, ws.k_cryst, [1.0],
+                                                       ws.vloc_r(), beta_c1, ws.dmat(), nocc=1,
+                                                       alpha=0.7, tol=1e-9))
+            scf[name]["cpu_oracle_s"] = tc
+        pl.close()
+    out["scf_hartree"] = {"workload": "Hartree-only SCF, linear mixing 0.7, density residual 1e-9: "
+                                      "c1 1 and c2 4 doubly occupied bands per k",
+                          "runs": scf,
+                          "cpu_oracle_note": "oracle.density.hartree_scf_ref (dense diagonalisation "
+                                             "every iteration) on c1, one thread"}
+    progress("Hartree-only SCF measured")
+    return out
+
+
 def progress(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -447,6 +591,8 @@ def main():
                     help="also measure H|psi> bands/s on the 2-, 8- and 216-atom workloads")
     ap.add_argument("--davidson-c5", type=int, default=1,
                     help="also time the Davidson on the 216-atom Gamma-point cell (about a minute)")
+    ap.add_argument("--adjacent", type=int, default=1,
+                    help="also time density, Hartree, SCF, ETRS and GW matrix elements")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy a MIB-sized device buffer (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -553,6 +699,8 @@ def main():
         for n in ("c1", "c2", "c5"):
             out["hpsi_other_workloads"][n] = hpsi_rates(n)
             progress(f"H|psi> on {n} measured")
+    if args.adjacent:
+        out["adjacent"] = adjacent_rows()
     if args.davidson:
         weights, tinfo = train_preconditioner()
         out["mlp_training"] = tinfo
