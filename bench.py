@@ -390,6 +390,8 @@ def davidson_run(name, weights=None, tol=1e-8, max_basis_factor=4, lanes=3, only
                                 "n_hpsi_bands_lowp": stats["n_hpsi_bands_lowp"],
                                 "max_resnorm": stats["max_resnorm"], "t_hpsi_ms": stats["t_hpsi_ms"],
                                 "t_eig_ms": stats["t_eig_ms"], "t_subspace_ms": stats["t_subspace_ms"],
+                                "gram_schmidt_calls": stats["n_gs"],
+                                "gram_schmidt_second_passes": stats["n_gs_second"],
                                 "extra_bands": eb, "switch_resid": arm[2],
                                 "subspace": "float32 before the switch" if arm[6] else "float64"}
                 if arm[0] in HEADLINE_ARMS and st == 0:

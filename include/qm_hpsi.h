@@ -130,6 +130,9 @@ typedef struct {
   double t_eig_ms;        /* device time in the projected eigenproblem (HIP events); with
                              lanes, each of the three is the largest over the lanes */
   double t_total_ms;      /* wall time of the call */
+  int64_t n_gs;           /* Gram-Schmidt orthogonalisations of a k-point's corrections */
+  int64_t n_gs_second;    /* of which needed a second pass (some column kept less than
+                             1/sqrt 2 of its norm in the first) */
 } qm_dav_stats;
 
 /* ------------------------------------------------------------------ plan */

@@ -71,7 +71,8 @@ class qm_dav_stats(ctypes.Structure):
                 ("n_hpsi_bands", ctypes.c_int64), ("n_hpsi_bands_lowp", ctypes.c_int64),
                 ("max_resnorm", ctypes.c_double), ("t_hpsi_ms", ctypes.c_double),
                 ("t_subspace_ms", ctypes.c_double), ("t_eig_ms", ctypes.c_double),
-                ("t_total_ms", ctypes.c_double)]
+                ("t_total_ms", ctypes.c_double), ("n_gs", ctypes.c_int64),
+                ("n_gs_second", ctypes.c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -38,6 +38,7 @@ struct DavState {
   double *theta = nullptr, *d = nullptr, *e = nullptr, *resn = nullptr, *tkin = nullptr,
          *yw = nullptr, *fw = nullptr;
   int32_t *unconv = nullptr, *info = nullptr;
+  double* cgs_ovl = nullptr;     // [k] overlap left after the first Gram-Schmidt pass
   int64_t* goff = nullptr;
   TrdWork trd{};
   EigWork ew{};
@@ -48,8 +49,10 @@ struct DavState {
   int64_t work_bytes = 0;
   double *h_resn = nullptr, *h_theta = nullptr;
   int32_t *h_unconv = nullptr, *h_info = nullptr;
+  double* h_cgs_ovl = nullptr;
   std::vector<int> m, it, done;
   int64_t n_hpsi = 0, n_hpsi_lowp = 0;
+  int64_t n_cgs = 0, n_cgs2 = 0;   // Gram-Schmidt calls per k, and those that took a second pass
   double tol = 1e-8;
   std::vector<double> hist;  // max residual per step (precision-ladder stagnation test)
   double* estar = nullptr;   // converged eigenvalues for training-pair generation
@@ -62,10 +65,10 @@ static void dav_release(DavState* d) {
   void* dev[] = {d->V, d->HV, d->X, d->HX, d->R, d->TS, d->Hs, d->Aw, d->Z, d->tau, d->Cw, d->G,
                  d->W, d->theta, d->d, d->e, d->resn, d->tkin, d->yw, d->fw, d->unconv, d->info,
                  d->goff, d->work, d->estar, d->ps.part, d->trd.v, d->trd.w, d->trd.part, d->trd.cnt,
-                 d->ew.sc, d->ew.nrm, d->chol_dmax, d->chol_ld, d->bt_t};
+                 d->ew.sc, d->ew.nrm, d->chol_dmax, d->chol_ld, d->bt_t, d->cgs_ovl};
   for (void* q : dev)
     if (q) (void)hipFree(q);
-  void* host[] = {d->h_resn, d->h_theta, d->h_unconv, d->h_info};
+  void* host[] = {d->h_resn, d->h_theta, d->h_unconv, d->h_info, d->h_cgs_ovl};
   for (void* q : host)
     if (q) (void)hipHostFree(q);
   for (hipEvent_t& e : d->ev)
@@ -128,6 +131,7 @@ static DavState* dav_create(qm_hpsi_plan* p, int k0, int k1, int nb, int mb, boo
     d->fw = dalloc<double>(nk * nb * 3 * mb);
     d->unconv = dalloc<int32_t>(nk * nb);
     d->info = dalloc<int32_t>(nk);
+    d->cgs_ovl = dalloc<double>(nk);
     d->goff = dalloc<int64_t>(nk);
     QM_REQUIRE(mb <= kTrdMaxBasis, QM_E_ARG, "max_basis above the tridiagonalisation limit (2048)");
     d->trd.v = dalloc<double2>(nk * 2 * mb);
@@ -149,6 +153,7 @@ static DavState* dav_create(qm_hpsi_plan* p, int k0, int k1, int nb, int mb, boo
     QM_HIP(hipHostMalloc(reinterpret_cast<void**>(&d->h_theta), nk * mb * sizeof(double)));
     QM_HIP(hipHostMalloc(reinterpret_cast<void**>(&d->h_unconv), nk * nb * sizeof(int32_t)));
     QM_HIP(hipHostMalloc(reinterpret_cast<void**>(&d->h_info), nk * sizeof(int32_t)));
+    QM_HIP(hipHostMalloc(reinterpret_cast<void**>(&d->h_cgs_ovl), nk * sizeof(double)));
     for (hipEvent_t& e : d->ev) QM_HIP(hipEventCreate(&e));
     const void* big[] = {reinterpret_cast<const void*>(&k_tridiag), reinterpret_cast<const void*>(&k_eig_vals),
                          reinterpret_cast<const void*>(&k_chol_inv_cols),
@@ -210,8 +215,12 @@ static void cholesky_inverse(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hi
 // to the reduced-precision H.  From the switch on they are float64 either way.
 static int subspace_lp(const DavState* d) { return (d->lowp && d->sub32) ? 3 : 0; }
 
-// T = rows [m - nu, m) of V; orthogonalise against rows [0, m - nu) (two CGS passes) and
-// orthonormalise (two CholQR passes).  Returns false if a Gram matrix was not positive definite.
+// T = rows [m - nu, m) of V (unit columns); orthogonalise against rows [0, m - nu) by
+// classical Gram-Schmidt and orthonormalise (two CholQR passes).  The second Gram-Schmidt
+// pass runs for the k-points where the first one removed more than half of some column's
+// squared norm (Kahan-Parlett "twice is enough": a column that keeps at least 1/sqrt 2 of its
+// norm is orthogonal to the basis to working precision after one pass), and always in the
+// float32-arithmetic subspace mode.  Returns false if a Gram matrix was not positive definite.
 static bool orthonormalise(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipStream_t s) {
   const int lp = subspace_lp(d);
   std::vector<GemmCN> cn;
@@ -220,11 +229,13 @@ static bool orthonormalise(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipS
   // cleared once here and only ever set by a failed pivot, so a failure in the first CholQR
   // pass is still reported after the second
   QM_HIP(hipMemsetAsync(d->info, 0, sizeof(int32_t) * d->nk, s));
+  DJobs again = jobs;   // the jobs of the second pass
   for (int pass = 0; pass < 2; ++pass) {
+    const DJobs& js = pass == 0 ? jobs : again;
     cn.clear();
     ex.clear();
-    for (int i = 0; i < jobs.n; ++i) {
-      const DJob& j = jobs.j[i];
+    for (int i = 0; i < js.n; ++i) {
+      const DJob& j = js.j[i];
       const int base = j.m - j.nu;
       if (base == 0) continue;
       double2* T = vrow(d, d->V, j, base);
@@ -232,8 +243,24 @@ static bool orthonormalise(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipS
       cn.push_back(GemmCN{vrow(d, d->V, j, 0), T, C, base, j.nu, j.npw, j.npw, j.npw, d->nb});
       ex.push_back(GemmEX{C, vrow(d, d->V, j, 0), T, j.nu, j.npw, base, d->nb, j.npw, j.npw});
     }
+    if (cn.empty()) break;
     zgemm_cn_batched(cn, 1.0, 0.0, d->work, d->work_bytes, s, nullptr, 0, lp);
+    if (pass == 0 && lp == 0) {
+      hipLaunchKernelGGL(k_cgs_overlap, dim3(jobs.n), dim3(256), 0, s, jobs, d->Cw, d->cgs_ovl);
+      QM_HIP(hipGetLastError());
+      QM_HIP(hipMemcpyAsync(d->h_cgs_ovl, d->cgs_ovl, sizeof(double) * d->nk, hipMemcpyDeviceToHost, s));
+    }
     zgemm_ex_batched(ex, -1.0, 1.0, s, lp);
+    if (pass == 0 && lp == 0) {
+      QM_HIP(hipStreamSynchronize(s));
+      again.n = 0;
+      for (int i = 0; i < jobs.n; ++i) {
+        const DJob& j = jobs.j[i];
+        if (j.m - j.nu > 0 && !(d->h_cgs_ovl[j.k] <= 0.5)) again.j[again.n++] = j;
+      }
+      d->n_cgs2 += again.n;
+      d->n_cgs += jobs.n;
+    }
   }
   for (int pass = 0; pass < 2; ++pass) {
     cn.clear();
@@ -459,6 +486,7 @@ static qm_status dav_step_range(qm_hpsi_plan* p, DavState** slot, bool own_scrat
     std::fill(d->it.begin(), d->it.end(), 0);
     std::fill(d->done.begin(), d->done.end(), 0);
     d->n_hpsi = d->n_hpsi_lowp = 0;
+    d->n_cgs = d->n_cgs2 = 0;
     d->t_hpsi = d->t_sub = d->t_eig = 0;
     d->lowp = o && o->switch_resid > 0.0 && p->prec != QM_PREC_FP64;
     d->sub32 = o && o->subspace_fp32 != 0;
@@ -839,6 +867,8 @@ qm_status qm_davidson_solve(qm_hpsi_plan* plan, int32_t k, void* psi, double* ei
       }
       stats->n_hpsi_bands += d->n_hpsi;
       stats->n_hpsi_bands_lowp += d->n_hpsi_lowp;
+      stats->n_gs += d->n_cgs;
+      stats->n_gs_second += d->n_cgs2;
       th = std::max(th, d->t_hpsi);   // lanes overlap in time: the slowest lane's phases
       te = std::max(te, d->t_eig);
       ts = std::max(ts, d->t_sub);

@@ -88,6 +88,7 @@ __global__ void k_residual(DJobs jobs, const double2* X, const double2* HX, doub
                            const double* theta, const double* kin_all, const int64_t* goff,
                            double* resn, double* tkin);
 __global__ void k_start_block(DJobs jobs, double2* V, int first);
+__global__ void k_cgs_overlap(DJobs jobs, const double2* Cw, double* ovl);
 __global__ void k_teter(DJobs jobs, const double2* Rr, double2* V, const int32_t* unconv,
                         const double* tkin, const double* kin_all, const int64_t* goff);
 }  // namespace qm

@@ -1443,6 +1443,31 @@ __global__ void __launch_bounds__(256) k_residual(DJobs jobs, const double2* __r
 
 // One workgroup per (job, j < nu): band n = unconv[k][j]; t = K(kin/T_n) r_n normalised,
 // written to row (m - nu + j) of the basis block V.
+// Largest squared norm, over the correction columns c of a job, of their overlap with the old
+// basis after a Gram-Schmidt pass: ovl[k] = max_c sum_{i < m - nu} |C(i, c)|^2, C = V^H T.
+// The corrections are unit vectors, so 1 - ovl[k] is the smallest squared column norm left
+// by the pass.  Fixed-order sums and a max: the same result on every run.
+__global__ void __launch_bounds__(256) k_cgs_overlap(DJobs jobs, const double2* __restrict__ Cw,
+                                                     double* __restrict__ ovl) {
+  __shared__ double red[4];
+  const DJob& J = jobs.j[blockIdx.x];
+  const int nb = jobs.nb, base = J.m - J.nu;
+  const double2* C = Cw + int64_t(J.k) * jobs.mb * nb;
+  double mx = 0.0;
+  for (int c = threadIdx.x; c < J.nu; c += blockDim.x) {
+    double sq = 0.0;
+    for (int i = 0; i < base; ++i) {
+      const double2 v = C[int64_t(i) * nb + c];
+      sq += v.x * v.x + v.y * v.y;
+    }
+    mx = fmax(mx, sq);
+  }
+  for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_down(mx, o, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) ovl[J.k] = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+}
+
 __global__ void __launch_bounds__(256) k_teter(DJobs jobs, const double2* __restrict__ Rr,
                                                double2* __restrict__ V,
                                                const int32_t* __restrict__ unconv,
