@@ -9,9 +9,12 @@
 //   EX:  Y(j,g) = alpha sum_i W(i,j) A(i,g) + beta Y   expansion beta (D P)
 //        accumulated into H psi, Ritz updates X = V Y, Gram-Schmidt and CholQR
 //        updates.
-// Complex products are four real MFMAs (v_mfma_f64_16x16x4f64 in float64,
-// v_mfma_f32_16x16x4f32 in float32, v_mfma_f32_16x16x32_bf16 for bfloat16
-// operands with float32 accumulation).  Workgroup tile 64x64, four waves of
+// Complex products in float64 and float32 are three real MFMAs (v_mfma_f64_16x16x4f64,
+// v_mfma_f32_16x16x4f32) by Gauss's three-multiplication form: with t1 = sum ar br,
+// t2 = sum ai bi and t3 = sum (ar + s ai)(br + s' bi) for the signs of the product, the real
+// and imaginary parts are t1 -+ t2 and t3 - t1 +- t2 (the sums of the operand parts are
+// formed once per element read from LDS).  bfloat16 operands (v_mfma_f32_16x16x32_bf16,
+// float32 accumulation) use four: those kernels are bound by memory traffic.  Workgroup tile 64x64, four waves of
 // 32x32 (2x2 MFMA tiles), K staged through LDS 16 (32 for bf16) at a time.
 #include <hip/hip_bf16.h>
 
@@ -92,7 +95,7 @@ __device__ __forceinline__ int find_prob(const B& b, int bid) {
 // Output tile TM x TN: 64 x 64, or 128 x 32 when the column count is a multiple of 32 but
 // not of 64 (e.g. 160 bands: no padded columns); four waves of 32 x 32 each.
 template <typename T, typename SA, typename SB, int TM, int TN>
-__global__ void __launch_bounds__(256) k_cgemm_cn(const CNBatch batch, int nsplit,
+__global__ void __launch_bounds__(256, 2) k_cgemm_cn(const CNBatch batch, int nsplit,
                                                   cplx<T>* __restrict__ work) {
   typedef typename Acc<T>::type AV;
   constexpr int NAE = TM * KC / 256, NBE = TN * KC / 256;   // K values per thread and chunk
@@ -115,13 +118,14 @@ __global__ void __launch_bounds__(256) k_cgemm_cn(const CNBatch batch, int nspli
   const int lbrow = tid / (KC / NBE), lbseg = (tid % (KC / NBE)) * NBE;
   const SA* A = reinterpret_cast<const SA*>(P.A);
   const SB* B = reinterpret_cast<const SB*>(P.B);
-  AV cr[2][2], ci[2][2];
+  AV t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      cr[a][b] = AV{0, 0, 0, 0};
-      ci[a][b] = AV{0, 0, 0, 0};
+      t1[a][b] = AV{0, 0, 0, 0};
+      t2[a][b] = AV{0, 0, 0, 0};
+      t3[a][b] = AV{0, 0, 0, 0};
     }
   const bool arow = (i0 + larow) < P.M, brow = (j0 + lbrow) < P.N;
   // rows past the matrix read row i0 / j0 (which exists) and are zeroed after the load
@@ -175,15 +179,20 @@ __global__ void __launch_bounds__(256) k_cgemm_cn(const CNBatch batch, int nspli
         a[t] = As[wi + t * 16 + (lane & 15)][kq];
         b[t] = Bs[wj + t * 16 + (lane & 15)][kq];
       }
+      // conj(a) b = (ar br + ai bi) + i (ar bi - ai br); (ar - ai)(br + bi) = t1 - t2 + im
+      T sa[2], sb[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        sa[t] = a[t].re - a[t].im;
+        sb[t] = b[t].re + b[t].im;
+      }
 #pragma unroll
       for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
         for (int tj = 0; tj < 2; ++tj) {
-          // conj(a) * b = (ar br + ai bi) + i (ar bi - ai br)
-          cr[ti][tj] = mfma4(a[ti].re, b[tj].re, cr[ti][tj]);
-          cr[ti][tj] = mfma4(a[ti].im, b[tj].im, cr[ti][tj]);
-          ci[ti][tj] = mfma4(a[ti].re, b[tj].im, ci[ti][tj]);
-          ci[ti][tj] = mfma4(-a[ti].im, b[tj].re, ci[ti][tj]);
+          t1[ti][tj] = mfma4(a[ti].re, b[tj].re, t1[ti][tj]);
+          t2[ti][tj] = mfma4(a[ti].im, b[tj].im, t2[ti][tj]);
+          t3[ti][tj] = mfma4(sa[ti], sb[tj], t3[ti][tj]);
         }
     }
     __syncthreads();
@@ -197,7 +206,8 @@ __global__ void __launch_bounds__(256) k_cgemm_cn(const CNBatch batch, int nspli
       for (int r = 0; r < 4; ++r) {
         const int i = i0 + wi + ti * 16 + acc_row<T>(lane, r);
         const int j = j0 + wj + tj * 16 + (lane & 15);
-        if (i < P.M && j < P.N) W[int64_t(i) * P.N + j] = cplx<T>{cr[ti][tj][r], ci[ti][tj][r]};
+        const T x1 = t1[ti][tj][r], x2 = t2[ti][tj][r];
+        if (i < P.M && j < P.N) W[int64_t(i) * P.N + j] = cplx<T>{x1 + x2, t3[ti][tj][r] - x1 + x2};
       }
 }
 
@@ -282,7 +292,7 @@ __device__ __forceinline__ void store_ex_tile(const EXDev& P, int m0, int n0, in
 // Output tile TM x TN (64 x 64, or 32 x 128 when the row count is a multiple of 32 but not
 // of 64, e.g. 160 bands: no padded rows); four waves of 32 x 32 each.
 template <typename T, typename SW, typename SA, int TM, int TN>
-__global__ void __launch_bounds__(256) k_cgemm_ex(const EXBatch batch, double alpha, double beta) {
+__global__ void __launch_bounds__(256, 2) k_cgemm_ex(const EXBatch batch, double alpha, double beta) {
   typedef typename Acc<T>::type AV;
   constexpr int NWE = KC * TM / 256, NAE = KC * TN / 256;   // elements per thread and chunk
   constexpr int WM = TM / 32;                               // waves along the rows
@@ -300,13 +310,14 @@ __global__ void __launch_bounds__(256) k_cgemm_ex(const EXBatch batch, double al
   const int lra = tid / (TN / NAE), lca = (tid % (TN / NAE)) * NAE;
   const SW* Wp = reinterpret_cast<const SW*>(P.W);
   const SA* Ap = reinterpret_cast<const SA*>(P.A);
-  AV cr[2][2], ci[2][2];
+  AV t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      cr[a][b] = AV{0, 0, 0, 0};
-      ci[a][b] = AV{0, 0, 0, 0};
+      t1[a][b] = AV{0, 0, 0, 0};
+      t2[a][b] = AV{0, 0, 0, 0};
+      t3[a][b] = AV{0, 0, 0, 0};
     }
   const int nch = (P.K + KC - 1) / KC;
   // the next chunk's operands are loaded into registers while this chunk's MFMAs run
@@ -351,18 +362,32 @@ __global__ void __launch_bounds__(256) k_cgemm_ex(const EXBatch batch, double al
         a[t] = Ws[kq][wi + t * 16 + (lane & 15)];
         b[t] = As[kq][wj + t * 16 + (lane & 15)];
       }
+      // w a = (wr ar - wi ai) + i (wr ai + wi ar); (wr + wi)(ar + ai) = t1 + t2 + im
+      T sa[2], sb[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        sa[t] = a[t].re + a[t].im;
+        sb[t] = b[t].re + b[t].im;
+      }
 #pragma unroll
       for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
         for (int tj = 0; tj < 2; ++tj) {
-          cr[ti][tj] = mfma4(a[ti].re, b[tj].re, cr[ti][tj]);
-          cr[ti][tj] = mfma4(-a[ti].im, b[tj].im, cr[ti][tj]);
-          ci[ti][tj] = mfma4(a[ti].re, b[tj].im, ci[ti][tj]);
-          ci[ti][tj] = mfma4(a[ti].im, b[tj].re, ci[ti][tj]);
+          t1[ti][tj] = mfma4(a[ti].re, b[tj].re, t1[ti][tj]);
+          t2[ti][tj] = mfma4(a[ti].im, b[tj].im, t2[ti][tj]);
+          t3[ti][tj] = mfma4(sa[ti], sb[tj], t3[ti][tj]);
         }
     }
     __syncthreads();
   }
+  AV cr[2][2], ci[2][2];
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj) {
+      cr[ti][tj] = t1[ti][tj] - t2[ti][tj];
+      ci[ti][tj] = t3[ti][tj] - t1[ti][tj] - t2[ti][tj];
+    }
   store_ex_tile<T>(P, m0, n0, wi, wj, lane, cr, ci, alpha, beta);
 }
 
