@@ -105,10 +105,11 @@ __global__ void __launch_bounds__(256, 2) k_cgemm_cn(const CNBatch batch, int ns
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const int pi = find_prob(batch, lb);
   const CNDev& P = batch.p[pi];
-  // row tiles fastest: the row tiles of one (column tile, K split) share the B slab
-  const int bid = lb - P.blk0, rest = bid / P.tm;
-  const int split = rest % nsplit;
-  const int i0 = (bid % P.tm) * TM, j0 = (rest / nsplit) * TN;
+  // the tiles of one K split are numbered consecutively (column tiles fastest), so each of
+  // its A and B slabs is fetched from memory once and shared through the XCD's L2
+  const int bid = lb - P.blk0, per_split = P.tm * P.tn;
+  const int split = bid / per_split, tile = bid - split * per_split;
+  const int i0 = (tile / P.tn) * TM, j0 = (tile % P.tn) * TN;
   const int nch = (P.K + KC - 1) / KC;
   const int per = (nch + nsplit - 1) / nsplit;
   const int c0 = split * per, c1 = min(nch, c0 + per);
@@ -451,10 +452,11 @@ __global__ void __launch_bounds__(256) k_cgemm_cn_bf16(const CNBatch batch, int 
   const int lb = xcd_logical_block(blockIdx.x, gridDim.x);
   const int pi = find_prob(batch, lb);
   const CNDev& P = batch.p[pi];
-  // row tiles fastest: the row tiles of one (column tile, K split) share the B slab
-  const int bid = lb - P.blk0, rest = bid / P.tm;
-  const int split = rest % nsplit;
-  const int i0 = (bid % P.tm) * BT, j0 = (rest / nsplit) * BT;
+  // the tiles of one K split are numbered consecutively (column tiles fastest), so each of
+  // its A and B slabs is fetched from memory once and shared through the XCD's L2
+  const int bid = lb - P.blk0, per_split = P.tm * P.tn;
+  const int split = bid / per_split, tile = bid - split * per_split;
+  const int i0 = (tile / P.tn) * BT, j0 = (tile % P.tn) * BT;
   const int nch = (P.K + KB - 1) / KB;
   const int per = (nch + nsplit - 1) / nsplit;
   const int c0 = split * per, c1 = min(nch, c0 + per);
