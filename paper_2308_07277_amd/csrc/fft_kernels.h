@@ -42,6 +42,8 @@ struct LocalArgs {
   const int32_t* tile_ptr;
   const int32_t* stick_pos;
   const int32_t* col_of_i1;
+  const int32_t* stick_at;  // [nk][N2][sat_stride] stick index of (i2, active column), or -1
+  int32_t sat_stride;
   const double* kin;
   const void* vplan;        // R [slot][i1][i2]
   const double2* tw_z;      // exp(+2 pi i m / N3), m < N3
@@ -236,23 +238,15 @@ __global__ void __launch_bounds__(256, (xy_min_waves<R, NX, OWN>())) k_xy(LocalA
   const int nax = ki.nax;
   cplx<R>* plane = stick_base<R>(a, ki) +
                    (int64_t(band) * N3 + p) * ki.nstick;
-  const int32_t* spos = a.stick_pos + ki.stick_off;
-  // the first group of sticks is loaded before the tables, the zero fill and their barrier,
-  // so its round trip to memory overlaps theirs (nstick >= 1: every k has a plane wave)
-  int ps0[kUnroll];
-  R re0[kUnroll], im0[kUnroll];   // scalar arrays: an array of complex stayed in scratch
-#pragma unroll
-  for (int u = 0; u < kUnroll; ++u) {
-    const int s = min(tid + u * 256, ki.nstick - 1);
-    ps0[u] = spos[s];
-    const cplx<R> v = plane[s];
-    re0[u] = v.re;
-    im0[u] = v.im;
-  }
+  // stick index of (row i2, active column ia) at sat[i2 * sat_stride + ia], -1 where the
+  // sphere has no stick: the y passes read and write the plane's sticks directly in memory
+  const int32_t* sat = a.stick_at + int64_t(k) * NX * a.sat_stride;
+  const int sts = a.sat_stride;
   for (int i = tid; i < NX; i += 256) {
     double2 w = a.tw_x[i];
     tw[i] = {R(w.x), R(w.y)};
     col[i] = a.col_of_i1[int64_t(k) * NX + i];
+    L[i * ns + ns - 1] = {R(0), R(0)};   // the zero slot of every row
   }
   if (!kTwReg) {
     for (int i = tid; i < R2 * R2; i += 256) {
@@ -261,24 +255,27 @@ __global__ void __launch_bounds__(256, (xy_min_waves<R, NX, OWN>())) k_xy(LocalA
       twr[i] = {R(w.x), R(w.y)};
     }
   }
-  for (int i = tid; i < NX * ns; i += 256) L[i] = {R(0), R(0)};
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < kUnroll; ++u) L[(ps0[u] & 0xffff) * ns + (ps0[u] >> 16)] = cplx<R>{re0[u], im0[u]};
-  sticks_to_lds<R, 256>(plane, spos, ki.nstick, L, ns, tid + kUnroll * 256);
   __syncthreads();
   // y-pass items w = ia + nax j: thread tid starts at (tid % nax, tid / nax) and steps by
   // 256 = dj nax + dia, so each pass walks its items without a division per item
   const int ia0 = tid % nax, j0 = tid / nax, dj = 256 / nax, dia = 256 - dj * nax;
-  // ---- inverse y on active columns: pass 1 (R2-point, stride R1)
+  // ---- inverse y on active columns: pass 1 (R2-point, stride R1), input gathered from the
+  // sticks (rows without a stick are zero; every load is issued at a valid address, so the
+  // group of loads stays together, and the absent ones are zeroed afterwards)
   for (int w = tid, ia = ia0, n1 = j0; w < nax * R1; w += 256, ia += dia, n1 += dj) {
     if (ia >= nax) {
       ia -= nax;
       ++n1;
     }
+    int si[R2];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2) si[n2] = sat[(n1 + R1 * n2) * sts + ia];
     cplx<R> x[R2];
 #pragma unroll
-    for (int n2 = 0; n2 < R2; ++n2) x[n2] = L[(n1 + R1 * n2) * ns + ia];
+    for (int n2 = 0; n2 < R2; ++n2) x[n2] = plane[max(si[n2], 0)];
+#pragma unroll
+    for (int n2 = 0; n2 < R2; ++n2)
+      if (si[n2] < 0) x[n2] = {R(0), R(0)};
     Dft<R2, +1, R>::run(x);
     // twiddle exponents n1 k2 <= (R1 - 1)(R2 - 1) < NX: no reduction modulo NX needed
 #pragma unroll
@@ -517,15 +514,18 @@ __global__ void __launch_bounds__(256, (xy_min_waves<R, NX, OWN>())) k_xy(LocalA
       ia -= nax;
       ++k2;
     }
+    int si[R2];
+#pragma unroll
+    for (int k1 = 0; k1 < R2; ++k1) si[k1] = sat[(k2 + R1 * k1) * sts + ia];
     cplx<R> z[R2];
 #pragma unroll
     for (int n1 = 0; n1 < R2; ++n1) z[n1] = L[(k2 + R1 * n1) * ns + ia];
     Dft<R2, -1, R>::run(z);
+    // row i2 = k2 + R1 k1 of the plane: written back where it has a stick
 #pragma unroll
-    for (int k1 = 0; k1 < R2; ++k1) L[(k2 + R1 * k1) * ns + ia] = z[k1];
+    for (int k1 = 0; k1 < R2; ++k1)
+      if (si[k1] >= 0) plane[si[k1]] = z[k1];
   }
-  __syncthreads();
-  lds_to_sticks<R, 256>(plane, spos, ki.nstick, L, ns, tid);
 }
 
 // ------------------------------------------------------------------ xy plane, lane-group lines

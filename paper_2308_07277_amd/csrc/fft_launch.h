@@ -37,6 +37,8 @@ LocalArgs make_local_args(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const 
   a.tile_ptr = p->g.tile_ptr;
   a.stick_pos = p->g.stick_pos;
   a.col_of_i1 = p->g.col_of_i1;
+  a.stick_at = p->g.stick_at;
+  a.sat_stride = p->nax_max;
   a.kin = p->g.kin;
   a.vplan = sizeof(R) == 8 ? p->vplan64 : p->vplan32;
   a.tw_z = p->tw_z;

@@ -41,7 +41,7 @@ static void plan_free(qm_hpsi_plan* p) {
   p->graphs.clear();
   if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
   void* ptrs[] = {p->g.kinfo, p->g.ent_g, p->g.ent_sz, p->g.tile_ptr, p->g.stick_pos,
-                  p->g.col_of_i1, p->g.flat, p->g.kin, p->vplan64, p->vplan32, p->beta64, p->beta_lp,
+                  p->g.col_of_i1, p->g.stick_at, p->g.flat, p->g.kin, p->vplan64, p->vplan32, p->beta64, p->beta_lp,
                   p->dmat, p->drange, p->tw_z, p->tw_x, p->sbuf, p->proj_part, p->proj_q};
   for (void* q : ptrs)
     if (q) (void)hipFree(q);
@@ -94,6 +94,7 @@ static void build_plan(qm_hpsi_plan* p, const double cell[9], const int32_t grid
   p->kinfo.resize(p->nk);
   int64_t g_off = 0, stick_off = 0, tile_off = 0;
   std::vector<int32_t> stick_of(size_t(N1) * N2);
+  std::vector<std::vector<int32_t>> sat_k(p->nk);   // per k: [N2][nax] stick index or -1
   for (int k = 0; k < p->nk; ++k) {
     const int npw = ks->npw[k];
     QM_REQUIRE(npw >= 1, QM_E_ARG, "every k needs npw >= 1");
@@ -137,6 +138,10 @@ static void build_plan(qm_hpsi_plan* p, const double cell[9], const int32_t grid
       if (ia_of[i1] > 0) ia_of[i1] = nax++;
       else ia_of[i1] = -1;
     for (int i1 = 0; i1 < N1; ++i1) col_of_i1[size_t(k) * N1 + i1] = ia_of[i1];
+    sat_k[k].assign(size_t(N2) * nax, -1);
+    for (int i2 = 0; i2 < N2; ++i2)
+      for (int i1 = 0; i1 < N1; ++i1)
+        if (ia_of[i1] >= 0) sat_k[k][size_t(i2) * nax + ia_of[i1]] = stick_of[size_t(i2) * N1 + i1];
     for (int s2 = 0; s2 < nstick; ++s2) stick_pos.push_back(st_i2[s2] | (ia_of[st_i1[s2]] << 16));
     // entries grouped by stick tile; inside a tile ordered by (i3, stick) so consecutive
     // threads of the z kernels touch neighbouring x-columns of one plane (adjacent in the
@@ -200,6 +205,16 @@ static void build_plan(qm_hpsi_plan* p, const double cell[9], const int32_t grid
   p->g.tile_ptr = upload(tile_ptr, s);
   p->g.stick_pos = upload(stick_pos, s);
   p->g.col_of_i1 = upload(col_of_i1, s);
+  {
+    std::vector<int32_t> stick_at(size_t(p->nk) * N2 * p->nax_max, -1);
+    for (int k = 0; k < p->nk; ++k) {
+      const int nax = p->kinfo[k].nax;
+      for (int i2 = 0; i2 < N2; ++i2)
+        for (int ia = 0; ia < nax; ++ia)
+          stick_at[(size_t(k) * N2 + i2) * p->nax_max + ia] = sat_k[k][size_t(i2) * nax + ia];
+    }
+    p->g.stick_at = upload(stick_at, s);
+  }
   p->g.flat = upload(flat, s);
   p->g.kin = upload(kin, s);
   // twiddles exp(+2 pi i m / N), exact octant reduction

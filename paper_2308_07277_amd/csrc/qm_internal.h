@@ -62,6 +62,7 @@ struct GTables {
   int32_t* tile_ptr = nullptr;   // [sum (ntile+1)] entry offset (within k) of each tile
   int32_t* stick_pos = nullptr;  // [sum nstick] i2 | (ia << 16)
   int32_t* col_of_i1 = nullptr;  // [nk][N1] active-column index of i1, or -1
+  int32_t* stick_at = nullptr;   // [nk][N2][nax_max] stick index of (i2, active column), or -1
   int32_t* flat = nullptr;       // [sum npw] C-order grid index of each G, caller order
   double* kin = nullptr;         // [sum npw] 1/2|k+G|^2 in caller order
 };
