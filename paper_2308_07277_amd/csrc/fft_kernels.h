@@ -188,6 +188,32 @@ __global__ void __launch_bounds__(TS * Split<N3>::R2) k_zinv(LocalArgs a) {
   }
 }
 
+// ------------------------------------------------------------------ stick access by index
+// Raw buffer loads and stores on one plane's sticks (a buffer resource of nstick elements):
+// an index s < 0 puts the byte offset past the resource's range, where the hardware returns
+// zero for a load and drops a store, so absent sticks need no select and no branch.
+constexpr int kBufferConfig = 0x00020000;   // gfx9 buffer resource word 3 (32-bit data format)
+template <typename R>
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t stick_rsrc(const cplx<R>* plane, int nstick) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<cplx<R>*>(plane), (short)0,
+                                           nstick * int(sizeof(cplx<R>)), kBufferConfig);
+}
+// the builtins' data types: vectors of 32-bit words (moved in and out by bit casts)
+typedef unsigned int qm_w4 __attribute__((vector_size(16)));
+typedef unsigned int qm_w2 __attribute__((vector_size(8)));
+__device__ __forceinline__ cplx<double> stick_load(__amdgpu_buffer_rsrc_t r, int s, double) {
+  return __builtin_bit_cast(cplx<double>, __builtin_amdgcn_raw_buffer_load_b128(r, s * 16, 0, 0));
+}
+__device__ __forceinline__ cplx<float> stick_load(__amdgpu_buffer_rsrc_t r, int s, float) {
+  return __builtin_bit_cast(cplx<float>, __builtin_amdgcn_raw_buffer_load_b64(r, s * 8, 0, 0));
+}
+__device__ __forceinline__ void stick_store(__amdgpu_buffer_rsrc_t r, int s, cplx<double> z) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(qm_w4, z), r, s * 16, 0, 0);
+}
+__device__ __forceinline__ void stick_store(__amdgpu_buffer_rsrc_t r, int s, cplx<float> z) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(qm_w2, z), r, s * 8, 0, 0);
+}
+
 // ------------------------------------------------------------------ xy plane
 // Orders the LDS accesses of one wave: every lane's earlier LDS writes are complete and
 // visible to the other lanes of the wave before any later LDS access.
@@ -242,6 +268,7 @@ __global__ void __launch_bounds__(256, (xy_min_waves<R, NX, OWN>())) k_xy(LocalA
   // sphere has no stick: the y passes read and write the plane's sticks directly in memory
   const int32_t* sat = a.stick_at + int64_t(k) * NX * a.sat_stride;
   const int sts = a.sat_stride;
+  const __amdgpu_buffer_rsrc_t prs = stick_rsrc<R>(plane, ki.nstick);
   for (int i = tid; i < NX; i += 256) {
     double2 w = a.tw_x[i];
     tw[i] = {R(w.x), R(w.y)};
@@ -260,8 +287,7 @@ __global__ void __launch_bounds__(256, (xy_min_waves<R, NX, OWN>())) k_xy(LocalA
   // 256 = dj nax + dia, so each pass walks its items without a division per item
   const int ia0 = tid % nax, j0 = tid / nax, dj = 256 / nax, dia = 256 - dj * nax;
   // ---- inverse y on active columns: pass 1 (R2-point, stride R1), input gathered from the
-  // sticks (rows without a stick are zero; every load is issued at a valid address, so the
-  // group of loads stays together, and the absent ones are zeroed afterwards)
+  // sticks (rows without a stick read zero)
   for (int w = tid, ia = ia0, n1 = j0; w < nax * R1; w += 256, ia += dia, n1 += dj) {
     if (ia >= nax) {
       ia -= nax;
@@ -272,10 +298,7 @@ __global__ void __launch_bounds__(256, (xy_min_waves<R, NX, OWN>())) k_xy(LocalA
     for (int n2 = 0; n2 < R2; ++n2) si[n2] = sat[(n1 + R1 * n2) * sts + ia];
     cplx<R> x[R2];
 #pragma unroll
-    for (int n2 = 0; n2 < R2; ++n2) x[n2] = plane[max(si[n2], 0)];
-#pragma unroll
-    for (int n2 = 0; n2 < R2; ++n2)
-      if (si[n2] < 0) x[n2] = {R(0), R(0)};
+    for (int n2 = 0; n2 < R2; ++n2) x[n2] = stick_load(prs, si[n2], R(0));
     Dft<R2, +1, R>::run(x);
     // twiddle exponents n1 k2 <= (R1 - 1)(R2 - 1) < NX: no reduction modulo NX needed
 #pragma unroll
@@ -523,8 +546,7 @@ __global__ void __launch_bounds__(256, (xy_min_waves<R, NX, OWN>())) k_xy(LocalA
     Dft<R2, -1, R>::run(z);
     // row i2 = k2 + R1 k1 of the plane: written back where it has a stick
 #pragma unroll
-    for (int k1 = 0; k1 < R2; ++k1)
-      if (si[k1] >= 0) plane[si[k1]] = z[k1];
+    for (int k1 = 0; k1 < R2; ++k1) stick_store(prs, si[k1], z[k1]);
   }
 }
 
