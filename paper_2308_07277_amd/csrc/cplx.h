@@ -177,6 +177,13 @@ struct DftComposite {
       for (int k2 = 1; k2 < M; ++k2) {
         if (n1 == 0) continue;
         const long e = long(n1) * k2;
+        if ((4 * e) % N == 0) {   // quarter turns are exact: S i, -1, -S i
+          const long q = (4 * e / N) % 4;
+          if (q == 1) y[n1][k2] = cmul_si<S>(y[n1][k2]);
+          else if (q == 2) y[n1][k2] = {-y[n1][k2].re, -y[n1][k2].im};
+          else if (q == 3) y[n1][k2] = cmul_si<-S>(y[n1][k2]);
+          continue;
+        }
         const R c = R(ct::cos_frac(e, N));
         const R s = R(S * ct::sin_frac(e, N));
         y[n1][k2] = cmul(y[n1][k2], cplx<R>{c, s});
