@@ -529,23 +529,35 @@ __global__ void __launch_bounds__(256) k_trd_step(DJobs jobs, int j, double2* __
     wpq[q] = W[rc];
   }
   // (A v)_r for row r of block ib: row sums of tiles (ib, 0..ib), then column sums of tiles
-  // (ib..nt-1, ib), always in this order
+  // (ib..nt-1, ib), always in this order.  The nt + 1 slots of a row are read in groups of
+  // kTrdGather, every load of a group issued before the group is added, so a row costs
+  // about (nt + 1) / kTrdGather round trips to memory instead of nt + 1.
+  constexpr int kTrdGather = 8;
 #pragma unroll
   for (int q = 0; q < kTrdRows; ++q) {
     const int r = j1 + tid + q * 256;
     pq[q] = z;
     if (r < m) {
       const int ib = r / T - b0, i = r - (b0 + ib) * T;
+      const int nrow = ib + 1, nall = nt + 1;
       double sx = 0.0, sy = 0.0;
-      for (int tj = 0; tj <= ib; ++tj) {
-        const int64_t o = ((int64_t(ib * (ib + 1) / 2 + tj) * 2) * T + i) * 2;
-        sx += __hip_atomic_load(&PS[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        sy += __hip_atomic_load(&PS[o + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      for (int ti = ib; ti < nt; ++ti) {
-        const int64_t o = ((int64_t(ti * (ti + 1) / 2 + ib) * 2 + 1) * T + i) * 2;
-        sx += __hip_atomic_load(&PS[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        sy += __hip_atomic_load(&PS[o + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      for (int c0 = 0; c0 < nall; c0 += kTrdGather) {
+        double gx[kTrdGather], gy[kTrdGather];
+#pragma unroll
+        for (int u = 0; u < kTrdGather; ++u) {
+          const int c = min(c0 + u, nall - 1);
+          const int64_t o = c < nrow ? ((int64_t(ib * (ib + 1) / 2 + c) * 2) * T + i) * 2
+                                     : ((int64_t((ib + c - nrow) * (ib + c - nrow + 1) / 2 + ib) * 2 + 1) * T + i) * 2;
+          gx[u] = __hip_atomic_load(&PS[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          gy[u] = __hip_atomic_load(&PS[o + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+#pragma unroll
+        for (int u = 0; u < kTrdGather; ++u) {
+          if (c0 + u < nall) {
+            sx += gx[u];
+            sy += gy[u];
+          }
+        }
       }
       pq[q] = make_double2(sx, sy);
     }
