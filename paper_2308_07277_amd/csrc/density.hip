@@ -16,6 +16,7 @@
 #include <cstring>
 
 #include "cplx.h"
+#include "fft_kernels.h"
 #include "qm_internal.h"
 
 namespace qm {
@@ -27,12 +28,13 @@ struct DensArgs {
   int32_t pair0[kMaxSlices + 1];    // prefix of band counts over the slices
   int32_t nsl, N3, npair, ngroups;
   const double2* sbuf;              // the plan's stick buffer (float64)
-  const int32_t* stick_pos;
+  const int32_t* stick_at;          // [nk][NX i2][sat_stride] stick index or -1
   const int32_t* col_of_i1;
   const double2* tw_x;
   const double* wf;                 // [npair] w_k f_kn / Omega
   double* part;                     // [ngroups][N3 slot][NX i2][NX i1]
-  int32_t nax_stride;
+  int32_t nax_stride;               // LDS row stride: active columns plus a zero slot
+  int32_t sat_stride;
 };
 
 __device__ __forceinline__ void wave_sync_lds() {
@@ -41,13 +43,16 @@ __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// One workgroup per (z-plane slot p, pair group g).  The plane's active columns go through
-// the two inverse y passes in LDS (positions in the transposed order the passes leave), then
+// One workgroup per (z-plane slot p, pair group g).  For every pair of the group the
+// plane's active columns go through the two inverse y passes in LDS, the first gathering its
+// input straight from the plane's sticks (raw buffer loads; absent sticks read zero), then
 // every row through the inverse x transform: lanes q < R1 of a row take the R2-point DFTs
-// over the row's samples q + R1 n2, the row scratch exchanges them, and lane q ends with the
-// row's values at i1 = q + R2 k1, whose squared moduli it accumulates with weight w_k f_kn.
-// Lane (wave, q, row slot rs) keeps the same rows for every pair, so the sums stay in
-// registers until the partial plane is written.
+// over the row's samples q + R1 n2 (inactive columns read the row's zero slot), the row
+// scratch exchanges them (lane q writes slots q R2 + k2 and reads slots n1 R2 + q: odd lane
+// strides, different LDS banks), and lane q ends with the row's values at i1 = q + R2 k1,
+// whose squared moduli it accumulates with weight w_k f_kn.  Lane (wave, q, row slot rs)
+// keeps the same rows for every pair, so the sums stay in registers until the partial plane
+// is written.
 template <int NX>
 __global__ void __launch_bounds__(256) k_density_xy(DensArgs a) {
   using R = double;
@@ -67,6 +72,7 @@ __global__ void __launch_bounds__(256) k_density_xy(DensArgs a) {
   for (int i = tid; i < NX; i += 256) {
     const double2 w = a.tw_x[i];
     tw[i] = {w.x, w.y};
+    L[i * ns + ns - 1] = {R(0), R(0)};   // the zero slot of every row (no pass writes it)
   }
   R acc[NRND][R1];
 #pragma unroll
@@ -74,42 +80,59 @@ __global__ void __launch_bounds__(256) k_density_xy(DensArgs a) {
 #pragma unroll
     for (int k1 = 0; k1 < R1; ++k1) acc[r][k1] = R(0);
   int kprev = -1;
+  int cr[R2];
+  cplx<R> tq[R2];
   for (int kb = g; kb < a.npair; kb += a.ngroups) {
     int si = 0;
     while (si < a.nsl - 1 && kb >= a.pair0[si + 1]) ++si;
     const int k = a.slk[si], band = kb - a.pair0[si];
     const KInfo ki = a.kinfo[k];
     const int nax = ki.nax;
-    __syncthreads();   // the previous pair's reads of L and col are done
-    if (k != kprev)
+    __syncthreads();   // the previous pair's reads of L and col are done; tw is written
+    if (k != kprev) {
       for (int i = tid; i < NX; i += 256) col[i] = a.col_of_i1[int64_t(k) * NX + i];
-    kprev = k;
-    for (int i = tid; i < NX * ns; i += 256) L[i] = {R(0), R(0)};
-    __syncthreads();
-    const double2* plane = a.sbuf + ki.sbuf_off + (int64_t(band) * N3 + p) * ki.nstick;
-    const int32_t* spos = a.stick_pos + ki.stick_off;
-    for (int s = tid; s < ki.nstick; s += 256) {
-      const int ps = spos[s];
-      const double2 v = plane[s];
-      L[(ps & 0xffff) * ns + (ps >> 16)] = {v.x, v.y};
+      __syncthreads();
+      // per-lane constants of every row: the slots of the samples i1 = q + R1 j (the zero
+      // slot for inactive columns) and the twiddles w^{q j} (exponents below NX)
+#pragma unroll
+      for (int j = 0; j < R2; ++j) {
+        const int c = col[min(q, R1 - 1) + R1 * j];
+        cr[j] = c >= 0 ? c : ns - 1;
+        tq[j] = tw[min(q * j, NX - 1)];
+      }
     }
-    __syncthreads();
-    // inverse y, pass 1 (R2-point, stride R1)
-    for (int w = tid; w < nax * R1; w += 256) {
-      const int ia = w % nax, n1 = w / nax;
+    kprev = k;
+    const double2* plane = a.sbuf + ki.sbuf_off + (int64_t(band) * N3 + p) * ki.nstick;
+    const __amdgpu_buffer_rsrc_t prs = stick_rsrc<R>(reinterpret_cast<const cplx<R>*>(plane), ki.nstick);
+    const int32_t* sat = a.stick_at + int64_t(k) * NX * a.sat_stride;
+    const int sts = a.sat_stride;
+    // y-pass items w = ia + nax j, walked without a division per item (256 = dj nax + dia)
+    const int ia0 = tid % nax, j0 = tid / nax, dj = 256 / nax, dia = 256 - dj * nax;
+    // inverse y, pass 1 (R2-point, stride R1), input gathered from the sticks
+    for (int w = tid, ia = ia0, n1 = j0; w < nax * R1; w += 256, ia += dia, n1 += dj) {
+      if (ia >= nax) {
+        ia -= nax;
+        ++n1;
+      }
+      int sx[R2];
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2) sx[n2] = sat[(n1 + R1 * n2) * sts + ia];
       cplx<R> x[R2];
 #pragma unroll
-      for (int n2 = 0; n2 < R2; ++n2) x[n2] = L[(n1 + R1 * n2) * ns + ia];
+      for (int n2 = 0; n2 < R2; ++n2) x[n2] = stick_load(prs, sx[n2], R(0));
       Dft<R2, +1, R>::run(x);
 #pragma unroll
-      for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tw[(n1 * k2) % NX]);
+      for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tw[n1 * k2]);   // n1 k2 < NX
 #pragma unroll
       for (int k2 = 0; k2 < R2; ++k2) L[(n1 + R1 * k2) * ns + ia] = x[k2];
     }
     __syncthreads();
     // pass 2 (R1-point on contiguous runs): y frequency k2 + R2 k1 at position k1 + R1 k2
-    for (int w = tid; w < nax * R2; w += 256) {
-      const int ia = w % nax, k2 = w / nax;
+    for (int w = tid, ia = ia0, k2 = j0; w < nax * R2; w += 256, ia += dia, k2 += dj) {
+      if (ia >= nax) {
+        ia -= nax;
+        ++k2;
+      }
       cplx<R> y[R1];
 #pragma unroll
       for (int n1 = 0; n1 < R1; ++n1) y[n1] = L[(n1 + R1 * k2) * ns + ia];
@@ -127,21 +150,18 @@ __global__ void __launch_bounds__(256) k_density_xy(DensArgs a) {
       if (act && q < R1) {
         cplx<R> x[R2];
 #pragma unroll
-        for (int n2 = 0; n2 < R2; ++n2) {
-          const int c = col[q + R1 * n2];
-          x[n2] = c >= 0 ? L[lrow * ns + c] : cplx<R>{R(0), R(0)};
-        }
+        for (int n2 = 0; n2 < R2; ++n2) x[n2] = L[lrow * ns + cr[n2]];
         Dft<R2, +1, R>::run(x);
 #pragma unroll
-        for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tw[(q * k2) % NX]);
+        for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tq[k2]);
 #pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) Xr[q + R1 * k2] = x[k2];
+        for (int k2 = 0; k2 < R2; ++k2) Xr[q * R2 + k2] = x[k2];
       }
       wave_sync_lds();
       if (act) {
         cplx<R> y[R1];
 #pragma unroll
-        for (int n1 = 0; n1 < R1; ++n1) y[n1] = Xr[n1 + R1 * q];
+        for (int n1 = 0; n1 < R1; ++n1) y[n1] = Xr[n1 * R2 + q];
         Dft<R1, +1, R>::run(y);   // y[k1]: the row at i1 = q + R2 k1
 #pragma unroll
         for (int k1 = 0; k1 < R1; ++k1) acc[rnd][k1] += wf * (y[k1].re * y[k1].re + y[k1].im * y[k1].im);
@@ -257,12 +277,13 @@ static void density(qm_hpsi_plan* p, int k, const void* psi, int nbnd, const dou
   grow(p->rho_part, have, int64_t(a.ngroups) * nr);
   p->rho_part_bytes = have * int64_t(sizeof(double));
   a.sbuf = reinterpret_cast<const double2*>(p->sbuf);
-  a.stick_pos = p->g.stick_pos;
+  a.stick_at = p->g.stick_at;
+  a.sat_stride = p->nax_max;
   a.col_of_i1 = p->g.col_of_i1;
   a.tw_x = p->tw_x;
   a.wf = p->dens_wf;
   a.part = p->rho_part;
-  a.nax_stride = p->nax_max | 1;
+  a.nax_stride = (p->nax_max + 1) | 1;
   launch_zinv_f64(p, sl, psi, s);
 #define QM_DXY(n)                       \
   case n:                               \
