@@ -53,7 +53,6 @@ size_t xy_lds_bytes(int n, int ns, size_t real_bytes, bool own) {
   const int r2 = fft_split_r2(n);
   size_t cplx_elems = size_t(n) * ns + n;            // plane + twiddles
   if (!own) cplx_elems += size_t(4 * (64 / r2)) * (n + 1);   // row scratch
-  if (own && real_bytes == 8) cplx_elems += size_t(r2) * r2;  // [j][q] twiddle table
   return 2 * real_bytes * cplx_elems + sizeof(int) * n;
 }
 

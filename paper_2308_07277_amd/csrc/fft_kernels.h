@@ -232,7 +232,8 @@ constexpr int xy_min_waves() { return OWN && sizeof(R) == 8 && NX <= 80 ? 3 : 1;
 // OWN = false: the x-row exchanges go through a row scratch of NX + 1 slots per row in flight
 // (4 R_W rows).  OWN = true: they go through the rows' own ns slots in two rounds each, which
 // leaves the plane as the only large LDS buffer (more workgroups per CU, more LDS operations);
-// float64 then reads its x-row twiddles from a [j][q] table instead of holding them in VGPRs.
+// float64 then forms its x-row twiddles w^{q j} from w^q at each use instead of holding them
+// in VGPRs.
 template <typename R, int NX, bool OWN>
 __global__ void __launch_bounds__(256, (xy_min_waves<R, NX, OWN>())) k_xy(LocalArgs a) {
   constexpr int R1 = Split<NX>::R1, R2 = Split<NX>::R2;
@@ -243,8 +244,7 @@ __global__ void __launch_bounds__(256, (xy_min_waves<R, NX, OWN>())) k_xy(LocalA
   cplx<R>* L = reinterpret_cast<cplx<R>*>(smem_raw);  // [NX positions][ns]
   cplx<R>* X = L + NX * ns;                              // [4 R_W rows][NX + 1] (OWN = false)
   cplx<R>* tw = X + (OWN ? 0 : 4 * RW * NXP);            // [NX]
-  cplx<R>* twr = tw + NX;                                // [R2 j][R2 q] = w^{q j} (!kTwReg)
-  int* col = reinterpret_cast<int*>(twr + (kTwReg ? 0 : R2 * R2));  // [NX]
+  int* col = reinterpret_cast<int*>(tw + NX);            // [NX]
   const int tid = threadIdx.x;
   const int N3 = a.N3;
   // (k, band) pair and z-slot; each XCD keeps a fixed eighth of the slots when N3 % 8 == 0
@@ -274,13 +274,6 @@ __global__ void __launch_bounds__(256, (xy_min_waves<R, NX, OWN>())) k_xy(LocalA
     tw[i] = {R(w.x), R(w.y)};
     col[i] = a.col_of_i1[int64_t(k) * NX + i];
     L[i * ns + ns - 1] = {R(0), R(0)};   // the zero slot of every row
-  }
-  if (!kTwReg) {
-    for (int i = tid; i < R2 * R2; i += 256) {
-      const int j = i / R2, qq = i - j * R2;
-      const double2 w = a.tw_x[min(qq * j, NX - 1)];
-      twr[i] = {R(w.x), R(w.y)};
-    }
   }
   __syncthreads();
   // y-pass items w = ia + nax j: thread tid starts at (tid % nax, tid / nax) and steps by
@@ -344,9 +337,8 @@ __global__ void __launch_bounds__(256, (xy_min_waves<R, NX, OWN>())) k_xy(LocalA
     // twiddles w^{q j}, used for j < R2 by lanes q < R1 (inverse pass 1) and for j < R1 by
     // lanes q < R2 (forward pass): those exponents stay below NX, so no reduction modulo NX
     // is needed; the other (unused) combinations are clamped into the table
-    // (float64 reads the twiddles from the [j][q] LDS table at each use instead, consecutive
-    // lanes at consecutive entries: held in registers they would cost 4 R2 VGPRs and a wave
-    // slot per SIMD)
+    // (float64 forms them at each use instead: held in registers they would cost 4 R2 VGPRs
+    // and a wave slot per SIMD)
     int cr[R2];  // active columns are below nax < ns - 1, so cr[j] != ns - 1 marks them
     cplx<R> tq[kTwReg ? R2 : 1];
 #pragma unroll
@@ -355,7 +347,15 @@ __global__ void __launch_bounds__(256, (xy_min_waves<R, NX, OWN>())) k_xy(LocalA
       cr[j] = c >= 0 ? c : ns - 1;
       if (kTwReg) tq[j] = tw[min(q * j, NX - 1)];
     }
-    auto twq = [&](int j) { return kTwReg ? tq[kTwReg ? j : 0] : twr[j * R2 + q]; };
+    // without the register table: w^{q j} = w^{q (j - 1)} w^q, one product per use (rounding
+    // grows like j, below 10 ulp for j < R2); the empty asm keeps the compiler from hoisting
+    // the powers out of the row loop, which would hold them in VGPRs after all
+    const cplx<R> w1 = tw[min(q, NX - 1)];
+    auto base = [&]() {
+      cplx<R> b = w1;
+      asm volatile("" : "+v"(b.re), "+v"(b.im));
+      return b;
+    };
     for (int r0 = wave * RW; r0 < NX; r0 += 4 * RW) {
       const int lr = r0 + rs;
       const bool act = rs < RW && lr < NX;
@@ -375,8 +375,18 @@ __global__ void __launch_bounds__(256, (xy_min_waves<R, NX, OWN>())) k_xy(LocalA
 #pragma unroll
         for (int n2 = 0; n2 < R2; ++n2) x[n2] = Lr[cr[n2]];
         Dft<R2, +1, R>::run(x);
+        if constexpr (kTwReg) {
 #pragma unroll
-        for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], twq(k2));
+          for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tq[k2]);
+        } else {
+          const cplx<R> b = base();
+          cplx<R> t = b;
+#pragma unroll
+          for (int k2 = 1; k2 < R2; ++k2) {
+            x[k2] = cmul(x[k2], t);
+            if (k2 + 1 < R2) t = cmul(t, b);
+          }
+        }
       }
       wave_lds_sync();
       // inverse exchange; lane q collects k2 = q
@@ -403,10 +413,17 @@ __global__ void __launch_bounds__(256, (xy_min_waves<R, NX, OWN>())) k_xy(LocalA
 #pragma unroll
         for (int k1 = 0; k1 < R1; ++k1) y[k1] = cscale(y[k1], vr[k1]);
         Dft<R1, -1, R>::run(y);  // forward, factorisation (R2, R1): first pass over n = k1
+        if constexpr (kTwReg) {
 #pragma unroll
-        for (int k2 = 1; k2 < R1; ++k2) {
-          const cplx<R> t = twq(k2);
-          y[k2] = cmul(y[k2], cplx<R>{t.re, -t.im});
+          for (int k2 = 1; k2 < R1; ++k2) y[k2] = cmul(y[k2], cplx<R>{tq[k2].re, -tq[k2].im});
+        } else {
+          const cplx<R> b = base();
+          cplx<R> t = {b.re, -b.im};
+#pragma unroll
+          for (int k2 = 1; k2 < R1; ++k2) {
+            y[k2] = cmul(y[k2], t);
+            if (k2 + 1 < R1) t = cmul(t, cplx<R>{b.re, -b.im});
+          }
         }
       }
       wave_lds_sync();
