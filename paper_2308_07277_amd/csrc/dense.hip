@@ -516,10 +516,52 @@ __global__ void __launch_bounds__(256) k_trd_step(DJobs jobs, int j, double2* __
   double* e = ee + int64_t(k) * mb;
   double2* tk = tau + int64_t(k) * mb;
   const double2 tj_ = tk[j];
-  // column j+1 as the previous launch left it, with the update of step j-1 applied; every
-  // independent load is issued before the slot reads
+  // (A v)_r for row r of block ib: row sums of tiles (ib, 0..ib), then column sums of tiles
+  // (ib..nt-1, ib), always in this order.  The slots are read with 16-byte loads under the
+  // same cache policy as the agent-scope atomic loads (sc1: served by the coherent level, not
+  // by this CU's cache), kTrdGather slots of every row of the thread in flight at once, so the
+  // whole gather costs about (nt + 1) / kTrdGather round trips to memory.
+  constexpr int kTrdGather = 4;
+  constexpr int kCohLoad = 16;   // cache-policy bits of a buffer load: sc1
+  const __amdgpu_buffer_rsrc_t prs = __builtin_amdgcn_make_buffer_rsrc(
+      PS, (short)0, tw.ptiles * 2 * T * int(sizeof(double2)), 0x00020000);
+  const int nall = nt + 1;
+  int ibq[kTrdRows], iq[kTrdRows];
+  double2 pq[kTrdRows];
+#pragma unroll
+  for (int q = 0; q < kTrdRows; ++q) {
+    const int r = j1 + tid + q * 256;
+    ibq[q] = r / T - b0;
+    iq[q] = r - (b0 + ibq[q]) * T;
+    pq[q] = z;
+  }
+  for (int c0 = 0; c0 < nall; c0 += kTrdGather) {
+    double2 g[kTrdRows][kTrdGather];
+#pragma unroll
+    for (int q = 0; q < kTrdRows; ++q) {
+      if (j1 + q * 256 >= m) break;   // no row of this q in the job (uniform)
+      const int ib = ibq[q], nrow = ib + 1;
+#pragma unroll
+      for (int u = 0; u < kTrdGather; ++u) {
+        const int c = min(c0 + u, nall - 1);
+        const int slot = c < nrow ? (ib * (ib + 1) / 2 + c) * 2
+                                  : ((ib + c - nrow) * (ib + c - nrow + 1) / 2 + ib) * 2 + 1;
+        // rows past m read a clamped slot; their sums are discarded below
+        const int off = (min(slot, tw.ptiles * 2 - 1) * T + iq[q]) * int(sizeof(double2));
+        g[q][u] = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(prs, off, 0, kCohLoad));
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kTrdRows; ++q) {
+      if (j1 + q * 256 >= m) break;
+#pragma unroll
+      for (int u = 0; u < kTrdGather; ++u)
+        if (c0 + u < nall) pq[q] = cadd2(pq[q], g[q][u]);
+    }
+  }
+  // column j+1 as the previous launch left it, with the update of step j-1 applied
   const double2 wpj1c = keep(cconj(W[j1]), pend), vpj1c = keep(cconj(vp[j1]), pend);
-  double2 pq[kTrdRows], vq[kTrdRows], col[kTrdRows], vpq[kTrdRows], wpq[kTrdRows];
+  double2 vq[kTrdRows], col[kTrdRows], vpq[kTrdRows], wpq[kTrdRows];
 #pragma unroll
   for (int q = 0; q < kTrdRows; ++q) {
     const int rc = min(j1 + tid + q * 256, m - 1);
@@ -528,44 +570,11 @@ __global__ void __launch_bounds__(256) k_trd_step(DJobs jobs, int j, double2* __
     vpq[q] = vp[rc];
     wpq[q] = W[rc];
   }
-  // (A v)_r for row r of block ib: row sums of tiles (ib, 0..ib), then column sums of tiles
-  // (ib..nt-1, ib), always in this order.  The nt + 1 slots of a row are read in groups of
-  // kTrdGather, every load of a group issued before the group is added, so a row costs
-  // about (nt + 1) / kTrdGather round trips to memory instead of nt + 1.
-  constexpr int kTrdGather = 8;
-#pragma unroll
-  for (int q = 0; q < kTrdRows; ++q) {
-    const int r = j1 + tid + q * 256;
-    pq[q] = z;
-    if (r < m) {
-      const int ib = r / T - b0, i = r - (b0 + ib) * T;
-      const int nrow = ib + 1, nall = nt + 1;
-      double sx = 0.0, sy = 0.0;
-      for (int c0 = 0; c0 < nall; c0 += kTrdGather) {
-        double gx[kTrdGather], gy[kTrdGather];
-#pragma unroll
-        for (int u = 0; u < kTrdGather; ++u) {
-          const int c = min(c0 + u, nall - 1);
-          const int64_t o = c < nrow ? ((int64_t(ib * (ib + 1) / 2 + c) * 2) * T + i) * 2
-                                     : ((int64_t((ib + c - nrow) * (ib + c - nrow + 1) / 2 + ib) * 2 + 1) * T + i) * 2;
-          gx[u] = __hip_atomic_load(&PS[o], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          gy[u] = __hip_atomic_load(&PS[o + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-#pragma unroll
-        for (int u = 0; u < kTrdGather; ++u) {
-          if (c0 + u < nall) {
-            sx += gx[u];
-            sy += gy[u];
-          }
-        }
-      }
-      pq[q] = make_double2(sx, sy);
-    }
-  }
   double sr = 0.0, si = 0.0;
 #pragma unroll
   for (int q = 0; q < kTrdRows; ++q) {
     const bool ok = j1 + tid + q * 256 < m;
+    pq[q] = keep(pq[q], ok);
     col[q] = keep(col[q], ok);
     vq[q] = keep(vq[q], ok);
     vpq[q] = keep(vpq[q], ok && pend);
