@@ -183,9 +183,11 @@ qm_status qm_hpsi_plan_set_precision(qm_hpsi_plan *plan, qm_prec prec, void *str
 qm_status qm_hpsi_plan_set_graphs(qm_hpsi_plan *plan, int32_t enable);
 
 /* Autotune for nbnd bands, timing the candidates with HIP events on stream: the split-K
- * count of the projector GEMM in every precision, and the xy-plane FFT kernel (two-pass or
- * lane-group, where the grid has both) of the float64 and float32 local parts.  The
- * choices are kept in the plan.  If the environment variable QM_AUTOTUNE_CACHE names a
+ * count of the projector GEMM in every precision, the xy-plane FFT kernel (two-pass or
+ * lane-group, where the grid has both) of the float64 and float32 local parts, and, per
+ * precision, whether qm_apply_h runs the projection beta^H psi and D on a side stream of
+ * the plan, concurrently with the local part (the default before tuning; the environment
+ * variable QM_OVERLAP=0 or 1 fixes it at plan creation).  The choices are kept in the plan.  If the environment variable QM_AUTOTUNE_CACHE names a
  * file, choices are read from and written to it (one JSON object keyed by problem shape).
  * Synchronous. */
 qm_status qm_hpsi_plan_autotune(qm_hpsi_plan *plan, int32_t nbnd, void *stream);

@@ -105,6 +105,23 @@ void apply_h_slices(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* 
     for (const KSlice& x : chunk)
       if (x.nb > 0) nz.push_back(x);
     if (nz.empty()) continue;
+    // the projection on the side stream, concurrent with the local part; calls with stage
+    // events, their own split-K scratch (Davidson lanes) or caller-given working memory stay
+    // on one stream.  The side stream first waits for everything before on s (the previous
+    // call's expansion still reads Q), and s waits for it before the expansion.
+    const int lp = prec == QM_PREC_FP64 ? 0 : (prec == QM_PREC_FP32 ? 1 : 2);
+    const int ovl = p->overlap_forced >= 0 ? p->overlap_forced : p->overlap_tuned[lp];
+    if (ovl && p->nproj > 0 && p->side_stream && !ev && !ps && !wk) {
+      convert_beta(p, prec, s);   // (a no-op unless the precision changed)
+      QM_HIP(hipEventRecord(p->ev_fork, s));
+      QM_HIP(hipStreamWaitEvent(p->side_stream, p->ev_fork, 0));
+      launch_nonlocal(p, nz, psi, hpsi, p->side_stream, prec, nullptr, nullptr, nullptr, kNlProject);
+      QM_HIP(hipEventRecord(p->ev_join, p->side_stream));
+      launch_hpsi_local(p, nz, psi, hpsi, s, prec != QM_PREC_FP64, nullptr, nullptr);
+      QM_HIP(hipStreamWaitEvent(s, p->ev_join, 0));
+      launch_nonlocal(p, nz, psi, hpsi, s, prec, nullptr, nullptr, nullptr, kNlExpand);
+      continue;
+    }
     launch_hpsi_local(p, nz, psi, hpsi, s, prec != QM_PREC_FP64, ev, wk);
     launch_nonlocal(p, nz, psi, hpsi, s, prec, ev, ps, wk);
   }

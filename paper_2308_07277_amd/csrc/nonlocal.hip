@@ -30,7 +30,7 @@ __global__ void k_apply_d(const double2* __restrict__ P, double2* __restrict__ Q
 
 void launch_nonlocal_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi,
                        void* hpsi, hipStream_t s, StageEvents* ev, int lp, const ProjScratch* ps,
-                       const HpsiWork* wk) {
+                       const HpsiWork* wk, int parts) {
   if (p->nproj == 0) return;
   const int np = p->nproj;
   double2* P = wk ? wk->P : reinterpret_cast<double2*>(p->proj_q);
@@ -50,6 +50,10 @@ void launch_nonlocal_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const voi
     cn.push_back(GemmCN{bk, pk, P + off, np, x.nb, ki.npw, ki.npw, ki.npw, x.nb});
     ex.push_back(GemmEX{Q + off, bk, hk, x.nb, ki.npw, np, x.nb, ki.npw, ki.npw});
   }
+  if (parts == kNlExpand) {
+    zgemm_ex_batched(ex, 1.0, 1.0, s, lp);
+    return;
+  }
   void* part = wk ? wk->part : (ps ? ps->part : p->proj_part);
   const int64_t part_bytes = wk ? wk->part_bytes : (ps ? ps->bytes : p->proj_part_bytes);
   zgemm_cn_batched(cn, 1.0, 0.0, part, part_bytes, s, ev, 3, lp, p->tuned_splits[lp]);
@@ -63,19 +67,20 @@ void launch_nonlocal_t(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const voi
     QM_HIP(hipGetLastError());
   }
   if (ev) ev->mark(5);
+  if (parts == kNlProject) return;
   zgemm_ex_batched(ex, 1.0, 1.0, s, lp);
   if (ev) ev->mark(6);
 }
 
 void launch_nonlocal(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
                      hipStream_t s, qm_prec prec, StageEvents* ev, const ProjScratch* ps,
-                     const HpsiWork* wk) {
+                     const HpsiWork* wk, int parts) {
   const int lp = prec == QM_PREC_FP64 ? 0 : (prec == QM_PREC_FP32 ? 1 : 2);
   if (lp != 0 && p->beta_lp_kind != lp) {
     QM_REQUIRE(!wk, QM_E_STATE, "the reduced-precision copy of beta is not built");
     convert_beta(p, prec, s);
   }
-  launch_nonlocal_t(p, sl, psi, hpsi, s, ev, lp, ps, wk);
+  launch_nonlocal_t(p, sl, psi, hpsi, s, ev, lp, ps, wk, parts);
 }
 
 // low-precision copy of beta for the FP32 (c64) or MIXED (bf16 pairs) projector GEMMs
@@ -241,6 +246,76 @@ static void autotune_xy(qm_hpsi_plan* p, int nbnd, hipStream_t s) {
   if (dirty) save_cache(path, cache);
 }
 
+// time whole H applications of every k at nbnd bands with the projection on the side stream
+// and with everything on the caller's stream, per precision, launched as qm_apply_h launches
+// them (graph replays when the plan uses graphs); keep the faster
+static void autotune_overlap(qm_hpsi_plan* p, int nbnd, hipStream_t s) {
+  if (p->overlap_forced >= 0 || p->nproj == 0) return;
+  const qm_prec saved = p->prec;
+  auto drop_graphs = [&]() {
+    for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
+    p->graphs.clear();
+  };
+  const char* path = std::getenv("QM_AUTOTUNE_CACHE");
+  std::map<std::string, int> cache = load_cache(path);
+  const std::vector<KSlice> sl = contiguous_slices(p, 0, p->nk, nbnd);
+  void* psi = nullptr;
+  void* out = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  bool dirty = false;
+  for (int lp = 0; lp < 3; ++lp) {
+    std::ostringstream key;
+    key << "ovl/" << lp << "/" << p->N1 << "x" << p->N2 << "x" << p->N3 << "/" << p->nproj << "x"
+        << nbnd << "/" << p->nk << "/" << p->npw_total;
+    auto it = cache.find(key.str());
+    if (it != cache.end()) {
+      p->overlap_tuned[lp] = it->second;
+      continue;
+    }
+    if (!psi) {
+      const size_t bytes = size_t(nbnd) * size_t(p->npw_total) * 16;
+      QM_HIP(hipMalloc(&psi, bytes));
+      QM_HIP(hipMalloc(&out, bytes));
+      QM_HIP(hipMemsetAsync(psi, 0, bytes, s));
+      QM_HIP(hipEventCreate(&e0));
+      QM_HIP(hipEventCreate(&e1));
+    }
+    const qm_prec prec = lp == 0 ? QM_PREC_FP64 : (lp == 1 ? QM_PREC_FP32 : QM_PREC_MIXED);
+    p->prec = prec;
+    auto run = [&]() {
+      if (p->use_graphs && p->nk <= kMaxSlices) apply_graph(p, -1, psi, out, nbnd, s);
+      else apply_h_slices(p, sl, psi, out, s, prec);
+    };
+    int best = 1;
+    double bms = 1e30;
+    for (int v = 1; v >= 0; --v) {
+      p->overlap_tuned[lp] = v;
+      drop_graphs();
+      run();   // warm (and capture)
+      QM_HIP(hipEventRecord(e0, s));
+      for (int r = 0; r < 3; ++r) run();
+      QM_HIP(hipEventRecord(e1, s));
+      QM_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      QM_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < bms) {
+        bms = ms;
+        best = v;
+      }
+    }
+    p->overlap_tuned[lp] = best;
+    cache[key.str()] = best;
+    dirty = true;
+  }
+  p->prec = saved;
+  drop_graphs();   // they name the tuning buffers
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (psi) (void)hipFree(psi);
+  if (out) (void)hipFree(out);
+  if (dirty) save_cache(path, cache);
+}
+
 }  // namespace qm
 
 extern "C" qm_status qm_hpsi_plan_autotune(qm_hpsi_plan* plan, int32_t nbnd, void* stream) {
@@ -252,6 +327,7 @@ extern "C" qm_status qm_hpsi_plan_autotune(qm_hpsi_plan* plan, int32_t nbnd, voi
     for (int lp = 0; lp < 3; ++lp)
       qm::autotune_projection(plan, nbnd, reinterpret_cast<hipStream_t>(stream), lp, nullptr);
     qm::autotune_xy(plan, nbnd, reinterpret_cast<hipStream_t>(stream));
+    qm::autotune_overlap(plan, nbnd, reinterpret_cast<hipStream_t>(stream));
     return QM_OK;
   } catch (const qm::Error& e) {
     plan->err = e.what();

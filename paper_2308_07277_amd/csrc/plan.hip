@@ -40,6 +40,9 @@ static void plan_free(qm_hpsi_plan* p) {
   for (auto& g : p->graphs) (void)hipGraphExecDestroy(g.exec);
   p->graphs.clear();
   if (p->capture_stream) (void)hipStreamDestroy(p->capture_stream);
+  if (p->side_stream) (void)hipStreamDestroy(p->side_stream);
+  if (p->ev_fork) (void)hipEventDestroy(p->ev_fork);
+  if (p->ev_join) (void)hipEventDestroy(p->ev_join);
   void* ptrs[] = {p->g.kinfo, p->g.ent_g, p->g.ent_sz, p->g.tile_ptr, p->g.stick_pos,
                   p->g.col_of_i1, p->g.stick_at, p->g.flat, p->g.kin, p->vplan64, p->vplan32, p->beta64, p->beta_lp,
                   p->dmat, p->drange, p->tw_z, p->tw_x, p->sbuf, p->proj_part, p->proj_q};
@@ -73,6 +76,10 @@ static void build_plan(qm_hpsi_plan* p, const double cell[9], const int32_t grid
   if (const char* xm = std::getenv("QM_XY_MODE")) p->xy_forced = std::atoi(xm);
   if (const char* tm = std::getenv("QM_TRIDIAG_MODE")) p->trd_forced = std::atoi(tm);
   if (const char* cm = std::getenv("QM_CHOL_MODE")) p->chol_forced = std::atoi(cm);
+  if (const char* om = std::getenv("QM_OVERLAP")) p->overlap_forced = std::atoi(om) != 0;
+  QM_HIP(hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking));
+  QM_HIP(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+  QM_HIP(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
   std::memcpy(p->cell, cell, sizeof(p->cell));
   // reciprocal rows b_i = 2 pi (A^-1)^T
   const double* a = cell;
@@ -282,6 +289,45 @@ static qm_status fail(qm_hpsi_plan* p, const qm::Error& e) {
   return e.code;
 }
 
+// Replay a captured launch sequence for (k, nbnd, psi, hpsi, prec), capturing it on the
+// plan's own stream the first time (the caller's stream may be the null stream, which cannot
+// be captured).  Graphs hold kernel nodes only.
+void apply_graph(qm_hpsi_plan* p, int k, const void* psi, void* hpsi, int nbnd, hipStream_t s) {
+  const int k0 = k < 0 ? 0 : k, k1 = k < 0 ? p->nk : k + 1;
+  for (auto& g : p->graphs)
+    if (g.k == k && g.nbnd == nbnd && g.prec == int(p->prec) && g.psi == psi && g.hpsi == hpsi) {
+      g.last_use = ++p->graph_clock;
+      QM_HIP(hipGraphLaunch(g.exec, s));
+      return;
+    }
+  if (!p->capture_stream) QM_HIP(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
+  convert_beta(p, p->prec, s);                     // any one-time conversion happens eagerly
+  QM_HIP(hipStreamSynchronize(s));
+  hipGraph_t graph = nullptr;
+  QM_HIP(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
+  try {
+    apply_h_slices(p, contiguous_slices(p, k0, k1, nbnd), psi, hpsi, p->capture_stream, p->prec);
+  } catch (...) {
+    (void)hipStreamEndCapture(p->capture_stream, &graph);
+    if (graph) (void)hipGraphDestroy(graph);
+    throw;
+  }
+  QM_HIP(hipStreamEndCapture(p->capture_stream, &graph));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  QM_HIP(ie);
+  if (p->graphs.size() >= 8) {   // evict the least recently used entry
+    size_t lru = 0;
+    for (size_t i = 1; i < p->graphs.size(); ++i)
+      if (p->graphs[i].last_use < p->graphs[lru].last_use) lru = i;
+    (void)hipGraphExecDestroy(p->graphs[lru].exec);
+    p->graphs.erase(p->graphs.begin() + lru);
+  }
+  p->graphs.push_back({k, nbnd, int(p->prec), psi, hpsi, exec, ++p->graph_clock});
+  QM_HIP(hipGraphLaunch(exec, s));
+}
+
 }  // namespace qm
 
 using namespace qm;
@@ -349,45 +395,6 @@ qm_status qm_hpsi_plan_set_precision(qm_hpsi_plan* plan, qm_prec prec, void* str
     convert_beta(plan, prec, reinterpret_cast<hipStream_t>(stream));
     QM_HIP(hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)));
   })
-}
-
-// Replay a captured launch sequence for (k, nbnd, psi, hpsi, prec), capturing it on the
-// plan's own stream the first time (the caller's stream may be the null stream, which cannot
-// be captured).  Graphs hold kernel nodes only.
-static void apply_graph(qm_hpsi_plan* p, int k, const void* psi, void* hpsi, int nbnd, hipStream_t s) {
-  const int k0 = k < 0 ? 0 : k, k1 = k < 0 ? p->nk : k + 1;
-  for (auto& g : p->graphs)
-    if (g.k == k && g.nbnd == nbnd && g.prec == int(p->prec) && g.psi == psi && g.hpsi == hpsi) {
-      g.last_use = ++p->graph_clock;
-      QM_HIP(hipGraphLaunch(g.exec, s));
-      return;
-    }
-  if (!p->capture_stream) QM_HIP(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
-  convert_beta(p, p->prec, s);                     // any one-time conversion happens eagerly
-  QM_HIP(hipStreamSynchronize(s));
-  hipGraph_t graph = nullptr;
-  QM_HIP(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));
-  try {
-    apply_h_slices(p, contiguous_slices(p, k0, k1, nbnd), psi, hpsi, p->capture_stream, p->prec);
-  } catch (...) {
-    (void)hipStreamEndCapture(p->capture_stream, &graph);
-    if (graph) (void)hipGraphDestroy(graph);
-    throw;
-  }
-  QM_HIP(hipStreamEndCapture(p->capture_stream, &graph));
-  hipGraphExec_t exec = nullptr;
-  const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-  (void)hipGraphDestroy(graph);
-  QM_HIP(ie);
-  if (p->graphs.size() >= 8) {   // evict the least recently used entry
-    size_t lru = 0;
-    for (size_t i = 1; i < p->graphs.size(); ++i)
-      if (p->graphs[i].last_use < p->graphs[lru].last_use) lru = i;
-    (void)hipGraphExecDestroy(p->graphs[lru].exec);
-    p->graphs.erase(p->graphs.begin() + lru);
-  }
-  p->graphs.push_back({k, nbnd, int(p->prec), psi, hpsi, exec, ++p->graph_clock});
-  QM_HIP(hipGraphLaunch(exec, s));
 }
 
 qm_status qm_apply_h(qm_hpsi_plan* plan, int32_t k, const void* psi, void* hpsi, int32_t nbnd,

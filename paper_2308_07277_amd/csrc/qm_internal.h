@@ -135,6 +135,16 @@ struct qm_hpsi_plan {
   uint64_t graph_clock = 0;
   hipStream_t capture_stream = nullptr;
   int32_t use_graphs = 1;
+  // The projection beta^H psi and D of an H application run on a side stream while the
+  // local part runs on the caller's stream (fork and join through two events), so the
+  // MFMA-bound GEMM shares the chip with the VALU-bound FFT kernels; the expansion then
+  // runs on the caller's stream.  Per precision (0 float64, 1 float32, 2 mixed) the
+  // autotuner keeps it or turns it off, whichever is faster; overlap_forced (environment
+  // QM_OVERLAP = 0 or 1) overrides that.
+  hipStream_t side_stream = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  int32_t overlap_tuned[3] = {1, 1, 1};
+  int32_t overlap_forced = -1;
   // xy-plane kernel per real type of the local part (0 float64, 1 float32): 1 the two-pass
   // kernel with a row scratch, 2 the lane-group kernel (grids 20, 40, 72), 3 the two-pass
   // kernel with the x-row exchanges in the rows' own slots, 0 the built-in choice; set by the
@@ -183,15 +193,22 @@ struct ProjScratch {
   void* part = nullptr;
   int64_t bytes = 0;
 };
+// parts: kNlAll the whole non-local term, kNlProject P = beta^H psi and Q = D P only,
+// kNlExpand H psi += beta Q only (Q from an earlier kNlProject call)
+enum { kNlAll = 0, kNlProject = 1, kNlExpand = 2 };
 void launch_nonlocal(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
                      hipStream_t s, qm_prec prec, StageEvents* ev = nullptr,
-                     const ProjScratch* ps = nullptr, const HpsiWork* wk = nullptr);
+                     const ProjScratch* ps = nullptr, const HpsiWork* wk = nullptr,
+                     int parts = kNlAll);
 // H applied to every slice (local + non-local), in chunks of kMaxSlices.  At most one slice
 // per k-point per call (stick buffer, P and Q are addressed per k).
 void apply_h_slices(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
                     hipStream_t s, qm_prec prec, StageEvents* ev = nullptr,
                     const ProjScratch* ps = nullptr, const HpsiWork* wk = nullptr);
 std::vector<KSlice> contiguous_slices(const qm_hpsi_plan* p, int k0, int k1, int nbnd);
+// qm_apply_h's graph path: replay (capturing on first use) the launch sequence of k (-1: all)
+// at nbnd bands for these buffers in the plan's precision
+void apply_graph(qm_hpsi_plan* p, int k, const void* psi, void* hpsi, int nbnd, hipStream_t s);
 int xy_group_lanes(int nx);                       // lanes per line of the lane-group kernel, 0: none
 // 1 two-pass with row scratch, 2 lane-group, 3 two-pass with the exchanges in the rows' slots
 int xy_pick(const qm_hpsi_plan* p, int real_type);

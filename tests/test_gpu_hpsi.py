@@ -183,6 +183,36 @@ def test_graph_replays_match_eager():
         assert torch.equal(hg, he), rep
 
 
+@pytest.mark.parametrize("prec", [0, 2])
+def test_side_stream_projection_matches_one_stream(prec, monkeypatch):
+    """The projection on the plan's side stream (concurrent with the local part) gives the
+    same bits as everything on one stream, eagerly and in graph replays, with new data and
+    eager work between calls, and with back-to-back calls (the second call's projection must
+    wait for the first call's expansion)."""
+    import torch
+    import paper_2308_07277_amd as qm
+    w = workload.make_workload("c2")
+    monkeypatch.setenv("QM_OVERLAP", "1")
+    plan_o, a = make_plan(w, w.nbnd, prec=prec)
+    monkeypatch.setenv("QM_OVERLAP", "0")
+    plan_s, _ = make_plan(w, w.nbnd, arrays=a, prec=prec)
+    psi = torch.empty(int(w.nbnd * w.npw.sum()), dtype=torch.complex128, device="cuda")
+    ho = torch.empty_like(psi)
+    hs = torch.empty_like(psi)
+    for graphs in (0, 1):
+        qm.qm_hpsi_plan_set_graphs(plan_o, graphs)
+        for rep in range(3):
+            flat, _ = psi_block(w, w.nbnd, purpose=20 + rep)
+            psi.copy_(torch.from_numpy(flat))
+            for _ in range(2):
+                qm.qm_apply_h(plan_o, -1, psi, ho, w.nbnd)
+            torch.cuda.synchronize()
+            _ = (psi.abs() ** 2).sum().item()
+            qm.qm_apply_h(plan_s, -1, psi, hs, w.nbnd)
+            torch.cuda.synchronize()
+            assert torch.equal(ho, hs), (graphs, rep)
+
+
 def test_autotune_keeps_results(tmp_path, monkeypatch):
     """Autotuning changes only the split-K schedule and the xy-plane kernel: results stay
     within float64 rounding and a second plan reads the choices back from the cache file."""
