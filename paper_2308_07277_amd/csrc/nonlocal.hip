@@ -286,8 +286,7 @@ static void autotune_overlap(qm_hpsi_plan* p, int nbnd, hipStream_t s) {
       if (p->use_graphs && p->nk <= kMaxSlices) apply_graph(p, -1, psi, out, nbnd, s);
       else apply_h_slices(p, sl, psi, out, s, prec);
     };
-    int best = 1;
-    double bms = 1e30;
+    float ms[2] = {0.f, 0.f};
     for (int v = 1; v >= 0; --v) {
       p->overlap_tuned[lp] = v;
       drop_graphs();
@@ -296,13 +295,11 @@ static void autotune_overlap(qm_hpsi_plan* p, int nbnd, hipStream_t s) {
       for (int r = 0; r < 3; ++r) run();
       QM_HIP(hipEventRecord(e1, s));
       QM_HIP(hipEventSynchronize(e1));
-      float ms = 0.f;
-      QM_HIP(hipEventElapsedTime(&ms, e0, e1));
-      if (ms < bms) {
-        bms = ms;
-        best = v;
-      }
+      QM_HIP(hipEventElapsedTime(&ms[v], e0, e1));
     }
+    // the side stream only where it gains at least 1% (one stream keeps each kernel's
+    // duration its own)
+    const int best = ms[1] < 0.99f * ms[0] ? 1 : 0;
     p->overlap_tuned[lp] = best;
     cache[key.str()] = best;
     dirty = true;
