@@ -162,17 +162,34 @@ struct DftOddPrime {
 template <int S, typename R> struct Dft<5, S, R> : DftOddPrime<5, S, R> {};
 template <int S, typename R> struct Dft<7, S, R> : DftOddPrime<7, S, R> {};
 
-// composite N = F * M in registers: x[n1 + F n2] -> DFT_M over n2, twiddle, DFT_F over n1
-template <int N, int F, int S, typename R>
+// 3-point DFT of (a0, 0, a2): the middle input is known to be zero and is not read
+template <int S, typename R>
+struct Dft3ZeroMid {
+  __device__ __forceinline__ static void run(cplx<R>* a) {
+    const R h = R(0.866025403784438646763723170752936183);  // sqrt(3)/2
+    const cplx<R> x0 = a[0], x2 = a[2];
+    cplx<R> m = {x0.re - R(0.5) * x2.re, x0.im - R(0.5) * x2.im};
+    cplx<R> t = cmul_si<S>(cscale(x2, -h));
+    a[0] = cadd(x0, x2);
+    a[1] = cadd(m, t);
+    a[2] = csub(m, t);
+  }
+};
+
+// composite N = F * M in registers: x[n1 + F n2] -> DFT_M over n2, twiddle, DFT_F over n1.
+// ZM (M = 3 only): the inputs [F, 2F) (n2 = 1 of every inner DFT) are known to be zero.
+template <int N, int F, int S, typename R, bool ZM = false>
 struct DftComposite {
   static constexpr int M = N / F;
+  static_assert(!ZM || M == 3, "zero-middle pruning needs M = 3");
   __device__ __forceinline__ static void run(cplx<R>* a) {
     cplx<R> y[F][M];
 #pragma unroll
     for (int n1 = 0; n1 < F; ++n1) {
 #pragma unroll
-      for (int n2 = 0; n2 < M; ++n2) y[n1][n2] = a[n1 + F * n2];
-      Dft<M, S, R>::run(y[n1]);
+      for (int n2 = 0; n2 < M; ++n2) y[n1][n2] = (ZM && n2 == 1) ? cplx<R>{R(0), R(0)} : a[n1 + F * n2];
+      if constexpr (ZM) Dft3ZeroMid<S, R>::run(y[n1]);
+      else Dft<M, S, R>::run(y[n1]);
 #pragma unroll
       for (int k2 = 1; k2 < M; ++k2) {
         if (n1 == 0) continue;
@@ -219,6 +236,15 @@ template <int S, typename R> struct Dft<64, S, R> : DftComposite<64, 8, S, R> {}
 template <int S, typename R> struct Dft<72, S, R> : DftComposite<72, 8, S, R> {};
 template <int S, typename R> struct Dft<27, S, R> : DftComposite<27, 3, S, R> {};
 template <int S, typename R> struct Dft<54, S, R> : DftComposite<54, 6, S, R> {};
+
+// DFTs of length N = 3F whose inputs [F, 2F) are zero (the middle third of a line whose
+// nonzero samples lie within a third of the length of index 0, taken modulo N); zero_mid_f(N)
+// is that F, or 0 where no such pruned form exists.
+template <int N, int S, typename R> struct DftZM;
+template <int S, typename R> struct DftZM<6, S, R> : DftComposite<6, 2, S, R, true> {};
+template <int S, typename R> struct DftZM<9, S, R> : DftComposite<9, 3, S, R, true> {};
+template <int S, typename R> struct DftZM<12, S, R> : DftComposite<12, 4, S, R, true> {};
+__host__ __device__ constexpr int zero_mid_f(int n) { return n == 6 ? 2 : n == 9 ? 3 : n == 12 ? 4 : 0; }
 
 // Two-factor split used by the LDS line transforms: N = R1 * R2 with R1 <= R2.
 template <int N> struct Split;

@@ -23,6 +23,7 @@
 // that order and produces natural order, so no transposition pass exists
 // anywhere; V(r) is stored in the plan in the same permuted plane order.
 #pragma once
+#include <type_traits>
 #include "cplx.h"
 #include "qm_internal.h"
 
@@ -52,6 +53,9 @@ struct LocalArgs {
   int32_t nax_stride;       // row stride of the lane-group xy-plane buffer (elements)
   int32_t xy_stride;        // row stride of the two-pass xy-plane buffer (elements)
   int32_t sbuf_per_k;       // 1: k's stick block at sbuf + kinfo[k].sbuf_off; 0: at sbuf (one slice)
+  int32_t zero_mid;         // 1: no stick of any k has i1 or i2 in [R1 F, 2 R1 F) (F = zero_mid_f(R2)
+                            // of the N1 = N2 split), so those inputs of the inverse x and y
+                            // transforms are zero and those outputs of the forward ones unused
 };
 
 // This k's stick buffer.  In the plan's buffer its region starts at the same byte offset
@@ -229,6 +233,32 @@ __device__ __forceinline__ void wave_lds_sync() {
 template <typename R, int NX, bool OWN>
 constexpr int xy_min_waves() { return OWN && sizeof(R) == 8 && NX <= 80 ? 3 : 1; }
 
+// the N-point DFT, pruned (inputs [N/3, 2N/3) known zero) when Z
+template <int N, int S, typename R, bool Z>
+__device__ __forceinline__ void dft_zm(cplx<R>* x) {
+  if constexpr (Z) DftZM<N, S, R>::run(x);
+  else Dft<N, S, R>::run(x);
+}
+
+// x[n2] = row[cr[n2]], then the inverse R2-point DFT; with zm the inputs n2 in [ZF, 2 ZF) are
+// known zeros (not read, pruned DFT)
+template <int R2, typename R, int ZF>
+__device__ __forceinline__ void inverse_first_pass(cplx<R> (&x)[R2], const cplx<R>* row,
+                                                   const int (&cr)[R2], bool zm) {
+  if constexpr (ZF > 0) {
+    if (zm) {
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2)
+        x[n2] = (n2 >= ZF && n2 < 2 * ZF) ? cplx<R>{R(0), R(0)} : row[cr[n2]];
+      DftZM<R2, +1, R>::run(x);
+      return;
+    }
+  }
+#pragma unroll
+  for (int n2 = 0; n2 < R2; ++n2) x[n2] = row[cr[n2]];
+  Dft<R2, +1, R>::run(x);
+}
+
 // OWN = false: the x-row exchanges go through a row scratch of NX + 1 slots per row in flight
 // (4 R_W rows).  OWN = true: they go through the rows' own ns slots in two rounds each, which
 // leaves the plane as the only large LDS buffer (more workgroups per CU, more LDS operations);
@@ -279,26 +309,39 @@ __global__ void __launch_bounds__(256, (xy_min_waves<R, NX, OWN>())) k_xy(LocalA
   // y-pass items w = ia + nax j: thread tid starts at (tid % nax, tid / nax) and steps by
   // 256 = dj nax + dia, so each pass walks its items without a division per item
   const int ia0 = tid % nax, j0 = tid / nax, dj = 256 / nax, dia = 256 - dj * nax;
+  // zero middle band: with a.zero_mid the samples n1 + R1 n2, n2 in [ZF, 2 ZF), of every
+  // x-row and y-column hold no stick, so the inverse R2-point passes skip those inputs (no
+  // load, pruned DFT) and the forward y pass skips those outputs' stores
+  constexpr int ZF = zero_mid_f(R2);
+  const bool zm = ZF > 0 && a.zero_mid;
+  auto in_zm = [](int n) { return ZF > 0 && n >= ZF && n < 2 * ZF; };
   // ---- inverse y on active columns: pass 1 (R2-point, stride R1), input gathered from the
   // sticks (rows without a stick read zero)
-  for (int w = tid, ia = ia0, n1 = j0; w < nax * R1; w += 256, ia += dia, n1 += dj) {
-    if (ia >= nax) {
-      ia -= nax;
-      ++n1;
+  auto ypass1 = [&](auto zmc) {
+    constexpr bool Z = decltype(zmc)::value;
+    for (int w = tid, ia = ia0, n1 = j0; w < nax * R1; w += 256, ia += dia, n1 += dj) {
+      if (ia >= nax) {
+        ia -= nax;
+        ++n1;
+      }
+      int si[R2];
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2)
+        if (!(Z && in_zm(n2))) si[n2] = sat[(n1 + R1 * n2) * sts + ia];
+      cplx<R> x[R2];
+#pragma unroll
+      for (int n2 = 0; n2 < R2; ++n2)
+        x[n2] = (Z && in_zm(n2)) ? cplx<R>{R(0), R(0)} : stick_load(prs, si[n2], R(0));
+      dft_zm<R2, +1, R, Z && (ZF > 0)>(x);
+      // twiddle exponents n1 k2 <= (R1 - 1)(R2 - 1) < NX: no reduction modulo NX needed
+#pragma unroll
+      for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tw[n1 * k2]);
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) L[(n1 + R1 * k2) * ns + ia] = x[k2];
     }
-    int si[R2];
-#pragma unroll
-    for (int n2 = 0; n2 < R2; ++n2) si[n2] = sat[(n1 + R1 * n2) * sts + ia];
-    cplx<R> x[R2];
-#pragma unroll
-    for (int n2 = 0; n2 < R2; ++n2) x[n2] = stick_load(prs, si[n2], R(0));
-    Dft<R2, +1, R>::run(x);
-    // twiddle exponents n1 k2 <= (R1 - 1)(R2 - 1) < NX: no reduction modulo NX needed
-#pragma unroll
-    for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tw[n1 * k2]);
-#pragma unroll
-    for (int k2 = 0; k2 < R2; ++k2) L[(n1 + R1 * k2) * ns + ia] = x[k2];
-  }
+  };
+  if (zm) ypass1(std::integral_constant<bool, (ZF > 0)>{});
+  else ypass1(std::false_type{});
   __syncthreads();
   // pass 2 (R1-point on contiguous runs); output X[k2 + R2 k1] at position k1 + R1 k2
   for (int w = tid, ia = ia0, k2 = j0; w < nax * R2; w += 256, ia += dia, k2 += dj) {
@@ -372,9 +415,7 @@ __global__ void __launch_bounds__(256, (xy_min_waves<R, NX, OWN>())) k_xy(LocalA
       // inverse pass 1: lanes q < R1 (n1 = q), R2-point DFT over n2 of x[q + R1 n2], twiddle
       cplx<R> x[R2];
       if (act && q < R1) {
-#pragma unroll
-        for (int n2 = 0; n2 < R2; ++n2) x[n2] = Lr[cr[n2]];
-        Dft<R2, +1, R>::run(x);
+        inverse_first_pass<R2, R, ZF>(x, Lr, cr, zm);
         if constexpr (kTwReg) {
 #pragma unroll
           for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tq[k2]);
@@ -491,9 +532,7 @@ __global__ void __launch_bounds__(256, (xy_min_waves<R, NX, OWN>())) k_xy(LocalA
       cplx<R>* Lrow = L + lrow * ns;
       if (act && q < R1) {
         cplx<R> x[R2];
-#pragma unroll
-        for (int n2 = 0; n2 < R2; ++n2) x[n2] = Lrow[cr[n2]];
-        Dft<R2, +1, R>::run(x);
+        inverse_first_pass<R2, R, ZF>(x, Lrow, cr, zm);
 #pragma unroll
         for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tq[k2]);
 #pragma unroll
@@ -554,16 +593,19 @@ __global__ void __launch_bounds__(256, (xy_min_waves<R, NX, OWN>())) k_xy(LocalA
       ia -= nax;
       ++k2;
     }
+    // rows of the zero middle band hold no stick: with zm neither their stick indices are
+    // read nor their (dropped) stores issued
     int si[R2];
 #pragma unroll
-    for (int k1 = 0; k1 < R2; ++k1) si[k1] = sat[(k2 + R1 * k1) * sts + ia];
+    for (int k1 = 0; k1 < R2; ++k1) si[k1] = (zm && in_zm(k1)) ? -1 : sat[(k2 + R1 * k1) * sts + ia];
     cplx<R> z[R2];
 #pragma unroll
     for (int n1 = 0; n1 < R2; ++n1) z[n1] = L[(k2 + R1 * n1) * ns + ia];
     Dft<R2, -1, R>::run(z);
     // row i2 = k2 + R1 k1 of the plane: written back where it has a stick
 #pragma unroll
-    for (int k1 = 0; k1 < R2; ++k1) stick_store(prs, si[k1], z[k1]);
+    for (int k1 = 0; k1 < R2; ++k1)
+      if (!(zm && in_zm(k1))) stick_store(prs, si[k1], z[k1]);
   }
 }
 

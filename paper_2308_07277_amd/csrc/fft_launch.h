@@ -46,6 +46,7 @@ LocalArgs make_local_args(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const 
   a.ts = kZTile;
   a.nax_stride = p->nax_max | 1;
   a.xy_stride = xy_row_stride(p->N1, p->nax_max, false);
+  a.zero_mid = p->zero_mid;
   QM_REQUIRE(nblk_z < (int64_t(1) << 31), QM_E_SHAPE, "launch too large");
   return a;
 }

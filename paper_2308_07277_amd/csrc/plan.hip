@@ -102,6 +102,9 @@ static void build_plan(qm_hpsi_plan* p, const double cell[9], const int32_t grid
   int64_t g_off = 0, stick_off = 0, tile_off = 0;
   std::vector<int32_t> stick_of(size_t(N1) * N2);
   std::vector<std::vector<int32_t>> sat_k(p->nk);   // per k: [N2][nax] stick index or -1
+  // zero middle band of the xy transforms: x and y indices [R1 F, 2 R1 F) must hold no stick
+  const int zf = zero_mid_f(fft_split_r2(N1)), zlo = fft_split_r1(N1) * zf, zhi = 2 * zlo;
+  bool zmid = zf > 0 && N1 == N2;
   for (int k = 0; k < p->nk; ++k) {
     const int npw = ks->npw[k];
     QM_REQUIRE(npw >= 1, QM_E_ARG, "every k needs npw >= 1");
@@ -150,6 +153,8 @@ static void build_plan(qm_hpsi_plan* p, const double cell[9], const int32_t grid
       for (int i1 = 0; i1 < N1; ++i1)
         if (ia_of[i1] >= 0) sat_k[k][size_t(i2) * nax + ia_of[i1]] = stick_of[size_t(i2) * N1 + i1];
     for (int s2 = 0; s2 < nstick; ++s2) stick_pos.push_back(st_i2[s2] | (ia_of[st_i1[s2]] << 16));
+    for (int s2 = 0; s2 < nstick; ++s2)
+      if ((st_i1[s2] >= zlo && st_i1[s2] < zhi) || (st_i2[s2] >= zlo && st_i2[s2] < zhi)) zmid = false;
     // entries grouped by stick tile; inside a tile ordered by (i3, stick) so consecutive
     // threads of the z kernels touch neighbouring x-columns of one plane (adjacent in the
     // usual G orders)
@@ -204,6 +209,8 @@ static void build_plan(qm_hpsi_plan* p, const double cell[9], const int32_t grid
     tile_off += ntile + 1;
   }
   p->npw_total = g_off;
+  p->zero_mid = zmid ? 1 : 0;
+  if (const char* zm = std::getenv("QM_ZERO_MID")) p->zero_mid = p->zero_mid && std::atoi(zm) != 0;
   QM_REQUIRE(N1 <= 65535 && p->nax_max <= 32767, QM_E_SHAPE, "grid too large for stick tables");
 
   p->g.kinfo = upload(p->kinfo, s);

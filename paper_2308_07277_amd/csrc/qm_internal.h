@@ -97,6 +97,7 @@ struct qm_hpsi_plan {
   qm_prec prec = QM_PREC_FP64;
   int32_t zts = 32;               // sticks per z-kernel tile
   int32_t nax_max = 0;
+  int32_t zero_mid = 0;           // LocalArgs::zero_mid, for every k of the plan
   int64_t npw_total = 0;
   int32_t npw_max = 0;
   double cell[9] = {0}, recip[9] = {0};

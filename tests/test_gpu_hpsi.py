@@ -264,6 +264,34 @@ def test_xy_kernel_variants_agree(name, prec, tol, monkeypatch):
     assert worst <= tol
 
 
+@pytest.mark.parametrize("name,prec,mode", [("c3", 0, "3"), ("c3", 1, "1"), ("c5", 0, "1")])
+def test_zero_middle_band_pruning(name, prec, mode, monkeypatch):
+    """On the 72- and 108-point grids no stick has an x or y index in the middle third of the
+    line ([24, 48) and [36, 72): the spheres reach 18 and 27 points from 0), so the inverse
+    xy passes skip those inputs (pruned 9- and 12-point DFTs) and the forward y pass skips
+    those stores.  Results equal the unpruned kernels (QM_ZERO_MID=0) to rounding, and the
+    pruned float64 path matches the oracle on two bands of the first k-point."""
+    w = workload.make_workload(name, nk_limit=1)
+    nb = 16
+    flat, per = psi_block(w, nb)
+    monkeypatch.setenv("QM_XY_MODE", mode)
+    outs = []
+    a = None
+    for zm in ("1", "0"):
+        monkeypatch.setenv("QM_ZERO_MID", zm)
+        plan, a = make_plan(w, nb, prec=prec, arrays=a)
+        outs.append(split_k(_run(plan, w, nb, psi_flat=flat), w, nb)[0])
+        plan.close()
+    diff = float(band_rel_err(np.asarray(outs[0]), np.asarray(outs[1])).max())
+    print(name, prec, mode, "pruned vs unpruned max band rel diff", diff)
+    assert diff <= (1e-14 if prec == 0 else 1e-6)
+    if prec == 0 and name == "c3":
+        ref = _oracle(w, a, 0, per[0][:2])
+        err = band_rel_err(np.asarray(outs[0])[:2], ref)
+        print("pruned vs oracle", err.max())
+        assert err.max() <= 1e-12
+
+
 def test_c2_mixed_against_float32():
     """Mixed precision differs from float32 only in the projector GEMMs (bfloat16 operands,
     float32 accumulation), so the band-wise difference isolates them: each projection and
