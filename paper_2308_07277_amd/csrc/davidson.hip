@@ -64,7 +64,7 @@ struct DavState {
 static void dav_release(DavState* d) {
   void* dev[] = {d->V, d->HV, d->X, d->HX, d->R, d->TS, d->Hs, d->Aw, d->Z, d->tau, d->Cw, d->G,
                  d->W, d->theta, d->d, d->e, d->resn, d->tkin, d->yw, d->fw, d->unconv, d->info,
-                 d->goff, d->work, d->estar, d->ps.part, d->trd.v, d->trd.w, d->trd.part, d->trd.cnt,
+                 d->goff, d->work, d->estar, d->ps.part, d->trd.v, d->trd.w, d->trd.part, d->trd.cnt, d->trd.bcnt, d->trd.prow,
                  d->ew.sc, d->ew.nrm, d->chol_dmax, d->chol_ld, d->bt_t, d->cgs_ovl};
   for (void* q : dev)
     if (q) (void)hipFree(q);
@@ -139,6 +139,10 @@ static DavState* dav_create(qm_hpsi_plan* p, int k0, int k1, int nb, int mb, boo
     d->trd.ptiles = trd_tile_slots(mb);
     d->trd.part = dalloc<double2>(nk * size_t(d->trd.ptiles) * 2 * kTrdTile);
     d->trd.cnt = dalloc<uint32_t>(nk);
+    d->trd.nblk = (mb + kTrdTile - 1) / kTrdTile;
+    d->trd.bcnt = dalloc<uint32_t>(nk * size_t(d->trd.nblk));
+    d->trd.prow = dalloc<double2>(nk * mb);
+    d->trd.fin_min = p->trd_fin_min;
     d->ew.sc = dalloc<double>(nk * nb);
     d->ew.nrm = dalloc<double>(nk);
     d->chol_dmax = dalloc<double>(nk);

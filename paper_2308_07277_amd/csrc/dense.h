@@ -27,8 +27,13 @@ struct TrdWork {
   double2* w;      // [k][mb]    w of the previous step (the pending rank-2 update is v w^H + w v^H)
   double2* part;   // [k][ptiles][2][kTrdTile] each tile's share of A v: its 64 row sums and
                    //            its 64 column sums, summed in a fixed order by the last workgroup
-  uint32_t* cnt;   // [k]        workgroups of the current step that have finished
+  uint32_t* cnt;   // [k]        workgroups (or, with row-block finishers, row blocks) of the
+                   //            current step that have finished
+  uint32_t* bcnt;  // [k][nblk]  per row block: slots of the current step written
+  double2* prow;   // [k][mb]    A v per row, summed by the row block's finisher
   int32_t ptiles;  // tile slots per k: nt (nt + 1) / 2 with nt = ceil(mb / kTrdTile)
+  int32_t nblk;    // row blocks per k: ceil(mb / kTrdTile)
+  int32_t fin_min; // steps with at least this many slots per row (nt + 1) use row-block finishers
 };
 inline int trd_tile_slots(int mb) {
   const int nt = (mb + kTrdTile - 1) / kTrdTile;

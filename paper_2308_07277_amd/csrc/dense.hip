@@ -364,6 +364,7 @@ __global__ void __launch_bounds__(256) k_trd_start(DJobs jobs, double2* __restri
   const int mb = jobs.mb, m = J.m, k = J.k;
   double2* A = Aw + int64_t(k) * mb * mb;
   if (threadIdx.x == 0) tw.cnt[k] = 0u;
+  for (int b = threadIdx.x; b < tw.nblk; b += 256) tw.bcnt[int64_t(k) * tw.nblk + b] = 0u;
   double2 a[kTrdRows];
 #pragma unroll
   for (int q = 0; q < kTrdRows; ++q) {
@@ -383,7 +384,7 @@ __global__ void __launch_bounds__(256) k_trd_step(DJobs jobs, int j, double2* __
   __shared__ double2 s_row[T];
   __shared__ double2 s_vec[6][T];
   __shared__ double red[32];
-  __shared__ unsigned s_last;
+  __shared__ unsigned s_last, s_fin;
   __shared__ double2 s_wj1, s_vj1;
   const DJob& J = jobs.j[blockIdx.y];
   const int mb = jobs.mb, m = J.m, k = J.k;
@@ -506,12 +507,84 @@ __global__ void __launch_bounds__(256) k_trd_step(DJobs jobs, int j, double2* __
     chk += __hip_atomic_exchange(&PS[(int64_t(t) * 2 * T + tid) * 2 + 1], s.y, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_AGENT);
   }
-  // the last workgroup of this job to finish carries on
   if (chk == 1.0e300) s_last = 2u;   // never true; makes the thread wait for its additions
-  __syncthreads();
-  if (tid == 0) s_last = atomicAdd(&tw.cnt[k], 1u) == unsigned(ntiles - 1) ? 1u : 0u;
-  __syncthreads();
-  if (s_last != 1u) return;
+  const int nall = nt + 1;
+  const bool blockfin = nall >= tw.fin_min;
+  constexpr int kCohLoad = 16;   // cache-policy bits of a buffer load: sc1 (see the gather below)
+  if (!blockfin) {
+    // the last workgroup of this job to finish carries on
+    __syncthreads();
+    if (tid == 0) s_last = atomicAdd(&tw.cnt[k], 1u) == unsigned(ntiles - 1) ? 1u : 0u;
+    __syncthreads();
+    if (s_last != 1u) return;
+  } else {
+    // Row-block finishers: a tile counts its row sums on its row block's counter and its
+    // column sums on its column block's counter.  The tile that completes a block adds that
+    // block's nt + 1 slots per row: four quarters of the slot list in turn (one quarter per
+    // wave, in slot order), then the quarters in order, so the sums do not depend on which
+    // tile finishes.  It stores A v of the block's rows (agent-scope exchanges, waited for)
+    // and counts the block on the job's counter; the workgroup that completes the last block
+    // carries on and reads A v per row.
+    uint32_t* bc = tw.bcnt + int64_t(k) * tw.nblk;
+    __syncthreads();
+    if (tid == 0) {
+      unsigned f = 0u;
+      if (ti == tj) {
+        if (atomicAdd(&bc[ti], 2u) == unsigned(nall - 2)) f = 1u;
+      } else {
+        if (atomicAdd(&bc[ti], 1u) == unsigned(nall - 1)) f |= 1u;
+        if (atomicAdd(&bc[tj], 1u) == unsigned(nall - 1)) f |= 2u;
+      }
+      s_fin = f;
+    }
+    __syncthreads();
+    const unsigned fin = s_fin;
+    if (fin == 0u) return;
+    const __amdgpu_buffer_rsrc_t srs = __builtin_amdgcn_make_buffer_rsrc(
+        PS, (short)0, tw.ptiles * 2 * T * int(sizeof(double2)), 0x00020000);
+    double2* prow = tw.prow + int64_t(k) * mb;
+    const int g = tid >> 6, i = lane;
+    const int Q = (nall + 3) / 4;   // slots per quarter (at most 9: nt <= 32)
+    const int c0 = g * Q, c1 = min(nall, c0 + Q);
+    double chk2 = 0.0;
+    unsigned nfin = 0u;
+    for (int h = 0; h < 2; ++h) {
+      if (!(fin & (1u << h))) continue;
+      const int ib = h == 0 ? ti : tj, nrow = ib + 1;
+      constexpr int kQMax = (kTrdMaxBasis / kTrdTile + 4) / 4;
+      double2 gl[kQMax];
+#pragma unroll
+      for (int u = 0; u < kQMax; ++u) {
+        const int c = min(c0 + u, nall - 1);
+        const int slot = c < nrow ? (ib * (ib + 1) / 2 + c) * 2
+                                  : ((ib + c - nrow) * (ib + c - nrow + 1) / 2 + ib) * 2 + 1;
+        gl[u] = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(
+                                                srs, (slot * T + i) * int(sizeof(double2)), 0, kCohLoad));
+      }
+      double2 acc = z;
+#pragma unroll
+      for (int u = 0; u < kQMax; ++u)
+        if (c0 + u < c1) acc = cadd2(acc, gl[u]);
+      s_col[g][i] = acc;
+      __syncthreads();
+      if (g == 0) {
+        const double2 pr = cadd2(cadd2(cadd2(s_col[0][i], s_col[1][i]), s_col[2][i]), s_col[3][i]);
+        const int r = (b0 + ib) * T + i;
+        if (r >= j1 && r < m) {
+          chk2 += __hip_atomic_exchange(&prow[r].x, pr.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          chk2 += __hip_atomic_exchange(&prow[r].y, pr.y, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+      }
+      if (tid == 0) __hip_atomic_store(&bc[ib], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __syncthreads();
+      ++nfin;
+    }
+    if (chk2 == 1.0e300) s_last = 2u;   // never true; waits for the exchanges
+    __syncthreads();
+    if (tid == 0) s_last = atomicAdd(&tw.cnt[k], nfin) + nfin == unsigned(nt) ? 1u : 0u;
+    __syncthreads();
+    if (s_last != 1u) return;
+  }
   double* d = dd + int64_t(k) * mb;
   double* e = ee + int64_t(k) * mb;
   double2* tk = tau + int64_t(k) * mb;
@@ -522,10 +595,8 @@ __global__ void __launch_bounds__(256) k_trd_step(DJobs jobs, int j, double2* __
   // by this CU's cache), kTrdGather slots of every row of the thread in flight at once, so the
   // whole gather costs about (nt + 1) / kTrdGather round trips to memory.
   constexpr int kTrdGather = 4;
-  constexpr int kCohLoad = 16;   // cache-policy bits of a buffer load: sc1
   const __amdgpu_buffer_rsrc_t prs = __builtin_amdgcn_make_buffer_rsrc(
       PS, (short)0, tw.ptiles * 2 * T * int(sizeof(double2)), 0x00020000);
-  const int nall = nt + 1;
   int ibq[kTrdRows], iq[kTrdRows];
   double2 pq[kTrdRows];
 #pragma unroll
@@ -535,7 +606,18 @@ __global__ void __launch_bounds__(256) k_trd_step(DJobs jobs, int j, double2* __
     iq[q] = r - (b0 + ibq[q]) * T;
     pq[q] = z;
   }
-  for (int c0 = 0; c0 < nall; c0 += kTrdGather) {
+  if (blockfin) {   // A v per row from the row-block finishers (rows past m read row m - 1)
+    const __amdgpu_buffer_rsrc_t rrs = __builtin_amdgcn_make_buffer_rsrc(
+        tw.prow + int64_t(k) * mb, (short)0, mb * int(sizeof(double2)), 0x00020000);
+#pragma unroll
+    for (int q = 0; q < kTrdRows; ++q) {
+      if (j1 + q * 256 >= m) break;
+      const int r = min(j1 + tid + q * 256, m - 1);
+      pq[q] = __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(
+                                              rrs, r * int(sizeof(double2)), 0, kCohLoad));
+    }
+  }
+  for (int c0 = 0; c0 < (blockfin ? 0 : nall); c0 += kTrdGather) {
     double2 g[kTrdRows][kTrdGather];
 #pragma unroll
     for (int q = 0; q < kTrdRows; ++q) {

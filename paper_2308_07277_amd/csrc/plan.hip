@@ -75,6 +75,7 @@ static void build_plan(qm_hpsi_plan* p, const double cell[9], const int32_t grid
   p->zts = kTileSticks;
   if (const char* xm = std::getenv("QM_XY_MODE")) p->xy_forced = std::atoi(xm);
   if (const char* tm = std::getenv("QM_TRIDIAG_MODE")) p->trd_forced = std::atoi(tm);
+  if (const char* tf = std::getenv("QM_TRD_FINISH_MIN")) p->trd_fin_min = std::max(2, std::atoi(tf));
   if (const char* cm = std::getenv("QM_CHOL_MODE")) p->chol_forced = std::atoi(cm);
   if (const char* om = std::getenv("QM_OVERLAP")) p->overlap_forced = std::atoi(om) != 0;
   QM_HIP(hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking));

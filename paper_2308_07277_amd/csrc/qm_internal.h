@@ -155,6 +155,10 @@ struct qm_hpsi_plan {
   // Davidson tridiagonalisation: 1 one workgroup per k-point, 2 many workgroups per k-point
   // (one launch per step), 0 chosen by basis size (environment QM_TRIDIAG_MODE).
   int32_t trd_forced = 0;
+  // Householder steps with at least this many tile slots per row (nt + 1) have each row block's
+  // slots added by the tile that completes the block, so the step's last workgroup reads A v
+  // per row instead of every slot (environment QM_TRD_FINISH_MIN)
+  int32_t trd_fin_min = 16;
   // CholQR Cholesky + inverse: 1 one workgroup per k-point, 2 blocked on many workgroups,
   // 0 blocked up to 576 bands (environment QM_CHOL_MODE).
   int32_t chol_forced = 0;
