@@ -180,7 +180,8 @@ static double2* vrow(DavState* d, double2* base, const DJob& j, int row) {
 static void timed_apply(qm_hpsi_plan* p, DavState* d, const std::vector<KSlice>& sl, const void* in,
                         void* out, hipStream_t s, bool lowp) {
   QM_HIP(hipEventRecord(d->ev[0], s));
-  apply_h_slices(p, sl, in, out, s, lowp ? p->prec : QM_PREC_FP64, nullptr, d->ps.part ? &d->ps : nullptr);
+  apply_h_slices(p, sl, in, out, s, lowp ? p->prec : QM_PREC_FP64, nullptr, d->ps.part ? &d->ps : nullptr,
+                 nullptr, false);
   QM_HIP(hipEventRecord(d->ev[1], s));
   QM_HIP(hipEventSynchronize(d->ev[1]));
   float ms = 0.f;

@@ -95,9 +95,25 @@ std::vector<KSlice> contiguous_slices(const qm_hpsi_plan* p, int k0, int k1, int
   return out;
 }
 
+bool side_stream_wanted(const qm_hpsi_plan* p, qm_prec prec) {
+  const int lp = prec == QM_PREC_FP64 ? 0 : (prec == QM_PREC_FP32 ? 1 : 2);
+  const int ovl = p->overlap_forced >= 0 ? p->overlap_forced : p->overlap_tuned[lp];
+  return ovl && p->nproj > 0;
+}
+
+// The side stream is created on first use: every stream of the process takes one of the few
+// hardware queues in turn, so a stream that is never used would still change which streams
+// share a queue (the Davidson lanes, for one).
+void ensure_side_stream(qm_hpsi_plan* p) {
+  if (p->side_stream) return;
+  QM_HIP(hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking));
+  QM_HIP(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
+  QM_HIP(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
+}
+
 void apply_h_slices(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
                     hipStream_t s, qm_prec prec, StageEvents* ev, const ProjScratch* ps,
-                    const HpsiWork* wk) {
+                    const HpsiWork* wk, bool side_ok) {
   QM_REQUIRE(!wk || sl.size() == 1, QM_E_STATE, "caller-given working memory takes one slice");
   for (size_t b = 0; b < sl.size(); b += kMaxSlices) {
     std::vector<KSlice> chunk(sl.begin() + b, sl.begin() + std::min(sl.size(), b + kMaxSlices));
@@ -106,12 +122,11 @@ void apply_h_slices(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* 
       if (x.nb > 0) nz.push_back(x);
     if (nz.empty()) continue;
     // the projection on the side stream, concurrent with the local part; calls with stage
-    // events, their own split-K scratch (Davidson lanes) or caller-given working memory stay
-    // on one stream.  The side stream first waits for everything before on s (the previous
+    // events, their own split-K scratch or caller-given working memory, and the Davidson's
+    // (side_ok = false: its lanes are streams of their own) stay on one stream.  The side stream first waits for everything before on s (the previous
     // call's expansion still reads Q), and s waits for it before the expansion.
-    const int lp = prec == QM_PREC_FP64 ? 0 : (prec == QM_PREC_FP32 ? 1 : 2);
-    const int ovl = p->overlap_forced >= 0 ? p->overlap_forced : p->overlap_tuned[lp];
-    if (ovl && p->nproj > 0 && p->side_stream && !ev && !ps && !wk) {
+    if (side_ok && side_stream_wanted(p, prec) && !ev && !ps && !wk) {
+      ensure_side_stream(p);
       convert_beta(p, prec, s);   // (a no-op unless the precision changed)
       QM_HIP(hipEventRecord(p->ev_fork, s));
       QM_HIP(hipStreamWaitEvent(p->side_stream, p->ev_fork, 0));

@@ -78,9 +78,6 @@ static void build_plan(qm_hpsi_plan* p, const double cell[9], const int32_t grid
   if (const char* tf = std::getenv("QM_TRD_FINISH_MIN")) p->trd_fin_min = std::max(2, std::atoi(tf));
   if (const char* cm = std::getenv("QM_CHOL_MODE")) p->chol_forced = std::atoi(cm);
   if (const char* om = std::getenv("QM_OVERLAP")) p->overlap_forced = std::atoi(om) != 0;
-  QM_HIP(hipStreamCreateWithFlags(&p->side_stream, hipStreamNonBlocking));
-  QM_HIP(hipEventCreateWithFlags(&p->ev_fork, hipEventDisableTiming));
-  QM_HIP(hipEventCreateWithFlags(&p->ev_join, hipEventDisableTiming));
   std::memcpy(p->cell, cell, sizeof(p->cell));
   // reciprocal rows b_i = 2 pi (A^-1)^T
   const double* a = cell;
@@ -310,6 +307,7 @@ void apply_graph(qm_hpsi_plan* p, int k, const void* psi, void* hpsi, int nbnd, 
     }
   if (!p->capture_stream) QM_HIP(hipStreamCreateWithFlags(&p->capture_stream, hipStreamNonBlocking));
   convert_beta(p, p->prec, s);                     // any one-time conversion happens eagerly
+  if (side_stream_wanted(p, p->prec)) ensure_side_stream(p);   // created outside the capture
   QM_HIP(hipStreamSynchronize(s));
   hipGraph_t graph = nullptr;
   QM_HIP(hipStreamBeginCapture(p->capture_stream, hipStreamCaptureModeThreadLocal));

@@ -207,10 +207,16 @@ void launch_nonlocal(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void*
                      int parts = kNlAll);
 // H applied to every slice (local + non-local), in chunks of kMaxSlices.  At most one slice
 // per k-point per call (stick buffer, P and Q are addressed per k).
+// side_ok = false keeps the projection on s (callers that run several streams of their own).
 void apply_h_slices(qm_hpsi_plan* p, const std::vector<KSlice>& sl, const void* psi, void* hpsi,
                     hipStream_t s, qm_prec prec, StageEvents* ev = nullptr,
-                    const ProjScratch* ps = nullptr, const HpsiWork* wk = nullptr);
+                    const ProjScratch* ps = nullptr, const HpsiWork* wk = nullptr,
+                    bool side_ok = true);
 std::vector<KSlice> contiguous_slices(const qm_hpsi_plan* p, int k0, int k1, int nbnd);
+// whether H applications in precision prec run the projection on the side stream, and the
+// side stream's creation on first use
+bool side_stream_wanted(const qm_hpsi_plan* p, qm_prec prec);
+void ensure_side_stream(qm_hpsi_plan* p);
 // qm_apply_h's graph path: replay (capturing on first use) the launch sequence of k (-1: all)
 // at nbnd bands for these buffers in the plan's precision
 void apply_graph(qm_hpsi_plan* p, int k, const void* psi, void* hpsi, int nbnd, hipStream_t s);
