@@ -35,6 +35,7 @@ struct DensArgs {
   double* part;                     // [ngroups][N3 slot][NX i2][NX i1]
   int32_t nax_stride;               // LDS row stride: active columns plus a zero slot
   int32_t sat_stride;
+  int32_t zero_mid;                 // the plan's zero middle band (LocalArgs::zero_mid)
 };
 
 __device__ __forceinline__ void wave_sync_lds() {
@@ -67,6 +68,9 @@ __global__ void __launch_bounds__(256) k_density_xy(DensArgs a) {
   int* col = reinterpret_cast<int*>(tw + NX);            // [NX]
   const int tid = threadIdx.x, p = blockIdx.x, g = blockIdx.y, N3 = a.N3;
   const int wave = tid >> 6, lane = tid & 63;
+  constexpr int ZF = zero_mid_f(R2);
+  const bool zm = ZF > 0 && a.zero_mid;
+  auto in_zm = [](int n) { return ZF > 0 && n >= ZF && n < 2 * ZF; };
   const int q = lane % R2, rs = lane / R2;
   cplx<R>* Xr = X + (wave * RW + (rs < RW ? rs : 0)) * NXP;
   for (int i = tid; i < NX; i += 256) {
@@ -115,12 +119,22 @@ __global__ void __launch_bounds__(256) k_density_xy(DensArgs a) {
         ++n1;
       }
       int sx[R2];
-#pragma unroll
-      for (int n2 = 0; n2 < R2; ++n2) sx[n2] = sat[(n1 + R1 * n2) * sts + ia];
       cplx<R> x[R2];
+      if (ZF > 0 && zm) {   // rows of the zero middle band hold no stick (as in k_xy)
 #pragma unroll
-      for (int n2 = 0; n2 < R2; ++n2) x[n2] = stick_load(prs, sx[n2], R(0));
-      Dft<R2, +1, R>::run(x);
+        for (int n2 = 0; n2 < R2; ++n2)
+          if (!in_zm(n2)) sx[n2] = sat[(n1 + R1 * n2) * sts + ia];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2)
+          x[n2] = in_zm(n2) ? cplx<R>{R(0), R(0)} : stick_load(prs, sx[n2], R(0));
+        dft_zm<R2, +1, R, (ZF > 0)>(x);
+      } else {
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) sx[n2] = sat[(n1 + R1 * n2) * sts + ia];
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) x[n2] = stick_load(prs, sx[n2], R(0));
+        Dft<R2, +1, R>::run(x);
+      }
 #pragma unroll
       for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tw[n1 * k2]);   // n1 k2 < NX
 #pragma unroll
@@ -149,9 +163,7 @@ __global__ void __launch_bounds__(256) k_density_xy(DensArgs a) {
       const int lrow = act ? (i2 / R2) + R1 * (i2 % R2) : 0;
       if (act && q < R1) {
         cplx<R> x[R2];
-#pragma unroll
-        for (int n2 = 0; n2 < R2; ++n2) x[n2] = L[lrow * ns + cr[n2]];
-        Dft<R2, +1, R>::run(x);
+        inverse_first_pass<R2, R, ZF>(x, L + lrow * ns, cr, zm);
 #pragma unroll
         for (int k2 = 1; k2 < R2; ++k2) x[k2] = cmul(x[k2], tq[k2]);
 #pragma unroll
@@ -284,6 +296,7 @@ static void density(qm_hpsi_plan* p, int k, const void* psi, int nbnd, const dou
   a.wf = p->dens_wf;
   a.part = p->rho_part;
   a.nax_stride = (p->nax_max + 1) | 1;
+  a.zero_mid = p->zero_mid;
   launch_zinv_f64(p, sl, psi, s);
 #define QM_DXY(n)                       \
   case n:                               \
