@@ -591,6 +591,8 @@ def main():
     ap.add_argument("--cpu-sample-bands", type=int, default=160)
     ap.add_argument("--other-workloads", type=int, default=1,
                     help="also measure H|psi> bands/s on the 2-, 8- and 216-atom workloads")
+    ap.add_argument("--davidson-c4", type=int, default=1,
+                    help="with --davidson: the arms on the 64-atom cell (0 skips them, for profiling)")
     ap.add_argument("--davidson-c5", type=int, default=1,
                     help="also time the Davidson on the 216-atom Gamma-point cell (about a minute)")
     ap.add_argument("--adjacent", type=int, default=1,
@@ -707,8 +709,9 @@ def main():
         weights, tinfo = train_preconditioner()
         out["mlp_training"] = tinfo
         progress("learned preconditioner trained")
-        out["davidson"] = davidson_run("c4", weights=weights, oracle_k=(0, 8, 16))
-        progress("Davidson on the 64-atom cell done")
+        if args.davidson_c4:
+            out["davidson"] = davidson_run("c4", weights=weights, oracle_k=(0, 8, 16))
+            progress("Davidson on the 64-atom cell done")
         if args.davidson_c5:
             # 64 buffer bands and a 3.5x basis (1974 columns): 45 iterations instead of 70
             # with 32 buffer bands and a 3x basis, for every arm
