@@ -51,6 +51,15 @@ struct DavState {
   int32_t *h_unconv = nullptr, *h_info = nullptr;
   double* h_cgs_ovl = nullptr;
   std::vector<int> m, it, done;
+  // qm_davidson_solve: Ritz vectors, H Ritz vectors and residuals only for the bands being
+  // corrected (the rest before a restart, a precision switch, a convergence verdict and the
+  // return); stale[k]: some rows of X and HX predate the last Rayleigh-Ritz step of k, whose
+  // refreshed bands are lastact[k]
+  bool lazy = false;
+  std::vector<char> stale;
+  std::vector<std::vector<int32_t>> lastact;
+  int32_t* slist = nullptr;      // [k][nb] device list of the stale bands being completed
+  int32_t* h_slist = nullptr;
   int64_t n_hpsi = 0, n_hpsi_lowp = 0;
   int64_t n_cgs = 0, n_cgs2 = 0;   // Gram-Schmidt calls per k, and those that took a second pass
   double tol = 1e-8;
@@ -65,10 +74,10 @@ static void dav_release(DavState* d) {
   void* dev[] = {d->V, d->HV, d->X, d->HX, d->R, d->TS, d->Hs, d->Aw, d->Z, d->tau, d->Cw, d->G,
                  d->W, d->theta, d->d, d->e, d->resn, d->tkin, d->yw, d->fw, d->unconv, d->info,
                  d->goff, d->work, d->estar, d->ps.part, d->trd.v, d->trd.w, d->trd.part, d->trd.cnt, d->trd.bcnt, d->trd.prow,
-                 d->ew.sc, d->ew.nrm, d->chol_dmax, d->chol_ld, d->bt_t, d->cgs_ovl};
+                 d->ew.sc, d->ew.nrm, d->chol_dmax, d->chol_ld, d->bt_t, d->cgs_ovl, d->slist};
   for (void* q : dev)
     if (q) (void)hipFree(q);
-  void* host[] = {d->h_resn, d->h_theta, d->h_unconv, d->h_info, d->h_cgs_ovl};
+  void* host[] = {d->h_resn, d->h_theta, d->h_unconv, d->h_info, d->h_cgs_ovl, d->h_slist};
   for (void* q : host)
     if (q) (void)hipHostFree(q);
   for (hipEvent_t& e : d->ev)
@@ -158,6 +167,8 @@ static DavState* dav_create(qm_hpsi_plan* p, int k0, int k1, int nb, int mb, boo
     QM_HIP(hipHostMalloc(reinterpret_cast<void**>(&d->h_unconv), nk * nb * sizeof(int32_t)));
     QM_HIP(hipHostMalloc(reinterpret_cast<void**>(&d->h_info), nk * sizeof(int32_t)));
     QM_HIP(hipHostMalloc(reinterpret_cast<void**>(&d->h_cgs_ovl), nk * sizeof(double)));
+    QM_HIP(hipHostMalloc(reinterpret_cast<void**>(&d->h_slist), nk * nb * sizeof(int32_t)));
+    d->slist = dalloc<int32_t>(nk * nb);
     for (hipEvent_t& e : d->ev) QM_HIP(hipEventCreate(&e));
     const void* big[] = {reinterpret_cast<const void*>(&k_tridiag), reinterpret_cast<const void*>(&k_eig_vals),
                          reinterpret_cast<const void*>(&k_chol_inv_cols),
@@ -166,6 +177,8 @@ static DavState* dav_create(qm_hpsi_plan* p, int k0, int k1, int nb, int mb, boo
     d->m.assign(nk, 0);
     d->it.assign(nk, 0);
     d->done.assign(nk, 0);
+    d->stale.assign(nk, 0);
+    d->lastact.assign(nk, {});
   } catch (...) {
     dav_release(d);
     throw;
@@ -327,7 +340,10 @@ static void tridiagonalise(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipS
 }
 
 // Projected matrix columns [m_old, m), eigenproblem, Ritz vectors and residuals.
-static void rayleigh_ritz(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipStream_t s) {
+// lazy: X, HX and the residuals only for each job's nu bands listed in d->unconv (the bands
+// being corrected this step); the other rows of X and HX are left as they were (stale)
+static void rayleigh_ritz(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipStream_t s,
+                          bool lazy = false) {
   const int lp = subspace_lp(d);
   std::vector<GemmCN> cn;
   QM_HIP(hipEventRecord(d->ev[6], s));
@@ -371,12 +387,20 @@ static void rayleigh_ritz(qm_hpsi_plan* p, DavState* d, const DJobs& jobs, hipSt
   for (int i = 0; i < jobs.n; ++i) {
     const DJob& j = jobs.j[i];
     double2* Zk = d->Z + int64_t(j.k) * d->mb * d->nb;
-    ex.push_back(GemmEX{Zk, vrow(d, d->V, j, 0), d->X + j.xoff, d->nb, j.npw, j.m, d->nb, j.npw, j.npw});
-    ex.push_back(GemmEX{Zk, vrow(d, d->HV, j, 0), d->HX + j.xoff, d->nb, j.npw, j.m, d->nb, j.npw, j.npw});
+    const int32_t* rows = lazy ? d->unconv + int64_t(j.k) * d->nb : nullptr;
+    const int nr = lazy ? j.nu : d->nb;
+    ex.push_back(GemmEX{Zk, vrow(d, d->V, j, 0), d->X + j.xoff, nr, j.npw, j.m, d->nb, j.npw, j.npw, rows});
+    ex.push_back(GemmEX{Zk, vrow(d, d->HV, j, 0), d->HX + j.xoff, nr, j.npw, j.m, d->nb, j.npw, j.npw, rows});
+    if (lazy) {
+      d->lastact[j.k].assign(d->h_unconv + int64_t(j.k) * d->nb, d->h_unconv + int64_t(j.k) * d->nb + j.nu);
+      d->stale[j.k] = j.nu < d->nb;
+    } else {
+      d->stale[j.k] = 0;
+    }
   }
   zgemm_ex_batched(ex, 1.0, 0.0, s, lp);
   hipLaunchKernelGGL(k_residual, dim3(d->nb, jobs.n), dim3(256), 0, s, jobs, d->X, d->HX, d->R,
-                     d->theta, p->g.kin, d->goff, d->resn, d->tkin);
+                     d->theta, p->g.kin, d->goff, d->resn, d->tkin, lazy ? d->unconv : nullptr);
   QM_HIP(hipGetLastError());
   QM_HIP(hipEventRecord(d->ev[7], s));
   QM_HIP(hipMemcpyAsync(d->h_resn, d->resn, sizeof(double) * d->nk * d->nb, hipMemcpyDeviceToHost, s));
@@ -397,6 +421,48 @@ static DJob make_job(qm_hpsi_plan* p, DavState* d, int k) {
   j.voff = int64_t(d->mb) * (p->kinfo[k].g_off - d->g0);
   j.xoff = int64_t(d->nb) * (p->kinfo[k].g_off - d->g0);
   return j;
+}
+
+// Bring the stale rows of X and HX of the k-points ks up to date with their last
+// Rayleigh-Ritz step (whose Z, V and HV are still in place), and with resid their residuals
+// too (host copy of the norms refreshed).
+static void complete_ritz(qm_hpsi_plan* p, DavState* d, const std::vector<int>& ks, bool resid,
+                          hipStream_t s) {
+  DJobs cj{};
+  cj.nb = d->nb;
+  cj.mb = d->mb;
+  std::vector<char> mark(size_t(d->nb));
+  for (int k : ks) {
+    if (!d->stale[k]) continue;
+    std::fill(mark.begin(), mark.end(), 0);
+    for (int32_t b : d->lastact[k]) mark[size_t(b)] = 1;
+    int cnt = 0;
+    for (int b = 0; b < d->nb; ++b)
+      if (!mark[size_t(b)]) d->h_slist[int64_t(k) * d->nb + cnt++] = b;
+    DJob j = make_job(p, d, k);
+    j.m = d->m[k];
+    j.nu = cnt;
+    cj.j[cj.n++] = j;
+    d->stale[k] = 0;
+  }
+  if (cj.n == 0) return;
+  QM_HIP(hipMemcpyAsync(d->slist, d->h_slist, sizeof(int32_t) * d->nk * d->nb, hipMemcpyHostToDevice, s));
+  std::vector<GemmEX> ex;
+  for (int i = 0; i < cj.n; ++i) {
+    const DJob& j = cj.j[i];
+    double2* Zk = d->Z + int64_t(j.k) * d->mb * d->nb;
+    const int32_t* rows = d->slist + int64_t(j.k) * d->nb;
+    ex.push_back(GemmEX{Zk, vrow(d, d->V, j, 0), d->X + j.xoff, j.nu, j.npw, j.m, d->nb, j.npw, j.npw, rows});
+    ex.push_back(GemmEX{Zk, vrow(d, d->HV, j, 0), d->HX + j.xoff, j.nu, j.npw, j.m, d->nb, j.npw, j.npw, rows});
+  }
+  zgemm_ex_batched(ex, 1.0, 0.0, s, 0);
+  if (resid) {
+    hipLaunchKernelGGL(k_residual, dim3(d->nb, cj.n), dim3(256), 0, s, cj, d->X, d->HX, d->R,
+                       d->theta, p->g.kin, d->goff, d->resn, d->tkin, d->slist);
+    QM_HIP(hipGetLastError());
+    QM_HIP(hipMemcpyAsync(d->h_resn, d->resn, sizeof(double) * d->nk * d->nb, hipMemcpyDeviceToHost, s));
+  }
+  QM_HIP(hipStreamSynchronize(s));   // (h_slist is rewritten by the next call)
 }
 
 // copy X (and HX) of the job's k into basis rows [0, nb) after re-orthonormalising X by CholQR
@@ -459,7 +525,8 @@ static void write_outputs(qm_hpsi_plan* p, DavState* d, void* psi, double* eig, 
 // needed).  psi points at k0's first band, eig and resnorm at k0's first entry.
 static qm_status dav_step_range(qm_hpsi_plan* p, DavState** slot, bool own_scratch, int k0, int k1,
                                 void* psi, double* eig, double* resnorm, int nwant,
-                                const qm_dav_opts* o, int32_t* n_unconv, hipStream_t s) {
+                                const qm_dav_opts* o, int32_t* n_unconv, hipStream_t s,
+                                bool lazy = false) {
   QM_REQUIRE(nwant >= 1, QM_E_ARG, "need nbnd >= 1");
   QM_REQUIRE(!o || o->extra_bands >= 0, QM_E_ARG, "extra_bands must be >= 0");
   QM_REQUIRE(!o || o->subspace_fp32 == 0 || o->subspace_fp32 == 1, QM_E_ARG,
@@ -495,7 +562,9 @@ static qm_status dav_step_range(qm_hpsi_plan* p, DavState** slot, bool own_scrat
     d->t_hpsi = d->t_sub = d->t_eig = 0;
     d->lowp = o && o->switch_resid > 0.0 && p->prec != QM_PREC_FP64;
     d->sub32 = o && o->subspace_fp32 != 0;
+    std::fill(d->stale.begin(), d->stale.end(), 0);
   }
+  d->lazy = lazy;
   DJobs jobs{};
   jobs.nb = nb;
   jobs.mb = mb;
@@ -536,6 +605,12 @@ static qm_status dav_step_range(qm_hpsi_plan* p, DavState** slot, bool own_scrat
     const bool refresh = d->lowp && o && (maxres <= o->switch_resid || stagnant);
     if (refresh) {
       d->lowp = false;
+      {
+        std::vector<int> ks;
+        for (int kk = k0; kk < k1; ++kk)
+          if (!d->done[kk]) ks.push_back(kk);
+        complete_ritz(p, d, ks, false, s);   // the new basis is every Ritz vector
+      }
       for (int kk = k0; kk < k1; ++kk) {
         if (d->done[kk]) continue;
         DJob j = make_job(p, d, kk);
@@ -557,6 +632,17 @@ static qm_status dav_step_range(qm_hpsi_plan* p, DavState** slot, bool own_scrat
         }
       }
     } else {
+      {   // the k-points that restart from their Ritz vectors need every row of X and HX
+        std::vector<int> ks;
+        for (int kk = k0; kk < k1; ++kk) {
+          if (d->done[kk] || !d->stale[kk]) continue;
+          int nu = 0;
+          for (int n = 0; n < nb; ++n)
+            if (!(d->h_resn[int64_t(kk) * nb + n] <= tol)) ++nu;
+          if (d->m[kk] + nu > mb) ks.push_back(kk);
+        }
+        complete_ritz(p, d, ks, false, s);
+      }
       std::vector<DJob> restart;
       for (int kk = k0; kk < k1; ++kk) {
         if (d->done[kk]) continue;
@@ -590,10 +676,23 @@ static qm_status dav_step_range(qm_hpsi_plan* p, DavState** slot, bool own_scrat
         }
         if (!orthonormalise(p, d, jobs, s)) throw Error(QM_E_NOT_SPD, "correction block lost rank");
         timed_apply(p, d, sl, d->V, d->HV, s, d->lowp);
-        rayleigh_ritz(p, d, jobs, s);
+        const bool lazy_now = d->lazy && subspace_lp(d) == 0;
+        rayleigh_ritz(p, d, jobs, s, lazy_now);
         for (int i = 0; i < jobs.n; ++i) {
           d->m[jobs.j[i].k] = jobs.j[i].m;
           d->it[jobs.j[i].k] += 1;
+        }
+        if (lazy_now) {   // before a k-point is declared converged, every band is checked
+          std::vector<int> ks;
+          for (int i = 0; i < jobs.n; ++i) {
+            const int kk = jobs.j[i].k;
+            if (!d->stale[kk]) continue;
+            bool open = false;
+            for (int n = 0; n < nwant; ++n)
+              if (!(d->h_resn[int64_t(kk) * nb + n] <= tol)) open = true;
+            if (!open) ks.push_back(kk);
+          }
+          complete_ritz(p, d, ks, true, s);
         }
       }
     }
@@ -761,7 +860,7 @@ static SolveResult solve_range(qm_hpsi_plan* p, DavState** slot, bool own_scratc
   const int max_iter = o.max_iter > 0 ? o.max_iter : 200;
   auto step = [&]() {
     try {
-      r.st = dav_step_range(p, slot, own_scratch, k0, k1, psi, eig, resnorm, nb, &o, &r.nun, s);
+      r.st = dav_step_range(p, slot, own_scratch, k0, k1, psi, eig, resnorm, nb, &o, &r.nun, s, true);
     } catch (const Error& e) {
       r.err = e.what();
       r.st = e.code;
@@ -775,6 +874,22 @@ static SolveResult solve_range(qm_hpsi_plan* p, DavState** slot, bool own_scratc
   step();
   o.restart = 0;
   for (int iter = 0; r.st == QM_OK && r.nun > 0 && iter < max_iter; ++iter) step();
+  // stopped at max_iter: the returned vectors and norms are completed for every band
+  DavState* d = *slot;
+  if (r.st == QM_OK && d && d->ready) {
+    try {
+      std::vector<int> ks;
+      for (int kk = k0; kk < k1; ++kk)
+        if (d->stale[kk]) ks.push_back(kk);
+      if (!ks.empty()) {
+        complete_ritz(p, d, ks, true, s);
+        write_outputs(p, d, psi, eig, resnorm, s);
+      }
+    } catch (const Error& e) {
+      r.err = e.what();
+      r.st = e.code;
+    }
+  }
   return r;
 }
 

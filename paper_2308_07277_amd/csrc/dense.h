@@ -91,7 +91,7 @@ __global__ void k_chol_inv_cols(DJobs jobs, const double2* Gm, const double2* Ld
                                 const int32_t* info);
 __global__ void k_residual(DJobs jobs, const double2* X, const double2* HX, double2* Rr,
                            const double* theta, const double* kin_all, const int64_t* goff,
-                           double* resn, double* tkin);
+                           double* resn, double* tkin, const int32_t* list);
 __global__ void k_start_block(DJobs jobs, double2* V, int first);
 __global__ void k_cgs_overlap(DJobs jobs, const double2* Cw, double* ovl);
 __global__ void k_teter(DJobs jobs, const double2* Rr, double2* V, const int32_t* unconv,

@@ -1509,7 +1509,8 @@ __global__ void __launch_bounds__(256) k_start_block(DJobs jobs, double2* __rest
 }
 
 // ---------------------------------------------------------------- residuals
-// One workgroup per (job, band): r = HX - theta X into R, ||r||, <x|T|x>/<x|x>.
+// One workgroup per (job, band): r = HX - theta X into R, ||r||, <x|T|x>/<x|x>.  With a
+// list, workgroup x < J.nu of a job takes band list[k][x] (the others return).
 __global__ void __launch_bounds__(256) k_residual(DJobs jobs, const double2* __restrict__ X,
                                                   const double2* __restrict__ HX,
                                                   double2* __restrict__ Rr,
@@ -1517,11 +1518,13 @@ __global__ void __launch_bounds__(256) k_residual(DJobs jobs, const double2* __r
                                                   const double* __restrict__ kin_all,
                                                   const int64_t* __restrict__ goff,
                                                   double* __restrict__ resn,
-                                                  double* __restrict__ tkin) {
+                                                  double* __restrict__ tkin,
+                                                  const int32_t* __restrict__ list) {
   __shared__ double red[16];
   const DJob& J = jobs.j[blockIdx.y];
-  const int nb = jobs.nb, n = blockIdx.x;
-  if (n >= nb) return;
+  const int nb = jobs.nb;
+  if (list ? int(blockIdx.x) >= J.nu : int(blockIdx.x) >= nb) return;
+  const int n = list ? list[int64_t(J.k) * nb + blockIdx.x] : int(blockIdx.x);
   const double th = theta[int64_t(J.k) * jobs.mb + n];
   const int64_t off = J.xoff + int64_t(n) * J.npw;
   const double* kin = kin_all + goff[J.k];

@@ -65,6 +65,7 @@ struct EXDev {
   const void* W; const void* A; void* Y;
   int32_t M, N, K, tm, tn, blk0;
   int64_t ldw, lda, ldy;
+  const int32_t* rows;    // nullptr, or the W column / Y row of each product row
 };
 
 constexpr int MAXP = 24; // problems per launch (descriptors travel as kernel arguments)
@@ -263,7 +264,8 @@ __device__ __forceinline__ void store_ex_tile(const EXDev& P, int m0, int n0, in
         for (int r = 0; r < 4; ++r) {
           const int m = min(m0 + wi + ti * 16 + acc_row<T>(lane, r), P.M - 1);
           const int n = min(n0 + wj + tj * 16 + (lane & 15), P.N - 1);
-          const double2 o = Y[int64_t(m) * P.ldy + n];
+          const int mr = P.rows ? P.rows[m] : m;
+          const double2 o = Y[int64_t(mr) * P.ldy + n];
           ore[tj * 4 + r] = o.x;
           oim[tj * 4 + r] = o.y;
         }
@@ -283,7 +285,7 @@ __device__ __forceinline__ void store_ex_tile(const EXDev& P, int m0, int n0, in
         const int m = m0 + wi + ti * 16 + acc_row<T>(lane, r);
         const int n = n0 + wj + tj * 16 + (lane & 15);
         if (m < P.M && n < P.N)
-          Y[int64_t(m) * P.ldy + n] =
+          Y[int64_t(P.rows ? P.rows[m] : m) * P.ldy + n] =
               make_double2(alpha * double(cr[ti][tj][r]) + beta * ore[tj * 4 + r],
                            alpha * double(ci[ti][tj][r]) + beta * oim[tj * 4 + r]);
       }
@@ -323,9 +325,21 @@ __global__ void __launch_bounds__(256, 2) k_cgemm_ex(const EXBatch batch, double
   const int nch = (P.K + KC - 1) / KC;
   // the next chunk's operands are loaded into registers while this chunk's MFMAs run
   cplx<T> pw[NWE], pa[NAE];
+  // with a row list, this thread's W columns (-1 past M), fixed for the whole K loop
+  int wcol[NWE];
+#pragma unroll
+  for (int q = 0; q < NWE; ++q) {
+    const int m = m0 + lcw + q;
+    wcol[q] = m < P.M ? (P.rows ? P.rows[m] : m) : -1;
+  }
   auto fetch = [&](int c) {
     const int iw = c * KC + lrw, ia = c * KC + lra;
-    if (iw < P.K && m0 + lcw + NWE <= P.M) {   // interior: no element tests
+    if (P.rows) {
+#pragma unroll
+      for (int q = 0; q < NWE; ++q)
+        pw[q] = (iw < P.K && wcol[q] >= 0) ? ld<T>(Wp + int64_t(iw) * P.ldw + wcol[q])
+                                           : cplx<T>{T(0), T(0)};
+    } else if (iw < P.K && m0 + lcw + NWE <= P.M) {   // interior: no element tests
 #pragma unroll
       for (int q = 0; q < NWE; ++q) pw[q] = ld<T>(Wp + int64_t(iw) * P.ldw + m0 + lcw + q);
     } else {
@@ -789,6 +803,8 @@ void zgemm_ex_batched(const std::vector<GemmEX>& probs, double alpha, double bet
       const GemmEX& g = probs[base + i];
       EXDev& x = d.p[i];
       x.W = g.W; x.A = g.A; x.Y = g.Y;
+      x.rows = g.rows;
+      QM_REQUIRE(!g.rows || lp != 2, QM_E_STATE, "row lists need the float64 or float32 kernels");
       x.M = g.M; x.N = g.N; x.K = g.K;
       x.tm = (g.M + tm_ - 1) / tm_; x.tn = (g.N + tn_ - 1) / tn_;
       x.blk0 = int32_t(blk);

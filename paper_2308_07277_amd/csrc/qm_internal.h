@@ -244,6 +244,9 @@ struct GemmEX {
   const void* W; const void* A; void* Y;
   int32_t M, N, K;        // M = rows of Y (j), N = cols of Y (g), K = i
   int64_t ldw, lda, ldy;
+  // optional [M] device list: row j of the product is W's column rows[j] and goes to Y's row
+  // rows[j] (float64 and float32 kernels only)
+  const int32_t* rows = nullptr;
 };
 void zgemm_cn_batched(const std::vector<GemmCN>& probs, double alpha, double beta_c,
                       void* work, int64_t work_bytes, hipStream_t s, StageEvents* ev = nullptr,
