@@ -389,6 +389,24 @@ def test_error_paths_forced_from_the_host():
     xs = x.reshape(w.nbnd, -1)
     r = np.linalg.norm(h(xs) - eig[0][:, None] * xs, axis=1)
     np.testing.assert_allclose(r, res[0], rtol=1e-6, atol=1e-12)
+    # a limit reached with some bands converged (their rows were last formed in earlier
+    # iterations): the returned vectors and norms are still those of the final Ritz pairs
+    w2 = workload.make_workload("c2", nk_limit=1)
+    plan2, a2 = make_plan(w2, w2.nbnd)
+    _, _, full, st, _ = _solve(plan2, w2, w2.nbnd, _start(w2, w2.nbnd), tol=1e-6)
+    assert st == 0
+    lim = full["iterations"] - 2      # stop two iterations short of convergence
+    eig, res, stats, st, x = _solve(plan2, w2, w2.nbnd, _start(w2, w2.nbnd), tol=1e-6, max_iter=lim)
+    nconv = int((res <= 1e-6).sum())
+    print(f"8-atom cell, max_iter {lim}:", st, stats, "converged bands", nconv)
+    assert st == qm.QM_E_NOT_CONVERGED
+    assert stats["n_hpsi_bands"] < w2.nbnd * (stats["iterations"] + 1)   # some rows went stale
+    h2, _ = _oracle_h(w2, a2, 0)
+    xs = x.reshape(w2.nbnd, -1)
+    r = np.linalg.norm(h2(xs) - eig[0][:, None] * xs, axis=1)
+    np.testing.assert_allclose(r, res[0], rtol=1e-6, atol=1e-12)
+    np.testing.assert_allclose(xs.conj() @ xs.T, np.eye(w2.nbnd), atol=1e-10)
+    plan2.close()
     _hpsi_ok(plan, w, a)
     eig, res, stats, st, _ = _solve(plan, w, w.nbnd, [start], tol=1e-9)
     assert st == 0 and res.max() <= 1e-9
