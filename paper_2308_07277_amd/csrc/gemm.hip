@@ -249,7 +249,7 @@ __device__ __forceinline__ void hold(double x) { asm volatile("" ::"v"(x)); }
 // loaded together, from addresses clamped into the matrix, and held in registers before
 // the guarded stores: a load under each element's guard had compiled to one memory round
 // trip per element.
-template <typename T, typename AV>
+template <typename T, typename AV, bool ROWS = false>
 __device__ __forceinline__ void store_ex_tile(const EXDev& P, int m0, int n0, int wi, int wj, int lane,
                                               const AV (&cr)[2][2], const AV (&ci)[2][2], double alpha,
                                               double beta) {
@@ -264,7 +264,7 @@ __device__ __forceinline__ void store_ex_tile(const EXDev& P, int m0, int n0, in
         for (int r = 0; r < 4; ++r) {
           const int m = min(m0 + wi + ti * 16 + acc_row<T>(lane, r), P.M - 1);
           const int n = min(n0 + wj + tj * 16 + (lane & 15), P.N - 1);
-          const int mr = P.rows ? P.rows[m] : m;
+          const int mr = (ROWS && P.rows) ? P.rows[m] : m;
           const double2 o = Y[int64_t(mr) * P.ldy + n];
           ore[tj * 4 + r] = o.x;
           oim[tj * 4 + r] = o.y;
@@ -285,7 +285,7 @@ __device__ __forceinline__ void store_ex_tile(const EXDev& P, int m0, int n0, in
         const int m = m0 + wi + ti * 16 + acc_row<T>(lane, r);
         const int n = n0 + wj + tj * 16 + (lane & 15);
         if (m < P.M && n < P.N)
-          Y[int64_t(P.rows ? P.rows[m] : m) * P.ldy + n] =
+          Y[int64_t((ROWS && P.rows) ? P.rows[m] : m) * P.ldy + n] =
               make_double2(alpha * double(cr[ti][tj][r]) + beta * ore[tj * 4 + r],
                            alpha * double(ci[ti][tj][r]) + beta * oim[tj * 4 + r]);
       }
@@ -294,7 +294,8 @@ __device__ __forceinline__ void store_ex_tile(const EXDev& P, int m0, int n0, in
 
 // Output tile TM x TN (64 x 64, or 32 x 128 when the row count is a multiple of 32 but not
 // of 64, e.g. 160 bands: no padded rows); four waves of 32 x 32 each.
-template <typename T, typename SW, typename SA, int TM, int TN>
+// ROWS: the problems may carry row lists (EXDev::rows); the other instantiations ignore them
+template <typename T, typename SW, typename SA, int TM, int TN, bool ROWS = false>
 __global__ void __launch_bounds__(256, 2) k_cgemm_ex(const EXBatch batch, double alpha, double beta) {
   typedef typename Acc<T>::type AV;
   constexpr int NWE = KC * TM / 256, NAE = KC * TN / 256;   // elements per thread and chunk
@@ -326,19 +327,21 @@ __global__ void __launch_bounds__(256, 2) k_cgemm_ex(const EXBatch batch, double
   // the next chunk's operands are loaded into registers while this chunk's MFMAs run
   cplx<T> pw[NWE], pa[NAE];
   // with a row list, this thread's W columns (-1 past M), fixed for the whole K loop
-  int wcol[NWE];
+  int wcol[ROWS ? NWE : 1];
+  if constexpr (ROWS) {
 #pragma unroll
-  for (int q = 0; q < NWE; ++q) {
-    const int m = m0 + lcw + q;
-    wcol[q] = m < P.M ? (P.rows ? P.rows[m] : m) : -1;
+    for (int q = 0; q < NWE; ++q) {
+      const int m = m0 + lcw + q;
+      wcol[q] = m < P.M ? (P.rows ? P.rows[m] : m) : -1;
+    }
   }
   auto fetch = [&](int c) {
     const int iw = c * KC + lrw, ia = c * KC + lra;
-    if (P.rows) {
+    if (ROWS && P.rows) {
 #pragma unroll
       for (int q = 0; q < NWE; ++q)
-        pw[q] = (iw < P.K && wcol[q] >= 0) ? ld<T>(Wp + int64_t(iw) * P.ldw + wcol[q])
-                                           : cplx<T>{T(0), T(0)};
+        pw[q] = (iw < P.K && wcol[ROWS ? q : 0] >= 0) ? ld<T>(Wp + int64_t(iw) * P.ldw + wcol[ROWS ? q : 0])
+                                                      : cplx<T>{T(0), T(0)};
     } else if (iw < P.K && m0 + lcw + NWE <= P.M) {   // interior: no element tests
 #pragma unroll
       for (int q = 0; q < NWE; ++q) pw[q] = ld<T>(Wp + int64_t(iw) * P.ldw + m0 + lcw + q);
@@ -403,7 +406,7 @@ __global__ void __launch_bounds__(256, 2) k_cgemm_ex(const EXBatch batch, double
       cr[ti][tj] = t1[ti][tj] - t2[ti][tj];
       ci[ti][tj] = t3[ti][tj] - t1[ti][tj] - t2[ti][tj];
     }
-  store_ex_tile<T>(P, m0, n0, wi, wj, lane, cr, ci, alpha, beta);
+  store_ex_tile<T, AV, ROWS>(P, m0, n0, wi, wj, lane, cr, ci, alpha, beta);
 }
 
 
@@ -804,7 +807,7 @@ void zgemm_ex_batched(const std::vector<GemmEX>& probs, double alpha, double bet
       EXDev& x = d.p[i];
       x.W = g.W; x.A = g.A; x.Y = g.Y;
       x.rows = g.rows;
-      QM_REQUIRE(!g.rows || lp != 2, QM_E_STATE, "row lists need the float64 or float32 kernels");
+
       x.M = g.M; x.N = g.N; x.K = g.K;
       x.tm = (g.M + tm_ - 1) / tm_; x.tn = (g.N + tn_ - 1) / tn_;
       x.blk0 = int32_t(blk);
@@ -812,7 +815,16 @@ void zgemm_ex_batched(const std::vector<GemmEX>& probs, double alpha, double bet
       blk += int64_t(x.tm) * x.tn;
     }
     if (blk == 0) continue;
-    if (lp == 0 && narrow)
+    bool rows = false;
+    for (size_t i = 0; i < n; ++i) rows = rows || probs[base + i].rows;
+    QM_REQUIRE(!rows || lp == 0, QM_E_STATE, "row lists need the float64 expansion kernels");
+    if (rows && narrow)
+      hipLaunchKernelGGL((k_cgemm_ex<double, double2, double2, 32, 128, true>), dim3(unsigned(blk)), dim3(256),
+                         0, s, d, alpha, beta_y);
+    else if (rows)
+      hipLaunchKernelGGL((k_cgemm_ex<double, double2, double2, 64, 64, true>), dim3(unsigned(blk)), dim3(256),
+                         0, s, d, alpha, beta_y);
+    else if (lp == 0 && narrow)
       hipLaunchKernelGGL((k_cgemm_ex<double, double2, double2, 32, 128>), dim3(unsigned(blk)), dim3(256), 0,
                          s, d, alpha, beta_y);
     else if (lp == 0)

@@ -245,7 +245,7 @@ struct GemmEX {
   int32_t M, N, K;        // M = rows of Y (j), N = cols of Y (g), K = i
   int64_t ldw, lda, ldy;
   // optional [M] device list: row j of the product is W's column rows[j] and goes to Y's row
-  // rows[j] (float64 and float32 kernels only)
+  // rows[j] (float64 operands only, lp = 0)
   const int32_t* rows = nullptr;
 };
 void zgemm_cn_batched(const std::vector<GemmCN>& probs, double alpha, double beta_c,
