@@ -251,7 +251,11 @@ qm_status qm_davidson_step(qm_hpsi_plan *plan, int32_t k, void *psi, double *eig
 
 /* Iterate qm_davidson_step (same passage) from the start block psi until every
  * residual norm is <= opts->tol or max_iter is reached (then QM_E_NOT_CONVERGED with
- * all outputs filled).  psi receives the Ritz vectors; stats may be NULL.
+ * all outputs filled).  psi receives the Ritz vectors; stats may be NULL.  Unlike a
+ * sequence of qm_davidson_step calls, the iterations in between form Ritz vectors and
+ * residuals only for the bands being corrected (as the Quantum ESPRESSO Davidson forms
+ * residuals only for its unconverged bands); every band's vector and residual is formed
+ * from the final Ritz pairs before a convergence verdict and before the return.
  * Errors: QM_E_NOT_SPD when a block to be orthonormalised is linearly dependent (for
  * example two equal start vectors), QM_E_NAN when a residual norm is not finite; in both
  * cases the Davidson state is dropped and the plan stays usable for qm_apply_h. */
