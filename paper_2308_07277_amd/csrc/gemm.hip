@@ -46,14 +46,12 @@ template <> __device__ __forceinline__ int acc_row<double>(int lane, int r) { re
 template <> __device__ __forceinline__ int acc_row<float>(int lane, int r) { return 4 * (lane >> 4) + r; }
 
 // storage -> compute conversion of one complex element
-template <typename T> __device__ __forceinline__ cplx<T> ld(const double2* p) {
-  double2 v = *p;
-  return {T(v.x), T(v.y)};
-}
-template <typename T> __device__ __forceinline__ cplx<T> ld(const float2* p) {
-  float2 v = *p;
-  return {T(v.x), T(v.y)};
-}
+template <typename T> __device__ __forceinline__ cplx<T> cv(double2 v) { return {T(v.x), T(v.y)}; }
+template <typename T> __device__ __forceinline__ cplx<T> cv(float2 v) { return {T(v.x), T(v.y)}; }
+// Ties a prefetched register value to this point of the program: the conversion and
+// masking that follow are not moved up to the load, where the wave would wait for it.
+__device__ __forceinline__ void pin(double2& v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
+__device__ __forceinline__ void pin(float2& v) { asm volatile("" : "+v"(v.x), "+v"(v.y)); }
 
 struct CNDev {
   const void* A; const void* B;
@@ -133,43 +131,40 @@ __global__ void __launch_bounds__(256, 2) k_cgemm_cn(const CNBatch batch, int ns
   // rows past the matrix read row i0 / j0 (which exists) and are zeroed after the load
   const SA* Ar = A + int64_t(arow ? i0 + larow : i0) * P.lda;
   const SB* Br = B + int64_t(brow ? j0 + lbrow : j0) * P.ldb;
-  // the next chunk's operands are loaded into registers while this chunk's MFMAs run
-  cplx<T> pa[NAE], pb[NBE];
+  // the next chunk's operands are loaded into registers, in their storage type, while this
+  // chunk's MFMAs run; they are converted, and the rows past the matrix zeroed, when they are
+  // stored to LDS (work on them right after the load would wait for it there)
+  SA pa[NAE];
+  SB pb[NBE];
   auto fetch = [&](int c) {
     const int ka = c * KC + laseg, kb = c * KC + lbseg;
-    if (ka + NAE <= P.K) {   // whole run inside K: one bounds test per row
+    // the test is the same for the whole workgroup, so the interior loads are not followed
+    // by lane-masked writes of the same registers (which would wait for them)
+    const bool inner = (c + 1) * KC <= P.K;
+    if (inner) {   // the whole chunk inside K: no element tests
 #pragma unroll
-      for (int q = 0; q < NAE; ++q) {
-        const cplx<T> av = ld<T>(Ar + ka + q);
-        pa[q] = arow ? av : cplx<T>{T(0), T(0)};
-      }
+      for (int q = 0; q < NAE; ++q) pa[q] = Ar[ka + q];
+#pragma unroll
+      for (int q = 0; q < NBE; ++q) pb[q] = Br[kb + q];
     } else {
 #pragma unroll
-      for (int q = 0; q < NAE; ++q) {
-        const int g = ka + q;
-        pa[q] = (arow && g < P.K) ? ld<T>(Ar + g) : cplx<T>{T(0), T(0)};
-      }
-    }
-    if (kb + NBE <= P.K) {
+      for (int q = 0; q < NAE; ++q) pa[q] = ka + q < P.K ? Ar[ka + q] : SA{0, 0};
 #pragma unroll
-      for (int q = 0; q < NBE; ++q) {
-        const cplx<T> bv = ld<T>(Br + kb + q);
-        pb[q] = brow ? bv : cplx<T>{T(0), T(0)};
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < NBE; ++q) {
-        const int g = kb + q;
-        pb[q] = (brow && g < P.K) ? ld<T>(Br + g) : cplx<T>{T(0), T(0)};
-      }
+      for (int q = 0; q < NBE; ++q) pb[q] = kb + q < P.K ? Br[kb + q] : SB{0, 0};
     }
   };
   if (c0 < c1) fetch(c0);
   for (int c = c0; c < c1; ++c) {
 #pragma unroll
-    for (int q = 0; q < NAE; ++q) As[larow][laseg + q] = pa[q];
+    for (int q = 0; q < NAE; ++q) {
+      pin(pa[q]);
+      As[larow][laseg + q] = arow ? cv<T>(pa[q]) : cplx<T>{T(0), T(0)};
+    }
 #pragma unroll
-    for (int q = 0; q < NBE; ++q) Bs[lbrow][lbseg + q] = pb[q];
+    for (int q = 0; q < NBE; ++q) {
+      pin(pb[q]);
+      Bs[lbrow][lbseg + q] = brow ? cv<T>(pb[q]) : cplx<T>{T(0), T(0)};
+    }
     __syncthreads();
     if (c + 1 < c1) fetch(c + 1);
 #pragma unroll
@@ -324,8 +319,10 @@ __global__ void __launch_bounds__(256, 2) k_cgemm_ex(const EXBatch batch, double
       t3[a][b] = AV{0, 0, 0, 0};
     }
   const int nch = (P.K + KC - 1) / KC;
-  // the next chunk's operands are loaded into registers while this chunk's MFMAs run
-  cplx<T> pw[NWE], pa[NAE];
+  // the next chunk's operands are loaded into registers, in their storage type, while this
+  // chunk's MFMAs run, and converted when they are stored to LDS
+  SW pw[NWE];
+  SA pa[NAE];
   // with a row list, this thread's W columns (-1 past M), fixed for the whole K loop
   int wcol[ROWS ? NWE : 1];
   if constexpr (ROWS) {
@@ -337,38 +334,47 @@ __global__ void __launch_bounds__(256, 2) k_cgemm_ex(const EXBatch batch, double
   }
   auto fetch = [&](int c) {
     const int iw = c * KC + lrw, ia = c * KC + lra;
-    if (ROWS && P.rows) {
+    // the interior tests are the same for the whole workgroup, so the interior loads are not
+    // followed by lane-masked writes of the same registers (which would wait for them)
+    const bool inner_k = (c + 1) * KC <= P.K;
+    if (ROWS && P.rows) {   // clamped loads; columns past M and rows past K zeroed in the store
 #pragma unroll
       for (int q = 0; q < NWE; ++q)
-        pw[q] = (iw < P.K && wcol[ROWS ? q : 0] >= 0) ? ld<T>(Wp + int64_t(iw) * P.ldw + wcol[ROWS ? q : 0])
-                                                      : cplx<T>{T(0), T(0)};
-    } else if (iw < P.K && m0 + lcw + NWE <= P.M) {   // interior: no element tests
+        pw[q] = Wp[int64_t(min(iw, P.K - 1)) * P.ldw + max(wcol[ROWS ? q : 0], 0)];
+    } else if (inner_k && m0 + TM <= P.M) {   // interior: no element tests
 #pragma unroll
-      for (int q = 0; q < NWE; ++q) pw[q] = ld<T>(Wp + int64_t(iw) * P.ldw + m0 + lcw + q);
+      for (int q = 0; q < NWE; ++q) pw[q] = Wp[int64_t(iw) * P.ldw + m0 + lcw + q];
     } else {
 #pragma unroll
       for (int q = 0; q < NWE; ++q) {
         const int m = m0 + lcw + q;
-        pw[q] = (iw < P.K && m < P.M) ? ld<T>(Wp + int64_t(iw) * P.ldw + m) : cplx<T>{T(0), T(0)};
+        pw[q] = (iw < P.K && m < P.M) ? Wp[int64_t(iw) * P.ldw + m] : SW{0, 0};
       }
     }
-    if (ia < P.K && n0 + lca + NAE <= P.N) {
+    if (inner_k && n0 + TN <= P.N) {
 #pragma unroll
-      for (int q = 0; q < NAE; ++q) pa[q] = ld<T>(Ap + int64_t(ia) * P.lda + n0 + lca + q);
+      for (int q = 0; q < NAE; ++q) pa[q] = Ap[int64_t(ia) * P.lda + n0 + lca + q];
     } else {
 #pragma unroll
       for (int q = 0; q < NAE; ++q) {
         const int n = n0 + lca + q;
-        pa[q] = (ia < P.K && n < P.N) ? ld<T>(Ap + int64_t(ia) * P.lda + n) : cplx<T>{T(0), T(0)};
+        pa[q] = (ia < P.K && n < P.N) ? Ap[int64_t(ia) * P.lda + n] : SA{0, 0};
       }
     }
   };
   if (nch > 0) fetch(0);
   for (int c = 0; c < nch; ++c) {
 #pragma unroll
-    for (int q = 0; q < NWE; ++q) Ws[lrw][lcw + q] = pw[q];
+    for (int q = 0; q < NWE; ++q) {
+      if constexpr (ROWS) {
+        const bool ok = !P.rows || (c * KC + lrw < P.K && wcol[q] >= 0);
+        Ws[lrw][lcw + q] = ok ? cv<T>(pw[q]) : cplx<T>{T(0), T(0)};
+      } else {
+        Ws[lrw][lcw + q] = cv<T>(pw[q]);
+      }
+    }
 #pragma unroll
-    for (int q = 0; q < NAE; ++q) As[lra][lca + q] = pa[q];
+    for (int q = 0; q < NAE; ++q) As[lra][lca + q] = cv<T>(pa[q]);
     __syncthreads();
     if (c + 1 < nch) fetch(c + 1);
 #pragma unroll
@@ -610,13 +616,11 @@ __global__ void __launch_bounds__(256) k_cgemm_ex_bf16(const EXBatch batch, doub
   uint32_t pa[8];
   auto fetch = [&](int c) {
     const int i0 = c * KB + kg;
-    if (i0 + 8 <= P.K) {   // all eight K rows exist: one bounds test per column
+    if ((c + 1) * KB <= P.K) {   // the whole chunk inside K (a workgroup-uniform test)
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const double2 wv = Wp[int64_t(i0 + q) * P.ldw + wc];
-        const uint32_t av = *reinterpret_cast<const uint32_t*>(Ap + int64_t(i0 + q) * P.lda + ac);
-        pw[q] = wcol ? wv : make_double2(0.0, 0.0);
-        pa[q] = acol ? av : 0u;
+      for (int q = 0; q < 8; ++q) {   // columns past the matrix are zeroed when staged
+        pw[q] = Wp[int64_t(i0 + q) * P.ldw + wc];
+        pa[q] = *reinterpret_cast<const uint32_t*>(Ap + int64_t(i0 + q) * P.lda + ac);
       }
     } else {
 #pragma unroll
@@ -631,11 +635,18 @@ __global__ void __launch_bounds__(256) k_cgemm_ex_bf16(const EXBatch batch, doub
   if (nch > 0) fetch(0);
   for (int c = 0; c < nch; ++c) {
     {
+      double2 w8[8];
+      uint32_t a8[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        w8[q] = wcol ? pw[q] : make_double2(0.0, 0.0);
+        a8[q] = acol ? pa[q] : 0u;
+      }
       uint4 re, im;
-      pack_c128(pw, re, im);
+      pack_c128(w8, re, im);
       *reinterpret_cast<uint4*>(&Wr[col][kg]) = re;
       *reinterpret_cast<uint4*>(&Wi[col][kg]) = im;
-      split_bf2(pa, re, im);
+      split_bf2(a8, re, im);
       *reinterpret_cast<uint4*>(&Ar[col][kg]) = re;
       *reinterpret_cast<uint4*>(&Ai[col][kg]) = im;
     }
