@@ -74,3 +74,20 @@ def test_struct_sizes_match_header(tmp_path):
         assert ctypes.sizeof(cls) == int(got[name]), name
         for fname, _ in cls._fields_:
             assert getattr(cls, fname).offset == int(got[f"{name}.{fname}"]), (name, fname)
+
+
+def test_entry_points_fail_loudly_without_the_library(monkeypatch, tmp_path):
+    """With no built library every entry point raises before touching its arguments: there is
+    no CPU fallback behind the binding."""
+    monkeypatch.setattr(qm, "_LIB", None)
+    monkeypatch.setattr(qm, "LIB_PATH", str(tmp_path / "libqm_hpsi.so"))
+    calls = [
+        lambda: qm.lib_loaded_path(),
+        lambda: qm.qm_hpsi_plan_create(None, None, None, None, None, 0, 0, None, None, None),
+        lambda: qm.qm_mlp_forward(None, None, None, 0),
+        lambda: qm.qm_mlp_loss_grad(None, None, None, None, None, 0, None),
+        lambda: qm.qm_mlp_adam(None, None, None, None, 1),
+    ]
+    for call in calls:
+        with pytest.raises(RuntimeError, match="is not built"):
+            call()
